@@ -1,0 +1,12 @@
+"""Plain FP64 CPU oracle for the TT hot path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` are the only callers.  It shares no code
+with the HIP library and never imports it.
+
+Parity pins: every function here is checked by ``tests/test_oracle_*.py``
+against dense brute force, closed forms and invariants.
+"""
+from .tt import *          # noqa: F401,F403
+from .schemes import *     # noqa: F401,F403
+from . import dense        # noqa: F401

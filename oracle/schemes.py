@@ -1,0 +1,184 @@
+"""FP64 CPU oracle for the TT orthogonalization schemes (TEST INFRASTRUCTURE ONLY).
+
+Literal transcriptions, in the paper's order and notation, of Section 3
+"Orthogonalization schemes": TT-CGS (Algorithm 1), TT-MGS (Algorithm 2),
+TT-CGS2 (Algorithm 3), TT-MGS2 (Algorithm 4) and TT-Gram (Algorithm 5), plus
+the loss of orthogonality of Section 3.4, equation (LOO).
+
+Inputs are lists of lazy sums ``[(coef, cores), ...]`` (a plain TT-vector is a
+one-term sum).  Sums are materialised before every dot product and rounding,
+so the running vector ``p`` is exactly the unrounded TT sum of the algorithms.
+
+Readings taken where the paper is loose:
+  * column i of R holds the projections of a_i (the text of Section 3.1.1),
+    so R is upper triangular with R[j, i], j <= i (Algorithm 1 prints R(i,j));
+  * in CGS2/MGS2 R_1 has a zero diagonal and R[i, i] = R_2[i, i] = ||p_2||;
+  * Gram forms q_i from column i of R^{-1}: q_i = sum_{k<=i} R^{-1}[k, i] a_k
+    (the equation of Section 3.2; the algorithm's R^{-1}(i, j) would read the
+    zero lower triangle) and q_i is not renormalised after rounding.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from .tt import tt_sum, tt_dot, tt_norm, tt_round, tt_scale, tt_ranks, RoundLog
+
+__all__ = ["OrthoResult", "cgs", "mgs", "cgs2", "mgs2", "gram", "orthogonalize",
+           "loo_curve", "gram_of", "SCHEMES", "GramBreakdown"]
+
+SCHEMES = ("cgs", "mgs", "cgs2", "mgs2", "gram")
+
+
+class GramBreakdown(RuntimeError):
+    """The Gram matrix is numerically not positive definite (Section 3.2 remark)."""
+
+
+@dataclass
+class OrthoResult:
+    Q: list
+    R: np.ndarray
+    rounds: int = 0
+    pre_ranks: list = field(default_factory=list)    # ranks of each rounded vector before rounding
+    post_ranks: list = field(default_factory=list)   # ranks after rounding
+    logs: list = field(default_factory=list)
+
+
+def _as_sum(a):
+    """Accept either a lazy sum [(coef, cores)] or a plain TT (list of arrays)."""
+    if isinstance(a, list) and a and isinstance(a[0], tuple):
+        return a
+    return [(1.0, a)]
+
+
+def _round(res, terms, delta):
+    p = tt_sum(terms)
+    res.pre_ranks.append(tt_ranks(p))
+    lg = RoundLog()
+    pr = tt_round(p, delta, log=lg)
+    res.rounds += 1
+    res.post_ranks.append(tt_ranks(pr))
+    res.logs.append(lg)
+    return pr
+
+
+def cgs(A, delta):
+    """TT-CGS (Algorithm 1): project a_i on every q_j, subtract, round, normalise."""
+    A = [_as_sum(a) for a in A]
+    m = len(A)
+    R = np.zeros((m, m))
+    res = OrthoResult(Q=[], R=R)
+    for i in range(m):
+        a_i = tt_sum(A[i])
+        terms = list(A[i])
+        for j in range(i):
+            R[j, i] = tt_dot(a_i, res.Q[j])
+            terms.append((-R[j, i], res.Q[j]))
+        p = _round(res, terms, delta)
+        R[i, i] = tt_norm(p)
+        res.Q.append(tt_scale(1.0 / R[i, i], p))
+    return res
+
+
+def mgs(A, delta):
+    """TT-MGS (Algorithm 2): as CGS but each projection uses the running p."""
+    A = [_as_sum(a) for a in A]
+    m = len(A)
+    R = np.zeros((m, m))
+    res = OrthoResult(Q=[], R=R)
+    for i in range(m):
+        terms = list(A[i])
+        for j in range(i):
+            p = tt_sum(terms)
+            R[j, i] = tt_dot(p, res.Q[j])
+            terms.append((-R[j, i], res.Q[j]))
+        p = _round(res, terms, delta)
+        R[i, i] = tt_norm(p)
+        res.Q.append(tt_scale(1.0 / R[i, i], p))
+    return res
+
+
+def _two_pass(A, delta, modified):
+    A = [_as_sum(a) for a in A]
+    m = len(A)
+    R1 = np.zeros((m, m))
+    R2 = np.zeros((m, m))
+    res = OrthoResult(Q=[], R=None)
+    for i in range(m):
+        prev_terms = list(A[i])               # p_0 = a_i
+        for Rk in (R1, R2):                   # k = 1, 2
+            prev = tt_sum(prev_terms)
+            terms = list(prev_terms)          # p_k = p_{k-1}
+            for j in range(i):
+                src = tt_sum(terms) if modified else prev
+                Rk[j, i] = tt_dot(src, res.Q[j])
+                terms.append((-Rk[j, i], res.Q[j]))
+            p = _round(res, terms, delta)
+            prev_terms = [(1.0, p)]
+        R2[i, i] = tt_norm(p)
+        res.Q.append(tt_scale(1.0 / R2[i, i], p))
+    res.R = R1 + R2
+    return res
+
+
+def cgs2(A, delta):
+    """TT-CGS2 (Algorithm 3): two CGS passes, each rounded; R = R_1 + R_2."""
+    return _two_pass(A, delta, modified=False)
+
+
+def mgs2(A, delta):
+    """TT-MGS2 (Algorithm 4): two MGS passes, each rounded; R = R_1 + R_2."""
+    return _two_pass(A, delta, modified=True)
+
+
+def gram_of(vectors):
+    """Matrix of pairwise TT inner products <v_i, v_j>."""
+    m = len(vectors)
+    G = np.zeros((m, m))
+    for i in range(m):
+        for j in range(i + 1):
+            G[i, j] = G[j, i] = tt_dot(vectors[i], vectors[j])
+    return G
+
+
+def gram(A, delta):
+    """TT-Gram (Algorithm 5): G = [<a_i, a_j>], G = L L^T, R = L^T, q_i from R^{-1}."""
+    A = [_as_sum(a) for a in A]
+    m = len(A)
+    mats = [tt_sum(a) for a in A]
+    G = gram_of(mats)
+    try:
+        L = np.linalg.cholesky(G)
+    except np.linalg.LinAlgError as e:
+        raise GramBreakdown(str(e)) from e
+    R = L.T.copy()
+    Rinv = sla.solve_triangular(R, np.eye(m), lower=False)
+    res = OrthoResult(Q=[], R=R)
+    for i in range(m):
+        terms = []
+        for k in range(i + 1):
+            for c, x in A[k]:
+                terms.append((Rinv[k, i] * c, x))
+        res.Q.append(_round(res, terms, delta))
+    return res
+
+
+def orthogonalize(scheme, A, delta):
+    fn = {"cgs": cgs, "mgs": mgs, "cgs2": cgs2, "mgs2": mgs2, "gram": gram}[scheme]
+    return fn(A, delta)
+
+
+def loo_curve(Q):
+    """||I_k - Q_k^T Q_k||_2 for k = 1..m (Section 3.4, loss of orthogonality).
+
+    Entries of Q_k^T Q_k are TT inner products; the 2-norm of the symmetric
+    matrix I - Q_k^T Q_k is its largest absolute eigenvalue.
+    """
+    G = gram_of(Q)
+    out = []
+    for k in range(1, len(Q) + 1):
+        E = np.eye(k) - G[:k, :k]
+        out.append(float(np.max(np.abs(np.linalg.eigvalsh(E)))))
+    return np.array(out)

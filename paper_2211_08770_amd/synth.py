@@ -1,0 +1,99 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle checks.
+
+This module draws random numbers and arranges them into TT cores; it holds no
+step of the TT method itself (no rounding, inner product, QR or SVD of TT data).
+Seeds follow ``10000 * workload + item`` with NumPy's PCG64 generator.
+
+Workloads (shapes mirror the ones the paper studies: order d, mode size n,
+TT-ranks, number of vectors m, rounding accuracy delta):
+  * ``conditioned_terms``  - generating TTs t_j for the orthogonalization inputs
+    x_k = sum_{j<=k} c_kj t_j (the coefficients are fixed by the test harness,
+    which needs inner products of the t_j to prescribe the Gram spectrum);
+  * ``sum_of_graded_terms`` - a sum of 20 rank-10 TTs (d=8, n=32) whose j-th
+    term has every core scaled by 2**-j, for single-rounding measurements;
+  * ``uneven_jobs``        - independent rounding jobs with d in [4, 10],
+    n in {16, 32, 64} and one internal rank R in [8, 128];
+  * ``correlation_with_spectrum`` - a unit-diagonal SPD matrix with a
+    prescribed eigenvalue set (Davies-Higham, via SciPy).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["rng", "random_tt", "sum_of_graded_terms", "conditioned_terms",
+           "uneven_jobs", "correlation_with_spectrum", "geometric_spectrum"]
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def random_tt(g: np.random.Generator, ns, ranks, dtype=np.float64, scale=1.0):
+    """TT with i.i.d. N(0, 1) cores (times ``scale``); ranks = (1, r_1, ..., 1)."""
+    d = len(ns)
+    if len(ranks) != d + 1 or ranks[0] != 1 or ranks[-1] != 1:
+        raise ValueError("ranks must be (1, r_1, ..., r_{d-1}, 1)")
+    cores = []
+    for k in range(d):
+        c = g.standard_normal((ranks[k], ns[k], ranks[k + 1])) * scale
+        cores.append(c.astype(dtype))
+    return cores
+
+
+def sum_of_graded_terms(seed=10001, nterms=20, d=8, n=32, r=10, dtype=np.float64):
+    """Lazy sum of ``nterms`` random rank-r TTs; term j has every core times 2**-j.
+
+    Returned as a list of (coef, cores) with coef = 1.  For float32 the values
+    are drawn in float64 and rounded once, so both precisions can be compared
+    on identical inputs (``astype(float64)`` of the float32 cores is exact).
+    """
+    g = rng(seed)
+    ranks = [1] + [r] * (d - 1) + [1]
+    terms = []
+    for j in range(nterms):
+        cores = random_tt(g, [n] * d, ranks, np.float64, scale=2.0 ** (-j))
+        terms.append((1.0, [c.astype(dtype) for c in cores]))
+    return terms
+
+
+def conditioned_terms(seed, m, d, n, r, dtype=np.float64):
+    """Generating TTs t_1..t_m with i.i.d. N(0, 1) cores, all ranks r."""
+    g = rng(seed)
+    ranks = [1] + [r] * (d - 1) + [1]
+    return [[c.astype(dtype) for c in random_tt(g, [n] * d, ranks)] for _ in range(m)]
+
+
+def geometric_spectrum(m, kappa):
+    """m eigenvalues spread geometrically over [1, 1/kappa], scaled to sum to m."""
+    if m == 1:
+        return np.ones(1)
+    lam = kappa ** (-np.arange(m) / (m - 1))
+    return lam * (m / lam.sum())
+
+
+def correlation_with_spectrum(seed, eigs):
+    """Random unit-diagonal SPD matrix with eigenvalues ``eigs`` (sum = len)."""
+    from scipy.stats import random_correlation
+    g = rng(seed)
+    M = random_correlation.rvs(np.asarray(eigs, dtype=np.float64), random_state=g, tol=1e-12)
+    return 0.5 * (M + M.T)
+
+
+def uneven_jobs(seed=30000, njobs=256, d_range=(4, 10), n_choices=(16, 32, 64),
+                r_range=(8, 128), dtype=np.float32):
+    """Independent rounding jobs: (cores, (d, n, R)) with N(0, 1) cores.
+
+    Each job draws d ~ U{d_lo..d_hi}, one mode size n ~ U(n_choices) for all
+    modes and one internal rank R ~ U{r_lo..r_hi} for every bond (bonds are
+    not capped to min(prod n_<=k, prod n_>k), so rounding must cut them).
+    """
+    g = rng(seed)
+    jobs = []
+    for _ in range(njobs):
+        d = int(g.integers(d_range[0], d_range[1] + 1))
+        n = int(g.choice(np.asarray(n_choices)))
+        R = int(g.integers(r_range[0], r_range[1] + 1))
+        ranks = [1] + [R] * (d - 1) + [1]
+        cores = random_tt(g, [n] * d, ranks, np.float64)
+        jobs.append(([c.astype(dtype) for c in cores], (d, n, R)))
+    return jobs

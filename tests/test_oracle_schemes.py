@@ -1,0 +1,155 @@
+"""Pins of the oracle's orthogonalization schemes (Algorithms 1-5) and LOO.
+
+Independent references: the dense matrix algorithms on vectorised inputs
+(to which each TT scheme reduces when the rounding accuracy goes to zero),
+structural invariants (round counts of Table 1, rank additivity of
+Section 2, the rank bound of the Gram scheme in Section 3.2), and the dense
+2-norm for the loss of orthogonality.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense, tt_full, tt_ranks, tt_sum
+from paper_2211_08770_amd import synth
+from inputs import conditioned_inputs, as_dense_columns
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_inputs(seed=40, m=5, ns=(3, 4, 3), r=2, kappa=1e3):
+    X, C, M = conditioned_inputs(seed, m, len(ns), ns[0], r, kappa)
+    return X
+
+
+POWER = {"cgs": 2, "mgs": 1, "cgs2": 0, "mgs2": 0, "gram": 2}
+
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+def test_scheme_matches_dense_matrix_version(scheme):
+    X, C, M = conditioned_inputs(41, 5, 3, 4, 2, 1e4)
+    A = as_dense_columns(X)
+    kappa = math.sqrt(1e4)
+    res = oracle.orthogonalize(scheme, X, 1e-14)
+    Qd, Rd = dense.dense_orthogonalize(scheme, A)
+    Qt = as_dense_columns(res.Q)
+    tol = 1e-11 * max(1.0, kappa ** POWER[scheme])
+    assert np.allclose(res.R, Rd, rtol=0, atol=tol)
+    assert np.allclose(Qt, Qd, rtol=0, atol=tol)
+
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+def test_orthonormal_input_gives_identity(scheme):
+    # Orthonormal TT inputs: R = I and Q = A.
+    g = synth.rng(42)
+    ns = (3, 4, 3)
+    Qd, _ = np.linalg.qr(g.standard_normal((36, 4)))
+    A = []
+    for i in range(4):
+        cores, _ = oracle.tt_svd(Qd[:, i].reshape(ns), 0.0)
+        A.append(cores)
+    res = oracle.orthogonalize(scheme, A, 1e-13)
+    assert np.allclose(res.R, np.eye(4), atol=1e-12)
+    assert np.allclose(as_dense_columns(res.Q), Qd, atol=1e-12)
+
+
+def test_round_counts_follow_table1():
+    with open(os.path.join(GOLDEN, "table1_round_counts.json")) as f:
+        table = json.load(f)
+    X = small_inputs(m=4)
+    for scheme in oracle.SCHEMES:
+        res = oracle.orthogonalize(scheme, X, 1e-8)
+        assert res.rounds == table["rounds_per_vector"][scheme] * 4, scheme
+
+
+@pytest.mark.parametrize("scheme", ["cgs", "mgs"])
+def test_pre_round_rank_is_sum_of_ranks(scheme):
+    # p = a_i - sum_j R(j,i) q_j: its k-th rank is rank_k(a_i) + sum_j rank_k(q_j).
+    X = small_inputs(seed=43, m=4)
+    res = oracle.orthogonalize(scheme, X, 1e-6)
+    for i in range(4):
+        ra = tt_ranks(tt_sum(X[i]))
+        expect = [a + sum(tt_ranks(res.Q[j])[k] for j in range(i)) for k, a in enumerate(ra)]
+        expect[0] = expect[-1] = 1
+        assert res.pre_ranks[i] == expect
+
+
+def test_gram_rank_bound():
+    # Section 3.2: before rounding q_i has rank sum_{k<=i} rank(a_k); after rounding at most that.
+    X = small_inputs(seed=44, m=4)
+    res = oracle.gram(X, 1e-6)
+    for i in range(4):
+        bound = [sum(tt_ranks(tt_sum(X[k]))[b] for k in range(i + 1)) for b in range(4)]
+        bound[0] = bound[-1] = 1
+        assert res.pre_ranks[i] == bound
+        assert all(p <= q for p, q in zip(res.post_ranks[i], bound))
+
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+def test_qr_residual_is_of_order_delta(scheme):
+    delta = 1e-6
+    X = small_inputs(seed=45, m=5, kappa=1e2)
+    res = oracle.orthogonalize(scheme, X, delta)
+    A = as_dense_columns(X)
+    Q = as_dense_columns(res.Q)
+    for i in range(5):
+        r = A[:, i] - Q[:, : i + 1] @ res.R[: i + 1, i]
+        assert np.linalg.norm(r) <= 20 * (i + 1) * delta * np.linalg.norm(A[:, i])
+    assert np.allclose(np.tril(res.R, -1), 0)
+
+
+def test_loo_matches_dense_two_norm():
+    X = small_inputs(seed=46, m=5, kappa=1e6)
+    res = oracle.cgs(X, 1e-4)
+    Q = as_dense_columns(res.Q)
+    assert np.allclose(oracle.loo_curve(res.Q), dense.dloo(Q), rtol=1e-9, atol=1e-14)
+
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+def test_loo_bounds_with_delta_in_place_of_u(scheme):
+    # Table 1 (TT column): LOO = O(delta kappa^2) for CGS/Gram/MGS as printed,
+    # O(delta) for CGS2/MGS2.  Checked only where delta * kappa^p <= 0.1.
+    delta = 1e-8
+    X, C, M = conditioned_inputs(47, 6, 3, 4, 2, 1e4)
+    kappa_g = np.linalg.cond(M)
+    res = oracle.orthogonalize(scheme, X, delta)
+    loo = oracle.loo_curve(res.Q)
+    for k in range(1, 7):
+        kap = math.sqrt(np.linalg.cond(M[:k, :k]))
+        p = {"cgs": 2, "gram": 2, "mgs": 2, "cgs2": 0, "mgs2": 0}[scheme]
+        if delta * kap ** p <= 0.1:
+            assert loo[k - 1] <= 10 * k * delta * max(1.0, kap ** p) + 1e-13, (scheme, k)
+    assert kappa_g == pytest.approx(1e4, rel=1e-6)
+
+
+def test_gram_breakdown_on_dependent_input():
+    X = small_inputs(seed=48, m=3)
+    X.append([(1.0, tt_sum(X[1]))])          # exact duplicate of a_2
+    with pytest.raises(oracle.GramBreakdown):
+        oracle.gram(X, 1e-8)
+
+
+def test_mgs_projection_equals_component_form():
+    # The MGS projection of the unrounded running sum equals
+    # <a_i, q_j> - sum_{l<j} R(l,i) <q_l, q_j>, up to reordering of rounding.
+    X = small_inputs(seed=49, m=5, kappa=1e4)
+    res = oracle.mgs(X, 1e-6)
+    GQ = oracle.gram_of(res.Q)
+    for i in range(1, 5):
+        a = tt_sum(X[i])
+        for j in range(i):
+            comp = oracle.tt_dot(a, res.Q[j]) - sum(res.R[l, i] * GQ[l, j] for l in range(j))
+            scale = abs(oracle.tt_dot(a, res.Q[j])) + sum(abs(res.R[l, i] * GQ[l, j]) for l in range(j))
+            assert abs(comp - res.R[j, i]) <= 1e-13 * max(scale, 1.0)
+
+
+def test_conditioned_inputs_have_prescribed_gram():
+    X, C, M = conditioned_inputs(50, 6, 4, 3, 2, 1e6)
+    A = as_dense_columns(X)
+    G = A.T @ A
+    assert np.allclose(G, M, atol=1e-9)
+    assert np.linalg.cond(G) == pytest.approx(1e6, rel=1e-3)
