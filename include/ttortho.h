@@ -1,0 +1,167 @@
+/*
+ * ttortho.h - C ABI of the MI355X (gfx950) TT-rounding / TT-orthogonalization library.
+ *
+ * Implements, for tensors in Tensor-Train (TT) format, the operations of
+ * Coulaud, Giraud & Iannacito, "On some orthogonalization schemes in Tensor
+ * Train format" (Inria RR-9491):
+ *   - TT inner product and TT sum/axpy            (Section 2, TT-format)
+ *   - TT-round(x, delta)                          (Section 2; rounding algorithm cited there)
+ *   - TT-CGS, TT-MGS, TT-CGS2, TT-MGS2, TT-Gram   (Section 3, Algorithms 1-5)
+ *   - loss of orthogonality ||I - Q^T Q||_2       (Section 3.4, equation LOO)
+ *
+ * Conventions shared by every entry point
+ *   - Tensor data are DEVICE pointers on the context's device; every call is
+ *     ordered on the context's HIP stream and returns after that stream has
+ *     completed the call's work (so host-side outputs are valid on return).
+ *   - A TT-vector of order d stores core k (k = 0..d-1) row-major as
+ *     [r_k][n_k][r_{k+1}] at element offset sum_{j<k} r_j n_j r_{j+1};
+ *     r_0 = r_d = 1.  Its left unfolding ((r_k n_k) x r_{k+1}) and its right
+ *     unfolding (r_k x (n_k r_{k+1})) are both plain row-major views.
+ *   - dtype TT_F64: all arithmetic in double.  dtype TT_F32 ("FP32-bulk"):
+ *     cores are float and the bulk QR panels and contractions run in float,
+ *     while R factors of the QR trees, the small SVDs, norms, thresholds,
+ *     Gram/Cholesky steps and orthogonality measures are double.
+ *   - The caller owns every buffer.  Outputs never alias inputs.  The library
+ *     works inside the workspace attached to the context (see
+ *     tt_ctx_set_workspace) and never allocates or frees caller memory; it
+ *     keeps only a few small internal device/pinned buffers per context.
+ *   - Errors are returned as tt_status; nothing is thrown across the ABI.
+ *     Argument errors are detected before any device work.  On error the
+ *     contents of outputs are undefined.  tt_last_error() gives a message.
+ */
+#ifndef TTORTHO_H
+#define TTORTHO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TT_MAXD 64
+
+typedef enum {
+  TT_OK = 0,
+  TT_EINVAL = -1,       /* bad argument (shape, rank, dtype, delta, pointer)            */
+  TT_ENOMEM = -2,       /* internal small buffer could not be allocated                */
+  TT_ECAPACITY = -3,    /* workspace or output capacity too small (see tt_last_error)   */
+  TT_ENOTSPD = -4,      /* Gram matrix not positive definite (Section 3.2, remark)      */
+  TT_EBREAKDOWN = -5,   /* ||p|| = 0 in a Gram-Schmidt scheme (dependent inputs)        */
+  TT_ENONFINITE = -6,   /* NaN or Inf met in the data                                   */
+  TT_EDEVICE = -7,      /* HIP runtime error                                            */
+  TT_EGUARD = -8,       /* pre-round rank exceeded the caller's guard                   */
+  TT_ENOTIMPL = -9
+} tt_status;
+
+typedef enum { TT_F64 = 0, TT_F32 = 1 } tt_dtype;
+
+typedef enum { TT_CGS = 0, TT_MGS = 1, TT_CGS2 = 2, TT_MGS2 = 3, TT_GRAM = 4 } tt_scheme;
+
+/* One TT-vector (Section 2, TT representation).  Host struct, device data. */
+typedef struct tt_vec {
+  int32_t d;                  /* order, 1 <= d <= TT_MAXD                                */
+  int32_t dtype;              /* tt_dtype                                                */
+  int64_t n[TT_MAXD];         /* mode sizes n_0..n_{d-1} >= 1                            */
+  int64_t r[TT_MAXD + 1];     /* ranks r_0..r_d with r_0 = r_d = 1; written for outputs  */
+  void* data;                 /* device pointer to the packed cores                      */
+  int64_t capacity;           /* elements available at data (checked for outputs)        */
+} tt_vec;
+
+/* Lazy TT sum  sum_c coef[c] * comp[c]  (Section 2: TT addition, ranks add).
+ * Never materialised: rounding reads the components directly and uses the
+ * block structure of the sum.  coef is a HOST array. */
+typedef struct tt_sum {
+  int32_t ncomp;
+  const double* coef;
+  const tt_vec* comp;
+} tt_sum;
+
+/* Per-call statistics of tt_orthogonalize. */
+typedef struct tt_ortho_stats {
+  int32_t rounds;             /* TT-round calls made (Table 1: m, m, 2m, 2m, m)           */
+  int32_t m_reached;          /* vectors completed before any error                      */
+  int32_t max_pre_rank;       /* largest bond rank of a vector before rounding           */
+  int32_t max_post_rank;      /* largest bond rank of a vector after rounding            */
+} tt_ortho_stats;
+
+typedef struct tt_ctx tt_ctx;
+
+/* Create a context bound to HIP device `device` and stream `stream`
+ * (a hipStream_t, or NULL for the default stream).  Allocates a few KB of
+ * device and pinned host memory for ranks, norms and status words. */
+tt_status tt_ctx_create(tt_ctx** ctx, int device, void* stream);
+void tt_ctx_destroy(tt_ctx* ctx);
+
+/* Attach caller-owned device workspace (bytes, 256-byte aligned pointer).
+ * Every compute call checks that its need fits; otherwise TT_ECAPACITY and
+ * tt_ctx_required_bytes() tells the size that is needed. */
+tt_status tt_ctx_set_workspace(tt_ctx* ctx, void* workspace, size_t bytes);
+size_t tt_ctx_required_bytes(const tt_ctx* ctx);
+
+/* Human-readable status and last error message of this context. */
+const char* tt_status_str(tt_status s);
+const char* tt_last_error(const tt_ctx* ctx);
+
+/* <x, y> for two lazy sums (Section 2, Euclidean inner product; used by every
+ * algorithm of Section 3).  Computed as sum over component pairs of
+ * coef * coef' * <x_c, y_c'>, each by the left-to-right contraction
+ * W_k = sum_i X_k(i)^T W_{k-1} Y_k(i).  out: HOST double. */
+tt_status tt_dot(tt_ctx* ctx, const tt_sum* x, const tt_sum* y, double* out);
+
+/* npairs inner products <xs[p], ys[p]> in one batched launch. out: HOST [npairs]. */
+tt_status tt_dot_batched(tt_ctx* ctx, int32_t npairs, const tt_sum* xs, const tt_sum* ys,
+                         double* out);
+
+/* z = alpha * x + y materialised (Section 2: first core concatenated
+ * horizontally, middle cores block diagonal, last core vertically; ranks add).
+ * alpha multiplies x's first core.  z->r is written; z->capacity must be at
+ * least the packed size of the result. */
+tt_status tt_axpy(tt_ctx* ctx, double alpha, const tt_vec* x, const tt_vec* y, tt_vec* z);
+
+/* TT-round(x, delta) (Section 2): returns x~ with ||x - x~|| <= delta ||x||.
+ * Right-to-left QR sweep, then left-to-right truncated SVD at per-bond
+ * threshold delta / sqrt(d-1) * ||x||, keeping the smallest rank whose
+ * discarded tail is <= the threshold (and <= max_rank when max_rank > 0).
+ * Cores 0..d-2 of the result are left-orthonormal.  d = 1 copies; a zero
+ * tensor yields all ranks 1 (unit-vector cores 0..d-2, zero last core).  out->r is written; norm_x (HOST, nullable)
+ * receives ||x||. */
+tt_status tt_round(tt_ctx* ctx, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out,
+                   double* norm_x);
+
+/* njobs independent roundings in shared batched launches (jobs may differ in
+ * d, n, ranks and component count).  deltas, max_ranks (nullable) and
+ * job_status are HOST arrays of length njobs. */
+tt_status tt_round_batched(tt_ctx* ctx, int32_t njobs, const tt_sum* xs, const double* deltas,
+                           const int64_t* max_ranks, tt_vec* outs, tt_status* job_status);
+
+/* Upper bound on the packed size (elements) of TT-round(x): ranks are capped
+ * by min(sum of component ranks, prod n_{<=k}, prod n_{>k}). */
+int64_t tt_round_out_capacity(const tt_sum* x);
+
+/* Workspace bytes tt_round needs for x (batched: sum over jobs). */
+int64_t tt_round_workspace_bytes(const tt_sum* x);
+
+/* Orthogonalize m TT-vectors a[0..m-1] (each a lazy sum) with rounding
+ * accuracy delta (Section 3):  TT_CGS Algorithm 1, TT_MGS Algorithm 2,
+ * TT_CGS2 Algorithm 3, TT_MGS2 Algorithm 4, TT_GRAM Algorithm 5.
+ * Outputs: q[0..m-1] (caller buffers with capacity; r written), R (HOST,
+ * m*m column-major, upper triangular, A ~ Q R: column i holds the
+ * projections of a_i), loo (HOST [m], nullable: ||I_k - Q_k^T Q_k||_2 for
+ * k = 1..m), stats (nullable).  rank_guard > 0 stops with TT_EGUARD when a
+ * vector to be rounded would exceed that bond rank.  Errors:
+ * TT_ENOTSPD (Gram: Cholesky fails), TT_EBREAKDOWN (||p|| = 0). */
+tt_status tt_orthogonalize(tt_ctx* ctx, tt_scheme scheme, int32_t m, const tt_sum* a, double delta,
+                           int64_t rank_guard, tt_vec* q, double* R, double* loo,
+                           tt_ortho_stats* stats);
+
+/* Loss of orthogonality ||I_k - Q_k^T Q_k||_2, k = 1..m (Section 3.4):
+ * Gram matrix of q by TT inner products, then the largest |eigenvalue| of
+ * each leading block (symmetric Jacobi on the device).  loo: HOST [m];
+ * gram (HOST m*m, nullable) receives Q^T Q. */
+tt_status tt_loo(tt_ctx* ctx, int32_t m, const tt_vec* q, double* loo, double* gram);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TTORTHO_H */

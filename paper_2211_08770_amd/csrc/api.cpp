@@ -1,0 +1,843 @@
+// extern "C" entry points of libttortho: argument checking, buffer planning
+// and the sequencing of the orthogonalization schemes (Algorithms 1-5 of the
+// paper).  All arithmetic on TT data and on the small FP64 matrices runs in
+// the kernels; this file only decides what to launch and moves descriptors,
+// ranks and scalar coefficients between host and device.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+
+#include "host.h"
+
+using namespace tto;
+
+// ============================================================================
+// arenas, workspace, errors
+// ============================================================================
+namespace tto {
+
+char* Arena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (chunks.empty() || off + bytes > chunks.back().second) {
+    size_t want = std::max<size_t>(bytes, chunks.empty() ? (size_t)4 << 20 : chunks.back().second * 2);
+    char* p = nullptr;
+    hipError_t e = pinned ? hipHostMalloc((void**)&p, want, hipHostMallocDefault) : hipMalloc((void**)&p, want);
+    if (e != hipSuccess || !p) return nullptr;
+    chunks.push_back({p, want});
+    off = 0;
+  }
+  char* p = chunks.back().first + off;
+  off += bytes;
+  used_total += bytes;
+  return p;
+}
+
+void Arena::reset() {
+  // keep one chunk big enough for the whole of the last call
+  if (chunks.size() > 1) {
+    size_t total = 0;
+    for (auto& c : chunks) total += c.second;
+    release();
+    char* p = nullptr;
+    hipError_t e = pinned ? hipHostMalloc((void**)&p, total, hipHostMallocDefault) : hipMalloc((void**)&p, total);
+    if (e == hipSuccess && p) chunks.push_back({p, total});
+  }
+  off = 0;
+  used_total = 0;
+}
+
+void Arena::release() {
+  for (auto& c : chunks) {
+    if (pinned) (void)hipHostFree(c.first);
+    else (void)hipFree(c.first);
+  }
+  chunks.clear();
+  off = 0;
+}
+
+tt_status fail(tt_ctx* c, tt_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+tt_status hip_fail(tt_ctx* c, hipError_t e, const char* where) {
+  return fail(c, TT_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+void* ws_alloc(tt_ctx* c, size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  const size_t off = c->ws_off;
+  c->ws_off += bytes;
+  c->required = std::max(c->required, c->ws_off);
+  if (c->ws_off > c->ws_bytes || c->ws == nullptr) {
+    c->ws_overflow = true;
+    return nullptr;
+  }
+  return c->ws + off;
+}
+
+void* upload_bytes(tt_ctx* c, const void* src, size_t bytes) {
+  char* d = c->dev.alloc(bytes);
+  char* h = c->pin.alloc(bytes);
+  if (!d || !h) return nullptr;
+  std::memcpy(h, src, bytes);
+  if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess) return nullptr;
+  return d;
+}
+
+void* dev_scratch(tt_ctx* c, size_t bytes) { return c->dev.alloc(bytes); }
+
+}  // namespace tto
+
+namespace {
+
+// Resets the per-call arenas once the stream has drained (every entry point
+// synchronises before returning, so nothing in flight refers to them).
+struct CallScope {
+  tt_ctx* c;
+  explicit CallScope(tt_ctx* ctx) : c(ctx) {
+    c->err.clear();
+    (void)hipSetDevice(c->device);
+  }
+  ~CallScope() {
+    (void)hipStreamSynchronize(c->stream);
+    c->dev.reset();
+    c->pin.reset();
+  }
+};
+
+int64_t packed_size(const tt_vec* v) {
+  int64_t s = 0;
+  for (int k = 0; k < v->d; ++k) s += v->r[k] * v->n[k] * v->r[k + 1];
+  return s;
+}
+
+tt_status check_vec(tt_ctx* c, const tt_vec* v, const char* what, bool input) {
+  if (!v) return fail(c, TT_EINVAL, std::string(what) + ": null tt_vec");
+  if (v->d < 1 || v->d > TT_MAXD) return fail(c, TT_EINVAL, std::string(what) + ": order d out of [1, 64]");
+  if (v->dtype != TT_F64 && v->dtype != TT_F32) return fail(c, TT_EINVAL, std::string(what) + ": bad dtype");
+  for (int k = 0; k < v->d; ++k)
+    if (v->n[k] < 1) return fail(c, TT_EINVAL, std::string(what) + ": mode size < 1");
+  if (!v->data) return fail(c, TT_EINVAL, std::string(what) + ": null data");
+  if (input) {
+    if (v->r[0] != 1 || v->r[v->d] != 1) return fail(c, TT_EINVAL, std::string(what) + ": r_0 and r_d must be 1");
+    for (int k = 1; k < v->d; ++k)
+      if (v->r[k] < 1) return fail(c, TT_EINVAL, std::string(what) + ": rank < 1");
+    if (v->capacity < packed_size(v))
+      return fail(c, TT_EINVAL, std::string(what) + ": capacity smaller than the packed cores");
+  }
+  return TT_OK;
+}
+
+tt_status check_sum(tt_ctx* c, const tt_sum* x, const char* what) {
+  if (!x || x->ncomp < 1 || !x->comp || !x->coef)
+    return fail(c, TT_EINVAL, std::string(what) + ": empty or null sum");
+  tt_status s;
+  for (int i = 0; i < x->ncomp; ++i) {
+    if ((s = check_vec(c, &x->comp[i], what, true)) != TT_OK) return s;
+    if (!std::isfinite(x->coef[i])) return fail(c, TT_EINVAL, std::string(what) + ": non-finite coefficient");
+    const tt_vec& a = x->comp[0];
+    const tt_vec& b = x->comp[i];
+    if (a.d != b.d || a.dtype != b.dtype) return fail(c, TT_EINVAL, std::string(what) + ": components differ in d/dtype");
+    for (int k = 0; k < a.d; ++k)
+      if (a.n[k] != b.n[k]) return fail(c, TT_EINVAL, std::string(what) + ": components differ in mode sizes");
+  }
+  return TT_OK;
+}
+
+bool same_shape(const tt_vec& a, const tt_vec& b) {
+  if (a.d != b.d || a.dtype != b.dtype) return false;
+  for (int k = 0; k < a.d; ++k)
+    if (a.n[k] != b.n[k]) return false;
+  return true;
+}
+
+// caps_k = min(prod_{j<k} n_j, prod_{j>=k} n_j), saturating
+void rank_caps(const tt_vec& v, int64_t* caps) {
+  const int d = v.d;
+  const int64_t BIG = std::numeric_limits<int64_t>::max() / 4;
+  caps[0] = caps[d] = 1;
+  for (int k = 1; k < d; ++k) {
+    int64_t l = 1, r = 1;
+    for (int j = 0; j < k; ++j) l = (l > BIG / v.n[j]) ? BIG : l * v.n[j];
+    for (int j = k; j < d; ++j) r = (r > BIG / v.n[j]) ? BIG : r * v.n[j];
+    caps[k] = std::min(l, r);
+  }
+}
+
+}  // namespace
+
+namespace tto {
+
+tt_status make_job(tt_ctx* c, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out, RJob& job) {
+  const tt_vec& v0 = x->comp[0];
+  job.d = v0.d;
+  job.dtype = v0.dtype;
+  for (int k = 0; k < job.d; ++k) job.n[k] = v0.n[k];
+  job.comps.clear();
+  job.roff.assign((size_t)x->ncomp * (job.d + 1), 0);
+  for (int k = 0; k <= job.d; ++k) job.R[k] = 0;
+  for (int i = 0; i < x->ncomp; ++i) {
+    const tt_vec& v = x->comp[i];
+    Comp cp;
+    cp.data = (const char*)v.data;
+    cp.coef = x->coef[i];
+    int64_t off = 0;
+    for (int k = 0; k <= job.d; ++k) cp.r[k] = v.r[k];
+    for (int k = 0; k < job.d; ++k) {
+      cp.core_off[k] = off;
+      off += v.r[k] * v.n[k] * v.r[k + 1];
+    }
+    for (int k = 0; k <= job.d; ++k) {
+      job.roff[(size_t)i * (job.d + 1) + k] = job.R[k];
+      job.R[k] += v.r[k];
+    }
+    job.comps.push_back(cp);
+  }
+  job.R[0] = job.R[job.d] = 1;
+  job.delta = delta;
+  job.max_rank = max_rank;
+  job.out = out;
+  job.status = TT_OK;
+  (void)c;
+  return TT_OK;
+}
+
+// out_dev[p] = <xs[p], ys[p]> = sum_{c, c'} coef_c coef'_c' <x_c, y_c'>  (device doubles).
+// When out_idx is given the p-th result goes to out_dev[out_idx[p]].
+tt_status dot_pairs_idx(tt_ctx* c, int npairs, const tt_sum* xs, const tt_sum* ys, double* out_dev,
+                        const std::vector<int32_t>* out_idx) {
+  if (npairs <= 0) return TT_OK;
+  const int dtype = xs[0].comp[0].dtype;
+  const size_t elt = elt_size(dtype);
+  struct Mark {
+    tt_ctx* c;
+    size_t off;
+    ~Mark() { c->ws_off = off; }
+  } mark{c, c->ws_off};
+  // device geometry per distinct component
+  std::vector<const tt_vec*> uniq;
+  std::vector<int64_t> geo;
+  auto geom_of = [&](const tt_vec* v) -> size_t {
+    for (size_t i = 0; i < uniq.size(); ++i)
+      if (uniq[i] == v) return i;
+    uniq.push_back(v);
+    return uniq.size() - 1;
+  };
+  struct Pair {
+    size_t gx, gy;
+    const tt_vec* x;
+    const tt_vec* y;
+    double coef;
+    int64_t wcap, tcap;
+  };
+  std::vector<Pair> pairs;
+  std::vector<int32_t> seg(1, 0);
+  for (int p = 0; p < npairs; ++p) {
+    for (int a = 0; a < xs[p].ncomp; ++a) {
+      for (int b = 0; b < ys[p].ncomp; ++b) {
+        const tt_vec* x = &xs[p].comp[a];
+        const tt_vec* y = &ys[p].comp[b];
+        if (!same_shape(*x, *y)) return fail(c, TT_EINVAL, "dot: operands differ in d, n or dtype");
+        Pair pr;
+        pr.x = x;
+        pr.y = y;
+        pr.gx = geom_of(x);
+        pr.gy = geom_of(y);
+        pr.coef = xs[p].coef[a] * ys[p].coef[b];
+        pr.wcap = 1;
+        pr.tcap = 1;
+        for (int k = 0; k < x->d; ++k) {
+          pr.wcap = std::max(pr.wcap, x->r[k + 1] * y->r[k + 1]);
+          pr.tcap = std::max(pr.tcap, x->r[k] * x->n[k] * y->r[k + 1]);
+        }
+        pairs.push_back(pr);
+      }
+    }
+    seg.push_back((int32_t)pairs.size());
+  }
+  // geometry upload: per component [n(d) | r(d+1)]
+  std::vector<size_t> goff;
+  for (const tt_vec* v : uniq) {
+    goff.push_back(geo.size());
+    for (int k = 0; k < v->d; ++k) geo.push_back(v->n[k]);
+    for (int k = 0; k <= v->d; ++k) geo.push_back(v->r[k]);
+  }
+  const int64_t* dgeo = upload(c, geo);
+  double* slots = (double*)dev_scratch(c, pairs.size() * 8);
+  if (!dgeo || !slots) return fail(c, TT_ENOMEM, "dot buffers");
+  // scratch in chunks bounded by a budget
+  const size_t budget = (size_t)256 << 20;
+  size_t i0 = 0;
+  while (i0 < pairs.size()) {
+    size_t bytes = 0, i1 = i0;
+    while (i1 < pairs.size()) {
+      const size_t need = ((size_t)(2 * pairs[i1].wcap + pairs[i1].tcap) * elt + 511) & ~(size_t)255;
+      if (i1 > i0 && bytes + need > budget) break;
+      bytes += need;
+      ++i1;
+    }
+    char* scratch = (char*)ws_alloc(c, bytes);
+    if (!scratch) return fail(c, TT_ECAPACITY, "workspace too small for dot scratch: need " + std::to_string(c->required));
+    std::vector<DotTask> tasks;
+    size_t o = 0;
+    for (size_t i = i0; i < i1; ++i) {
+      const Pair& pr = pairs[i];
+      DotTask t;
+      std::memset(&t, 0, sizeof(t));
+      t.d = pr.x->d;
+      t.x = pr.x->data;
+      t.y = pr.y->data;
+      t.nn = dgeo + goff[pr.gx];
+      t.rx = dgeo + goff[pr.gx] + pr.x->d;
+      t.ry = dgeo + goff[pr.gy] + pr.y->d;
+      t.coef = pr.coef;
+      t.w = scratch + o;
+      t.wcap = pr.wcap;
+      o += (size_t)2 * pr.wcap * elt;
+      o = (o + 255) & ~(size_t)255;
+      t.tmp = scratch + o;
+      o += (size_t)pr.tcap * elt;
+      o = (o + 255) & ~(size_t)255;
+      t.out = slots + i;
+      tasks.push_back(t);
+    }
+    const DotTask* dt = upload(c, tasks);
+    if (!dt) return fail(c, TT_ENOMEM, "dot tasks");
+    hipError_t e = launch_dot(dtype, dt, (int)tasks.size(), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "dot");
+    c->ws_off -= bytes;   // chunk scratch is reused by the next chunk (stream ordered)
+    c->ws_off = mark.off > c->ws_off ? mark.off : c->ws_off;
+    i0 = i1;
+  }
+  const int32_t* dseg = upload(c, seg);
+  const int32_t* didx = out_idx ? upload(c, *out_idx) : nullptr;
+  hipError_t e = launch_segsum(slots, dseg, didx, npairs, out_dev, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "dot reduce");
+  return TT_OK;
+}
+
+tt_status dot_pairs(tt_ctx* c, int npairs, const tt_sum* xs, const tt_sum* ys, double* out_dev) {
+  return dot_pairs_idx(c, npairs, xs, ys, out_dev, nullptr);
+}
+
+}  // namespace tto
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* tt_status_str(tt_status s) {
+  switch (s) {
+    case TT_OK: return "ok";
+    case TT_EINVAL: return "invalid argument";
+    case TT_ENOMEM: return "out of memory (internal buffers)";
+    case TT_ECAPACITY: return "workspace or output capacity too small";
+    case TT_ENOTSPD: return "Gram matrix not positive definite";
+    case TT_EBREAKDOWN: return "breakdown: zero vector after projection";
+    case TT_ENONFINITE: return "non-finite value";
+    case TT_EDEVICE: return "HIP runtime error";
+    case TT_EGUARD: return "rank guard exceeded";
+    case TT_ENOTIMPL: return "shape not supported";
+  }
+  return "unknown status";
+}
+
+tt_status tt_ctx_create(tt_ctx** ctx, int device, void* stream) {
+  if (!ctx) return TT_EINVAL;
+  *ctx = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TT_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return TT_EDEVICE;
+  static bool lds_ready = false;
+  if (!lds_ready) {
+    if (qr_kernels_init() != hipSuccess) return TT_EDEVICE;
+    lds_ready = true;
+  }
+  tt_ctx* c = new tt_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  c->pin.pinned = true;
+  c->dev.pinned = false;
+  *ctx = c;
+  return TT_OK;
+}
+
+void tt_ctx_destroy(tt_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  c->dev.release();
+  c->pin.release();
+  delete c;
+}
+
+tt_status tt_ctx_set_workspace(tt_ctx* c, void* ws, size_t bytes) {
+  if (!c) return TT_EINVAL;
+  if (ws && ((uintptr_t)ws & 255)) return fail(c, TT_EINVAL, "workspace must be 256-byte aligned");
+  c->ws = (char*)ws;
+  c->ws_bytes = ws ? bytes : 0;
+  c->ws_off = 0;
+  return TT_OK;
+}
+
+size_t tt_ctx_required_bytes(const tt_ctx* c) { return c ? c->required : 0; }
+
+const char* tt_last_error(const tt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+tt_status tt_dot_batched(tt_ctx* c, int32_t npairs, const tt_sum* xs, const tt_sum* ys, double* out) {
+  if (!c || npairs < 0 || (npairs > 0 && (!xs || !ys || !out))) return fail(c, TT_EINVAL, "dot: bad arguments");
+  if (npairs == 0) return TT_OK;
+  CallScope scope(c);
+  tt_status s;
+  for (int p = 0; p < npairs; ++p) {
+    if ((s = check_sum(c, &xs[p], "x")) != TT_OK) return s;
+    if ((s = check_sum(c, &ys[p], "y")) != TT_OK) return s;
+    if (!same_shape(xs[p].comp[0], ys[p].comp[0])) return fail(c, TT_EINVAL, "dot: shapes differ");
+    if (xs[p].comp[0].dtype != xs[0].comp[0].dtype) return fail(c, TT_EINVAL, "dot: mixed dtypes in a batch");
+  }
+  double* dout = (double*)dev_scratch(c, (size_t)npairs * 8);
+  double* hout = (double*)c->pin.alloc((size_t)npairs * 8);
+  if (!dout || !hout) return fail(c, TT_ENOMEM, "dot output");
+  if ((s = dot_pairs(c, npairs, xs, ys, dout)) != TT_OK) return s;
+  hipError_t e = hipMemcpyAsync(hout, dout, (size_t)npairs * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "dot readback");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "dot sync");
+  std::memcpy(out, hout, (size_t)npairs * 8);
+  return TT_OK;
+}
+
+tt_status tt_dot(tt_ctx* c, const tt_sum* x, const tt_sum* y, double* out) {
+  return tt_dot_batched(c, 1, x, y, out);
+}
+
+tt_status tt_axpy(tt_ctx* c, double alpha, const tt_vec* x, const tt_vec* y, tt_vec* z) {
+  if (!c) return TT_EINVAL;
+  tt_status s;
+  if ((s = check_vec(c, x, "x", true)) != TT_OK) return s;
+  if ((s = check_vec(c, y, "y", true)) != TT_OK) return s;
+  if ((s = check_vec(c, z, "z", false)) != TT_OK) return s;
+  if (!same_shape(*x, *y) || !same_shape(*x, *z)) return fail(c, TT_EINVAL, "axpy: operands differ in d, n or dtype");
+  if (!std::isfinite(alpha)) return fail(c, TT_EINVAL, "axpy: non-finite alpha");
+  const int d = x->d;
+  int64_t zr[TT_MAXD + 1];
+  zr[0] = zr[d] = 1;
+  for (int k = 1; k < d; ++k) zr[k] = x->r[k] + y->r[k];
+  int64_t need = 0;
+  for (int k = 0; k < d; ++k) need += zr[k] * x->n[k] * zr[k + 1];
+  if (z->capacity < need) return fail(c, TT_ECAPACITY, "axpy: z capacity " + std::to_string(z->capacity) +
+                                                           " < " + std::to_string(need));
+  CallScope scope(c);
+  const size_t elt = elt_size(x->dtype);
+  std::vector<AxpyTask> tasks;
+  int64_t xo = 0, yo = 0, zo = 0, maxe = 0;
+  for (int k = 0; k < d; ++k) {
+    AxpyTask t;
+    std::memset(&t, 0, sizeof(t));
+    t.x = (const char*)x->data + (size_t)xo * elt;
+    t.y = (const char*)y->data + (size_t)yo * elt;
+    t.z = (char*)z->data + (size_t)zo * elt;
+    t.n = (int32_t)x->n[k];
+    t.xr0 = (int32_t)x->r[k];
+    t.xr1 = (int32_t)x->r[k + 1];
+    t.yr0 = (int32_t)y->r[k];
+    t.yr1 = (int32_t)y->r[k + 1];
+    t.first = (k == 0);
+    t.last = (k == d - 1);
+    t.alpha = (k == 0) ? alpha : 1.0;
+    tasks.push_back(t);
+    xo += x->r[k] * x->n[k] * x->r[k + 1];
+    yo += y->r[k] * y->n[k] * y->r[k + 1];
+    const int64_t ze = zr[k] * x->n[k] * zr[k + 1];
+    zo += ze;
+    maxe = std::max(maxe, ze);
+  }
+  const AxpyTask* dt = upload(c, tasks);
+  if (!dt) return fail(c, TT_ENOMEM, "axpy tasks");
+  hipError_t e = launch_axpy(x->dtype, dt, (int)tasks.size(), maxe, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "axpy");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "axpy sync");
+  for (int k = 0; k <= d; ++k) z->r[k] = zr[k];
+  return TT_OK;
+}
+
+int64_t tt_round_out_capacity(const tt_sum* x) {
+  if (!x || x->ncomp < 1 || !x->comp) return -1;
+  const tt_vec& v = x->comp[0];
+  if (v.d < 1 || v.d > TT_MAXD) return -1;
+  int64_t caps[TT_MAXD + 1], R[TT_MAXD + 1];
+  rank_caps(v, caps);
+  for (int k = 0; k <= v.d; ++k) {
+    R[k] = 0;
+    for (int i = 0; i < x->ncomp; ++i) R[k] += x->comp[i].r[k];
+  }
+  R[0] = R[v.d] = 1;
+  int64_t s = 0;
+  for (int k = 0; k < v.d; ++k) s += std::min(R[k], caps[k]) * v.n[k] * std::min(R[k + 1], caps[k + 1]);
+  return s;
+}
+
+int64_t tt_round_workspace_bytes(const tt_sum* x) {
+  if (!x || x->ncomp < 1 || !x->comp) return -1;
+  std::vector<RJob> jobs(1);
+  make_job(nullptr, x, 0.0, 0, nullptr, jobs[0]);
+  return round_workspace_bytes(jobs);
+}
+
+tt_status tt_round_batched(tt_ctx* c, int32_t njobs, const tt_sum* xs, const double* deltas,
+                           const int64_t* max_ranks, tt_vec* outs, tt_status* job_status) {
+  if (!c || njobs < 0 || (njobs > 0 && (!xs || !deltas || !outs))) return fail(c, TT_EINVAL, "round: bad arguments");
+  if (njobs == 0) return TT_OK;
+  tt_status s;
+  for (int j = 0; j < njobs; ++j) {
+    if ((s = check_sum(c, &xs[j], "x")) != TT_OK) return s;
+    if ((s = check_vec(c, &outs[j], "out", false)) != TT_OK) return s;
+    if (!same_shape(xs[j].comp[0], outs[j])) return fail(c, TT_EINVAL, "round: out shape differs from x");
+    if (!(deltas[j] >= 0.0) || !std::isfinite(deltas[j])) return fail(c, TT_EINVAL, "round: delta must be >= 0");
+    if (xs[j].comp[0].dtype != xs[0].comp[0].dtype) return fail(c, TT_EINVAL, "round: mixed dtypes in a batch");
+  }
+  CallScope scope(c);
+  std::vector<RJob> jobs(njobs);
+  for (int j = 0; j < njobs; ++j)
+    make_job(c, &xs[j], deltas[j], max_ranks ? max_ranks[j] : 0, &outs[j], jobs[j]);
+  s = round_jobs(c, jobs);
+  if (s != TT_OK) return s;
+  tt_status first = TT_OK;
+  for (int j = 0; j < njobs; ++j) {
+    if (job_status) job_status[j] = jobs[j].status;
+    if (first == TT_OK && jobs[j].status != TT_OK) first = jobs[j].status;
+  }
+  if (first != TT_OK && c->err.empty()) c->err = "one or more jobs failed (see job_status)";
+  return first;
+}
+
+tt_status tt_round(tt_ctx* c, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out, double* norm_x) {
+  if (!c) return TT_EINVAL;
+  tt_status s;
+  if ((s = check_sum(c, x, "x")) != TT_OK) return s;
+  if ((s = check_vec(c, out, "out", false)) != TT_OK) return s;
+  if (!same_shape(x->comp[0], *out)) return fail(c, TT_EINVAL, "round: out shape differs from x");
+  if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(c, TT_EINVAL, "round: delta must be >= 0");
+  CallScope scope(c);
+  std::vector<RJob> jobs(1);
+  make_job(c, x, delta, max_rank, out, jobs[0]);
+  s = round_jobs(c, jobs);
+  if (s != TT_OK) return s;
+  if (jobs[0].status != TT_OK) return fail(c, jobs[0].status, "round: output capacity too small");
+  if (norm_x) *norm_x = jobs[0].norm;
+  return TT_OK;
+}
+
+// ----------------------------------------------------------------------------
+// Orthogonalization schemes (Section 3, Algorithms 1-5)
+// ----------------------------------------------------------------------------
+namespace {
+
+int64_t max_bond(const int64_t* R, int d) {
+  int64_t m = 0;
+  for (int k = 1; k < d; ++k) m = std::max(m, R[k]);
+  return m;
+}
+
+tt_status read_doubles(tt_ctx* c, const double* dsrc, double* hdst, size_t n) {
+  if (n == 0) return TT_OK;
+  double* h = (double*)c->pin.alloc(n * 8);
+  if (!h) return fail(c, TT_ENOMEM, "readback");
+  hipError_t e = hipMemcpyAsync(h, dsrc, n * 8, hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "readback");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "sync");
+  std::memcpy(hdst, h, n * 8);
+  return TT_OK;
+}
+
+tt_status round_one(tt_ctx* c, const tt_sum* x, double delta, tt_vec* out) {
+  std::vector<RJob> jobs(1);
+  make_job(c, x, delta, 0, out, jobs[0]);
+  tt_status s = round_jobs(c, jobs);
+  if (s != TT_OK) return s;
+  if (jobs[0].status != TT_OK) return fail(c, jobs[0].status, "rounding output capacity too small");
+  return TT_OK;
+}
+
+// Gq[i][j] = <q_i, q_j> for j <= i, then mirror into the upper triangle.
+tt_status gram_row(tt_ctx* c, int i, int m, const tt_vec* q, double* Gq) {
+  std::vector<tt_sum> xs(i + 1), ys(i + 1);
+  static const double one = 1.0;
+  for (int j = 0; j <= i; ++j) {
+    xs[j] = tt_sum{1, &one, &q[i]};
+    ys[j] = tt_sum{1, &one, &q[j]};
+  }
+  tt_status s = dot_pairs(c, i + 1, xs.data(), ys.data(), Gq + (size_t)i * m);
+  if (s != TT_OK) return s;
+  hipError_t e = launch_sym_lower(Gq, m, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "sym");
+  return TT_OK;
+}
+
+tt_status loo_from_gram(tt_ctx* c, const double* Gq, int m, double* loo_host) {
+  size_t esz = 0;
+  for (int k = 1; k <= m; ++k) esz += (size_t)k * k;
+  double* E = (double*)dev_scratch(c, esz * 8);
+  double* scratch = (double*)dev_scratch(c, (size_t)m * (4 * (size_t)m * m + 4 * m) * 8);
+  double* zero = (double*)dev_scratch(c, 8);
+  int32_t* ranks = (int32_t*)dev_scratch(c, (size_t)m * 4);
+  if (!E || !scratch || !zero || !ranks) return fail(c, TT_ENOMEM, "loo buffers");
+  hipError_t e = hipMemsetAsync(zero, 0, 8, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "loo");
+  if ((e = launch_loo_mats(Gq, m, E, c->stream)) != hipSuccess) return hip_fail(c, e, "loo mats");
+  std::vector<SvdTask> tasks;
+  size_t eo = 0, so = 0;
+  for (int k = 1; k <= m; ++k) {
+    SvdTask t;
+    std::memset(&t, 0, sizeof(t));
+    t.R = E + eo;
+    t.r_ld = k;
+    t.kr = k;
+    t.ncol = k;
+    t.upper = 0;
+    t.A = scratch + so;
+    so += (size_t)k * k;
+    t.acc = scratch + so;
+    so += (size_t)k * k;
+    t.sigma = scratch + so;
+    so += k;
+    t.perm = (int32_t*)(scratch + so);
+    so += k;
+    t.norm = zero;
+    t.delta_scaled = 0.0;
+    t.max_rank = 0;
+    t.rank_out = ranks + (k - 1);
+    t.wt = scratch + so;
+    so += (size_t)k * k;
+    t.ur = scratch + so;
+    so += (size_t)k * k;
+    tasks.push_back(t);
+    eo += (size_t)k * k;
+  }
+  const SvdTask* dt = upload(c, tasks);
+  if (!dt) return fail(c, TT_ENOMEM, "loo tasks");
+  if ((e = launch_svd(dt, m, c->stream)) != hipSuccess) return hip_fail(c, e, "loo svd");
+  for (int k = 0; k < m; ++k) {
+    tt_status s = read_doubles(c, tasks[k].sigma, &loo_host[k], 1);
+    if (s != TT_OK) return s;
+  }
+  return TT_OK;
+}
+
+}  // namespace
+
+tt_status tt_loo(tt_ctx* c, int32_t m, const tt_vec* q, double* loo, double* gram) {
+  if (!c || m < 1 || !q || !loo) return fail(c, TT_EINVAL, "loo: bad arguments");
+  tt_status s;
+  for (int i = 0; i < m; ++i) {
+    if ((s = check_vec(c, &q[i], "q", true)) != TT_OK) return s;
+    if (!same_shape(q[0], q[i])) return fail(c, TT_EINVAL, "loo: vectors differ in shape");
+  }
+  CallScope scope(c);
+  double* Gq = (double*)dev_scratch(c, (size_t)m * m * 8);
+  if (!Gq) return fail(c, TT_ENOMEM, "loo gram");
+  for (int i = 0; i < m; ++i)
+    if ((s = gram_row(c, i, m, q, Gq)) != TT_OK) return s;
+  if (gram && (s = read_doubles(c, Gq, gram, (size_t)m * m)) != TT_OK) return s;
+  return loo_from_gram(c, Gq, m, loo);
+}
+
+tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum* a, double delta, int64_t rank_guard,
+                           tt_vec* q, double* R, double* loo, tt_ortho_stats* stats) {
+  if (!c || m < 1 || !a || !q || !R) return fail(c, TT_EINVAL, "orthogonalize: bad arguments");
+  if (scheme < TT_CGS || scheme > TT_GRAM) return fail(c, TT_EINVAL, "orthogonalize: unknown scheme");
+  if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(c, TT_EINVAL, "orthogonalize: delta must be >= 0");
+  tt_status s;
+  for (int i = 0; i < m; ++i) {
+    if ((s = check_sum(c, &a[i], "a")) != TT_OK) return s;
+    if (!same_shape(a[i].comp[0], a[0].comp[0])) return fail(c, TT_EINVAL, "orthogonalize: inputs differ in shape");
+    if ((s = check_vec(c, &q[i], "q", false)) != TT_OK) return s;
+    if (!same_shape(q[i], a[0].comp[0])) return fail(c, TT_EINVAL, "orthogonalize: q shape differs from inputs");
+  }
+  tt_ortho_stats st;
+  std::memset(&st, 0, sizeof(st));
+  CallScope scope(c);
+  const size_t mark = c->ws_off;
+  struct Mark {
+    tt_ctx* c;
+    size_t off;
+    ~Mark() { c->ws_off = off; }
+  } wmark{c, mark};
+  const int d = a[0].comp[0].d;
+  double* R1 = (double*)dev_scratch(c, (size_t)m * m * 8);   // column-major: R(j, i) at i*m + j
+  double* R2 = (double*)dev_scratch(c, (size_t)m * m * 8);
+  double* Gq = (double*)dev_scratch(c, (size_t)m * m * 8);
+  double* dots = (double*)dev_scratch(c, (size_t)m * 8);
+  double* neg = (double*)dev_scratch(c, (size_t)m * 8);
+  double* nrm = (double*)dev_scratch(c, (size_t)m * 8);
+  if (!R1 || !R2 || !Gq || !dots || !neg || !nrm) return fail(c, TT_ENOMEM, "orthogonalize buffers");
+  hipError_t e;
+  if ((e = hipMemsetAsync(R1, 0, (size_t)m * m * 8, c->stream)) != hipSuccess) return hip_fail(c, e, "memset");
+  if ((e = hipMemsetAsync(R2, 0, (size_t)m * m * 8, c->stream)) != hipSuccess) return hip_fail(c, e, "memset");
+  auto finish = [&](tt_status rs) {
+    if (stats) *stats = st;
+    return rs;
+  };
+
+  if (scheme == TT_GRAM) {
+    // G(i, j) = <a_i, a_j>  (one batched launch), Cholesky, R^{-1}
+    std::vector<tt_sum> xs, ys;
+    std::vector<int32_t> idx;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j <= i; ++j) {
+        xs.push_back(a[i]);
+        ys.push_back(a[j]);
+        idx.push_back(i * m + j);
+      }
+    double* G = (double*)dev_scratch(c, (size_t)m * m * 8);
+    double* Rinv = (double*)dev_scratch(c, (size_t)m * m * 8);
+    int32_t* info = (int32_t*)dev_scratch(c, 8);
+    if (!G || !Rinv || !info) return finish(fail(c, TT_ENOMEM, "gram buffers"));
+    if ((s = dot_pairs_idx(c, (int)xs.size(), xs.data(), ys.data(), G, &idx)) != TT_OK) return finish(s);
+    if ((e = launch_sym_lower(G, m, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "sym"));
+    if ((e = launch_cholinv(G, m, Rinv, info, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "cholesky"));
+    int32_t* hinfo = (int32_t*)c->pin.alloc(8);
+    if ((e = hipMemcpyAsync(hinfo, info, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
+      return finish(hip_fail(c, e, "info"));
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return finish(hip_fail(c, e, "sync"));
+    if (*hinfo != 0)
+      return finish(fail(c, TT_ENOTSPD, "Gram matrix not positive definite at pivot " + std::to_string(*hinfo)));
+    // R = L^T in column-major == lower triangle of L in row-major
+    if ((e = launch_tril(G, m, R1, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "tril"));
+    if ((s = read_doubles(c, R1, R, (size_t)m * m)) != TT_OK) return finish(s);
+    std::vector<double> rinv((size_t)m * m);
+    if ((s = read_doubles(c, Rinv, rinv.data(), rinv.size())) != TT_OK) return finish(s);
+    // q_i = round( sum_{k<=i} R^{-1}(k, i) a_k ): m independent roundings, one batch
+    std::vector<std::vector<double>> coefs(m);
+    std::vector<std::vector<tt_vec>> comps(m);
+    std::vector<RJob> jobs(m);
+    std::vector<tt_sum> sums(m);
+    for (int i = 0; i < m; ++i) {
+      for (int k = 0; k <= i; ++k)
+        for (int cc = 0; cc < a[k].ncomp; ++cc) {
+          coefs[i].push_back(rinv[(size_t)k * m + i] * a[k].coef[cc]);
+          comps[i].push_back(a[k].comp[cc]);
+        }
+      sums[i] = tt_sum{(int32_t)comps[i].size(), coefs[i].data(), comps[i].data()};
+      make_job(c, &sums[i], delta, 0, &q[i], jobs[i]);
+      const int64_t pre = max_bond(jobs[i].R, d);
+      st.max_pre_rank = (int32_t)std::max<int64_t>(st.max_pre_rank, pre);
+      if (rank_guard > 0 && pre > rank_guard) {
+        jobs.resize(i);
+        st.m_reached = i;
+        break;
+      }
+    }
+    const bool guarded = (int)jobs.size() < m;
+    if (!jobs.empty()) {
+      if ((s = round_jobs(c, jobs)) != TT_OK) return finish(s);
+      for (auto& jb : jobs) {
+        if (jb.status != TT_OK) return finish(fail(c, jb.status, "gram: output capacity"));
+        st.max_post_rank = (int32_t)std::max<int64_t>(st.max_post_rank, max_bond(jb.out->r, d));
+      }
+      st.rounds = (int32_t)jobs.size();
+    }
+    if (guarded) return finish(fail(c, TT_EGUARD, "pre-round rank exceeds the guard at vector " + std::to_string(st.m_reached)));
+    st.m_reached = m;
+    if (loo) {
+      for (int i = 0; i < m; ++i)
+        if ((s = gram_row(c, i, m, q, Gq)) != TT_OK) return finish(s);
+      if ((s = loo_from_gram(c, Gq, m, loo)) != TT_OK) return finish(s);
+    }
+    return finish(TT_OK);
+  }
+
+  // ---- CGS, MGS, CGS2, MGS2
+  const bool modified = (scheme == TT_MGS || scheme == TT_MGS2);
+  const int passes = (scheme == TT_CGS2 || scheme == TT_MGS2) ? 2 : 1;
+  static const double one = 1.0;
+  tt_vec p1;                                 // rounded first-pass vector of the two-pass schemes
+  std::memset(&p1, 0, sizeof(p1));
+  for (int i = 0; i < m; ++i) {
+    tt_sum src = a[i];
+    for (int pass = 0; pass < passes; ++pass) {
+      double* Rk = (pass == 0) ? R1 : R2;
+      std::vector<double> coefs(src.coef, src.coef + src.ncomp);
+      std::vector<tt_vec> comps(src.comp, src.comp + src.ncomp);
+      if (i > 0) {
+        std::vector<tt_sum> xs(i, src), ys(i);
+        for (int j = 0; j < i; ++j) ys[j] = tt_sum{1, &one, &q[j]};
+        if ((s = dot_pairs(c, i, xs.data(), ys.data(), dots)) != TT_OK) return finish(s);
+        double* col = Rk + (size_t)i * m;
+        if (modified) {
+          if ((e = launch_mgs_correct(dots, Gq, m, i, col, neg, c->stream)) != hipSuccess)
+            return finish(hip_fail(c, e, "mgs"));
+        } else {
+          if ((e = hipMemcpyAsync(col, dots, (size_t)i * 8, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+            return finish(hip_fail(c, e, "copy"));
+          if ((e = launch_neg(dots, neg, i, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "neg"));
+        }
+        std::vector<double> hneg(i);
+        if ((s = read_doubles(c, neg, hneg.data(), i)) != TT_OK) return finish(s);
+        for (int j = 0; j < i; ++j) {
+          coefs.push_back(hneg[j]);
+          comps.push_back(q[j]);
+        }
+      }
+      tt_sum p{(int32_t)comps.size(), coefs.data(), comps.data()};
+      RJob probe;
+      make_job(c, &p, delta, 0, nullptr, probe);
+      const int64_t pre = max_bond(probe.R, d);
+      st.max_pre_rank = (int32_t)std::max<int64_t>(st.max_pre_rank, pre);
+      if (rank_guard > 0 && pre > rank_guard) {
+        st.m_reached = i;
+        return finish(fail(c, TT_EGUARD, "pre-round rank " + std::to_string(pre) + " exceeds the guard at vector " +
+                                             std::to_string(i)));
+      }
+      tt_vec* dest = &q[i];
+      if (pass + 1 < passes) {
+        // first pass of CGS2/MGS2: keep the rounded p_1 in the workspace
+        p1 = q[i];
+        const int64_t cap = tt_round_out_capacity(&p);
+        c->ws_off = mark;   // the previous p_1 is no longer needed
+        p1.data = ws_alloc(c, (size_t)cap * elt_size(p1.dtype));
+        p1.capacity = cap;
+        if (!p1.data)
+          return finish(fail(c, TT_ECAPACITY, "workspace too small for p_1: need " + std::to_string(c->required)));
+        dest = &p1;
+      }
+      if ((s = round_one(c, &p, delta, dest)) != TT_OK) return finish(s);
+      ++st.rounds;
+      st.max_post_rank = (int32_t)std::max<int64_t>(st.max_post_rank, max_bond(dest->r, d));
+      src = tt_sum{1, &one, &p1};
+    }
+    // R(i, i) = ||p|| = ||last core|| (cores 0..d-2 are left-orthonormal); q_i = p / R(i, i)
+    tt_vec& qi = q[i];
+    int64_t off = 0;
+    for (int k = 0; k + 1 < d; ++k) off += qi.r[k] * qi.n[k] * qi.r[k + 1];
+    const int64_t last = qi.r[d - 1] * qi.n[d - 1];
+    char* lastp = (char*)qi.data + (size_t)off * elt_size(qi.dtype);
+    if ((e = launch_sumsq(qi.dtype, lastp, last, nrm + i, c->stream)) != hipSuccess)
+      return finish(hip_fail(c, e, "norm"));
+    double* Rfin = (passes == 2) ? R2 : R1;
+    if ((e = hipMemcpyAsync(Rfin + (size_t)i * m + i, nrm + i, 8, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+      return finish(hip_fail(c, e, "diag"));
+    double hn = 0.0;
+    if ((s = read_doubles(c, nrm + i, &hn, 1)) != TT_OK) return finish(s);
+    if (!(hn > 0.0)) {
+      st.m_reached = i;
+      return finish(fail(c, hn == 0.0 ? TT_EBREAKDOWN : TT_ENONFINITE,
+                         "zero or non-finite norm after projection at vector " + std::to_string(i)));
+    }
+    if ((e = launch_scale(qi.dtype, lastp, last, nrm + i, c->stream)) != hipSuccess)
+      return finish(hip_fail(c, e, "scale"));
+    if ((s = gram_row(c, i, m, q, Gq)) != TT_OK) return finish(s);
+    st.m_reached = i + 1;
+  }
+  if (passes == 2) {
+    if ((e = launch_add(R1, R2, R1, m * m, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "R1+R2"));
+  }
+  if ((s = read_doubles(c, R1, R, (size_t)m * m)) != TT_OK) return finish(s);
+  if (loo && (s = loo_from_gram(c, Gq, m, loo)) != TT_OK) return finish(s);
+  return finish(TT_OK);
+}
+
+}  // extern "C"

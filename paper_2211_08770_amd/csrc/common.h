@@ -1,0 +1,163 @@
+// Internal declarations shared by the HIP kernels and the host library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tto {
+
+// ---------------------------------------------------------------------------
+// Householder QR of one tile (TSQR leaf or tree node).
+//
+// The tile is row-major m x ncol (ld = ncol).  After factorisation its upper
+// triangle holds R and the strict lower part holds the Householder vectors
+// (unit leading entry implied); tau[j] and the per-panel triangular factors
+// T (blocked WY, Q = (I - V1 T1 V1^T)(I - V2 T2 V2^T)...) are stored beside it.
+// ---------------------------------------------------------------------------
+constexpr int QR_NB = 16;          // panel width
+constexpr int QR_THREADS = 256;
+constexpr int QR_MAXROWS = 768;    // LDS panel: QR_MAXROWS x QR_NB doubles = 96 KiB
+
+struct QrTask {
+  const void* src;        // leaf: element (r, c) at src[r * src_rs + c * src_cs]
+  int64_t src_rs, src_cs;
+  int32_t nchild;         // > 0: tree node stacking the R factors of children[child0 ..]
+  int32_t child0;
+  int32_t m, ncol;        // tile shape
+  void* tile;             // row-major m x ncol
+  double* tau;            // [min(m, ncol)]
+  void* tmat;             // [npanels][QR_NB][QR_NB] row-major upper triangular T
+};
+
+// Apply the orthogonal factor of a factored tile:  out = Q * [X; 0].
+// X is k_in x t (double, row-major, ld = x_ld); out is m x t.
+struct ApplyTask {
+  const void* tile;       // factored tile (V below the diagonal), ld = ncol
+  const double* tau;
+  const void* tmat;
+  int32_t m, ncol, kq;    // kq = number of reflectors = min(m, ncol)
+  int32_t k_in, t;
+  const double* x;
+  int64_t x_ld;
+  double* work;           // m x t row-major scratch (tree nodes keep their result here)
+  void* out;              // leaves: final destination (out dtype), strides below
+  int64_t out_rs, out_cs;
+  int32_t to_out;         // 1: write to out (with cast); 0: result stays in work
+};
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi SVD of a (kr x ncol) upper-trapezoidal R factor, FP64.
+// ---------------------------------------------------------------------------
+struct SvdTask {
+  const double* R;        // row-major kr x ncol, ld = r_ld (root tile of a TSQR)
+  int64_t r_ld;
+  int32_t kr, ncol;
+  int32_t upper;          // 1: R is upper trapezoidal (entries below the diagonal read as 0)
+  double* A;              // scratch ncol x kr, column-major
+  double* acc;            // scratch kr x kr, column-major
+  double* sigma;          // [kr] sorted decreasing on exit
+  int32_t* perm;          // [kr] scratch
+  const double* norm;     // device ||x||; eps = delta / sqrt(d-1) * norm
+  double delta_scaled;    // delta / sqrt(d-1)
+  int64_t max_rank;       // <= 0: none
+  int32_t* rank_out;      // device int
+  double* wt;             // ncol x t row-major:  W^T  with W = Sigma_t V_t^T
+  double* ur;             // kr x t row-major:  left factor fed to Q application
+  int32_t* info;          // device int: sweeps used (diagnostic)
+};
+
+// ---------------------------------------------------------------------------
+// Batched GEMM used by the right-to-left contraction:
+//   C[r][c] = sum_parts coef_p * sum_k A_p[r][k] * B[c][b_off_p + k]
+// A_p row-major (M x K_p, ld = K_p, dtype T); B row-major double (ld = b_ld);
+// C row-major (M x N, ld = c_ld, dtype T).
+// ---------------------------------------------------------------------------
+struct GemmPart {
+  const void* A;
+  int32_t K;
+  int32_t b_off;
+  double coef;
+};
+
+struct GemmTask {
+  int32_t M, N;
+  int32_t part0, nparts;
+  const double* B;        // entries B[c][j] with j < c read as zero (R factor of a tile)
+  int64_t b_ld;
+  void* C;
+  int64_t c_ld;
+};
+
+// ---------------------------------------------------------------------------
+// TT inner product of one pair of components (left-to-right contraction).
+// ---------------------------------------------------------------------------
+struct DotTask {
+  int32_t d;
+  const void* x;          // packed cores
+  const void* y;
+  const int64_t* nn;      // device [d] mode sizes
+  const int64_t* rx;      // device [d+1] ranks of x
+  const int64_t* ry;      // device [d+1] ranks of y
+  double coef;
+  void* w;                // scratch 2 * wcap elements (compute dtype)
+  int64_t wcap;           // >= max_k rx_k * ry_k
+  void* tmp;              // scratch >= max_k rx_k * n_k * ry_{k+1} elements
+  double* out;            // result slot: coef * <x, y>
+};
+
+// Batched strided copy: dst[i] = coef * src[i] (+ dst[i] when accumulate).
+struct CopySeg {
+  const void* src;
+  void* dst;
+  int64_t count;
+  double coef;
+  int32_t accumulate;
+};
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (defined in the .hip files).
+// ---------------------------------------------------------------------------
+hipError_t launch_qr_factor(int dtype_src, int dtype_tile, const QrTask* d_tasks, const QrTask* d_children,
+                            int ntasks, hipStream_t s);
+hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tasks, int ntasks,
+                           hipStream_t s);
+hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s);
+hipError_t launch_gemm(int dtype, const GemmTask* d_tasks, const GemmPart* d_parts, int ntasks,
+                       int max_m, int max_n, hipStream_t s);
+hipError_t launch_dot(int dtype, const DotTask* d_tasks, int ntasks, hipStream_t s);
+hipError_t launch_sumsq(int dtype, const void* x, int64_t n, double* out_norm, hipStream_t s);
+hipError_t launch_scale(int dtype, void* x, int64_t n, const double* d_norm, hipStream_t s);
+hipError_t launch_copy_segs(int dtype, const CopySeg* d_segs, int nsegs, hipStream_t s);
+// out[idx ? idx[o] : o] = sum of slots[seg[o] .. seg[o+1])
+hipError_t launch_segsum(const double* slots, const int32_t* seg, const int32_t* idx, int nout, double* out,
+                         hipStream_t s);
+hipError_t launch_cholinv(double* G, int m, double* Rinv, int32_t* info, hipStream_t s);
+hipError_t launch_loo_mats(const double* G, int m, double* E, hipStream_t s);
+
+// z core = alpha*x core (+) y core in the TT-sum layout (block concatenation).
+struct AxpyTask {
+  const void* x;
+  const void* y;
+  void* z;
+  int32_t n;
+  int32_t xr0, xr1, yr0, yr1;  // ranks of the x / y cores
+  int32_t first, last;         // first core: rows shared; last core: columns shared
+  double alpha;                // applied to x (first core only)
+};
+hipError_t launch_axpy(int dtype, const AxpyTask* d_tasks, int ntasks, int64_t max_elems, hipStream_t s);
+
+// Small FP64 updates of the scheme drivers (single thread, sequential order):
+//   MGS correction   r[j] = dots[j] - sum_{l<j} r[l] * Gq[l*ldg + j]   (j < i)
+//   negated copy     coef[j] = -r[j]
+hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int i, double* r, double* neg,
+                              hipStream_t s);
+// out[j] = a[j] + b[j]
+hipError_t launch_add(const double* a, const double* b, double* out, int n, hipStream_t s);
+hipError_t launch_neg(const double* a, double* out, int n, hipStream_t s);
+// Symmetrise a Gram matrix filled on (i, j), j <= i: G[j][i] = G[i][j].
+hipError_t launch_sym_lower(double* G, int m, hipStream_t s);
+// out[i*m + j] = L[i*m + j] for j <= i, else 0
+hipError_t launch_tril(const double* L, int m, double* out, hipStream_t s);
+
+hipError_t qr_kernels_init();   // raise LDS limits, once per process
+
+}  // namespace tto

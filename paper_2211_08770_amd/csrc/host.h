@@ -1,0 +1,121 @@
+// Host-side internals of the C ABI: context, allocators, TSQR planning and the
+// batched TT-round pipeline.  Only host code lives here; every arithmetic step
+// of the method runs in the kernels declared in common.h.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/ttortho.h"
+#include "common.h"
+
+namespace tto {
+
+// Library-owned growable arena (device or pinned host) for task descriptors
+// and small scalars.  Chunks allocated during a call stay valid until reset().
+struct Arena {
+  bool pinned = false;
+  std::vector<std::pair<char*, size_t>> chunks;
+  size_t off = 0;
+  size_t used_total = 0;
+  char* alloc(size_t bytes);
+  void reset();
+  void release();
+};
+
+}  // namespace tto
+
+struct tt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;          // caller workspace
+  size_t ws_bytes = 0;
+  size_t ws_off = 0;
+  bool ws_overflow = false;
+  size_t required = 0;
+  tto::Arena dev;              // task descriptors, scalars
+  tto::Arena pin;              // staging for uploads / readbacks
+  std::string err;
+};
+
+namespace tto {
+
+// ---- helpers used by the API implementation -------------------------------
+tt_status fail(tt_ctx* c, tt_status s, const std::string& msg);
+tt_status hip_fail(tt_ctx* c, hipError_t e, const char* where);
+
+// bump allocation in the caller workspace (256-byte aligned).  On overflow
+// returns nullptr and records the needed size; callers check c->ws_overflow
+// before launching anything.
+void* ws_alloc(tt_ctx* c, size_t bytes);
+
+template <typename T>
+T* ws_alloc_n(tt_ctx* c, size_t n) {
+  return (T*)ws_alloc(c, n * sizeof(T));
+}
+
+// upload a host array to a library-owned device buffer (stream ordered)
+void* upload_bytes(tt_ctx* c, const void* src, size_t bytes);
+template <typename T>
+T* upload(tt_ctx* c, const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  return (T*)upload_bytes(c, v.data(), v.size() * sizeof(T));
+}
+void* dev_scratch(tt_ctx* c, size_t bytes);
+
+inline size_t elt_size(int dtype) { return dtype == TT_F64 ? 8 : 4; }
+
+// ---- TSQR tree -------------------------------------------------------------
+struct Tree {
+  int64_t M = 0, N = 0;
+  int leaf_dtype = 0;                           // 0 f64, 1 f32
+  std::vector<std::vector<QrTask>> lvl;         // lvl[0] = leaves
+  std::vector<int64_t> leaf_row0;               // first row of each leaf
+  int kr() const;                               // rows of the root R factor
+  const double* root_R() const;                 // FP64 root tile (row-major, ld = N)
+  int depth() const { return (int)lvl.size(); }
+};
+
+// Plan (and carve from `alloc`) a TSQR tree for an M x N matrix whose element
+// (r, c) is at src[r*rs + c*cs] (dtype of the leaves).  Returns false when the
+// shape is outside what the tile kernels support.
+struct Carver {
+  tt_ctx* ctx = nullptr;    // carve from workspace when base == nullptr
+  char* base = nullptr;     // carve inside a reserved block
+  size_t off = 0, cap = 0;
+  bool measure = false;
+  void* take(size_t bytes);
+};
+bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs, int64_t cs,
+               std::string* why);
+
+// ---- rounding jobs ---------------------------------------------------------
+struct Comp {
+  const char* data = nullptr;
+  int64_t r[TT_MAXD + 1];
+  int64_t core_off[TT_MAXD];
+  double coef = 1.0;
+};
+
+struct RJob {
+  int d = 0;
+  int dtype = 0;
+  int64_t n[TT_MAXD];
+  std::vector<Comp> comps;
+  std::vector<int64_t> roff;      // [ncomp * (d+1)] rank offset of each component per bond
+  int64_t R[TT_MAXD + 1];         // summed ranks
+  double delta = 0.0;
+  int64_t max_rank = 0;
+  tt_vec* out = nullptr;
+  double norm = 0.0;
+  tt_status status = TT_OK;
+};
+
+tt_status make_job(tt_ctx* c, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out, RJob& job);
+tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs);
+int64_t round_workspace_bytes(const std::vector<RJob>& jobs);
+
+// ---- inner products ----------------------------------------------------------
+// out_dev[p] = <xs[p], ys[p]> (device doubles)
+tt_status dot_pairs(tt_ctx* c, int npairs, const tt_sum* xs, const tt_sum* ys, double* out_dev);
+
+}  // namespace tto

@@ -1,0 +1,324 @@
+// Small kernels of the TT hot path: TT inner products (batched over
+// component pairs), norms and scaling, block copies of TT sums, the FP64
+// Cholesky + triangular inverse of the Gram scheme, and the matrices whose
+// 2-norms give the loss of orthogonality.
+#include "common.h"
+
+namespace tto {
+
+namespace {
+
+constexpr int NT = 256;
+
+__device__ inline double block_sum256(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// <x, y> for one component pair:  W_k = sum_i X_k(i)^T W_{k-1} Y_k(i)  (left to right).
+// Step k first forms tmp = W_{k-1} * Y_k (as rx_k x (n_k ry_{k+1})), then
+// W_k = L(X_k)^T * tmp (viewing tmp as (rx_k n_k) x ry_{k+1}).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dot(const DotTask* __restrict__ tasks) {
+  const DotTask tk = tasks[blockIdx.x];
+  const int d = tk.d;
+  const int64_t* nn = tk.nn;
+  const int64_t* rx = tk.rx;
+  const int64_t* ry = tk.ry;
+  const T* X = (const T*)tk.x;
+  const T* Y = (const T*)tk.y;
+  T* W = (T*)tk.w;
+  T* Wn = W + tk.wcap;
+  T* tmp = (T*)tk.tmp;
+  const int tid = threadIdx.x;
+  if (tid == 0) W[0] = (T)1;
+  __syncthreads();
+  int64_t xo = 0, yo = 0;
+  for (int k = 0; k < d; ++k) {
+    const int64_t n = nn[k], a0 = rx[k], a1 = rx[k + 1], b0 = ry[k], b1 = ry[k + 1];
+    const T* Xk = X + xo;
+    const T* Yk = Y + yo;
+    const int64_t nt = a0 * n * b1;
+    for (int64_t e = tid; e < nt; e += NT) {
+      const int64_t a = e / (n * b1);
+      const int64_t rem = e - a * n * b1;   // = i * b1 + c
+      T s = (T)0;
+      for (int64_t b = 0; b < b0; ++b) s += W[a * b0 + b] * Yk[b * n * b1 + rem];
+      tmp[e] = s;
+    }
+    __syncthreads();
+    const int64_t nw = a1 * b1, q_n = a0 * n;
+    for (int64_t e = tid; e < nw; e += NT) {
+      const int64_t p = e / b1, c = e - p * b1;
+      T s = (T)0;
+      for (int64_t q = 0; q < q_n; ++q) s += Xk[q * a1 + p] * tmp[q * b1 + c];
+      Wn[e] = s;
+    }
+    __syncthreads();
+    T* sw = W;
+    W = Wn;
+    Wn = sw;
+    xo += a0 * n * a1;
+    yo += b0 * n * b1;
+  }
+  if (tid == 0) *tk.out = tk.coef * (double)W[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sumsq(const T* __restrict__ x, int64_t n, double* out) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double v = (double)x[i];
+    s += v * v;
+  }
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) *out = sqrt(s);
+}
+
+template <typename T>
+__global__ void k_scale(T* __restrict__ x, int64_t n, const double* __restrict__ nrm) {
+  const double v = *nrm;
+  const double inv = v > 0.0 ? 1.0 / v : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = (T)((double)x[i] * inv);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_copy_segs(const CopySeg* __restrict__ segs) {
+  const CopySeg sg = segs[blockIdx.y];
+  const T* src = (const T*)sg.src;
+  T* dst = (T*)sg.dst;
+  for (int64_t i = blockIdx.x * (int64_t)NT + threadIdx.x; i < sg.count; i += (int64_t)gridDim.x * NT) {
+    const double v = sg.coef * (double)src[i];
+    dst[i] = sg.accumulate ? (T)((double)dst[i] + v) : (T)v;
+  }
+}
+
+__global__ void k_segsum(const double* __restrict__ slots, const int32_t* __restrict__ seg,
+                         const int32_t* __restrict__ idx, int nout, double* __restrict__ out) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nout) return;
+  double s = 0.0;
+  for (int i = seg[o]; i < seg[o + 1]; ++i) s += slots[i];
+  out[idx ? idx[o] : o] = s;
+}
+
+// In-place lower Cholesky of the row-major m x m matrix G, then
+// Rinv = (L^T)^{-1} (upper triangular, row-major).  info = 0 on success,
+// j+1 when the j-th pivot is not positive (G not numerically SPD).
+__global__ __launch_bounds__(NT) void k_cholinv(double* __restrict__ G, int m, double* __restrict__ Rinv,
+                                                int32_t* __restrict__ info) {
+  __shared__ int fail;
+  const int tid = threadIdx.x;
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    if (tid == 0) {
+      double dj = G[j * m + j];
+      for (int k = 0; k < j; ++k) dj -= G[j * m + k] * G[j * m + k];
+      if (!(dj > 0.0)) fail = j + 1;
+      else G[j * m + j] = sqrt(dj);
+    }
+    __syncthreads();
+    if (fail) break;
+    for (int i = j + 1 + tid; i < m; i += NT) {
+      double s = G[i * m + j];
+      for (int k = 0; k < j; ++k) s -= G[i * m + k] * G[j * m + k];
+      G[i * m + j] = s / G[j * m + j];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (tid == 0) *info = fail;
+    return;
+  }
+  // R = L^T: R[r][k] = G[k*m + r].  Column c of R^{-1} by back substitution.
+  for (int c = tid; c < m; c += NT) {
+    for (int r = m - 1; r >= 0; --r) {
+      double v = 0.0;
+      if (r <= c) {
+        double s = (r == c) ? 1.0 : 0.0;
+        for (int k = r + 1; k <= c; ++k) s -= G[k * m + r] * Rinv[k * m + c];
+        v = s / G[r * m + r];
+      }
+      Rinv[r * m + c] = v;
+    }
+  }
+  if (tid == 0) *info = 0;
+}
+
+// E_k = I_k - G[:k, :k] for k = 1..m, stored back to back (row-major k x k).
+__global__ void k_loo_mats(const double* __restrict__ G, int m, double* __restrict__ E) {
+  const int k = blockIdx.x + 1;
+  double* Ek = E + (int64_t)(k - 1) * k * (2 * k - 1) / 6;
+  for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+    const int r = e / k, c = e - r * k;
+    Ek[e] = (r == c ? 1.0 : 0.0) - G[r * m + c];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_axpy(const AxpyTask* __restrict__ tasks) {
+  const AxpyTask tk = tasks[blockIdx.y];
+  const int zr0 = tk.first ? 1 : tk.xr0 + tk.yr0;
+  const int zr1 = tk.last ? 1 : tk.xr1 + tk.yr1;
+  const int64_t total = (int64_t)zr0 * tk.n * zr1;
+  const T* X = (const T*)tk.x;
+  const T* Y = (const T*)tk.y;
+  T* Z = (T*)tk.z;
+  for (int64_t e = blockIdx.x * (int64_t)NT + threadIdx.x; e < total; e += (int64_t)gridDim.x * NT) {
+    const int a = (int)(e / ((int64_t)tk.n * zr1));
+    const int64_t rem = e - (int64_t)a * tk.n * zr1;
+    const int i = (int)(rem / zr1), b = (int)(rem - (int64_t)i * zr1);
+    double v = 0.0;
+    const bool inx = (tk.first || a < tk.xr0) && (tk.last || b < tk.xr1);
+    const bool iny = (tk.first || a >= tk.xr0) && (tk.last || b >= tk.xr1);
+    if (inx) {
+      const int ax = tk.first ? 0 : a, bx = tk.last ? 0 : b;
+      v += tk.alpha * (double)X[((int64_t)ax * tk.n + i) * tk.xr1 + bx];
+    }
+    if (iny) {
+      const int ay = tk.first ? 0 : a - tk.xr0, by = tk.last ? 0 : b - tk.xr1;
+      v += (double)Y[((int64_t)ay * tk.n + i) * tk.yr1 + by];
+    }
+    Z[e] = (T)v;
+  }
+}
+
+__global__ void k_mgs_correct(const double* __restrict__ dots, const double* __restrict__ Gq, int ldg, int i,
+                              double* __restrict__ r, double* __restrict__ neg) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int j = 0; j < i; ++j) {
+    double s = dots[j];
+    for (int l = 0; l < j; ++l) s -= r[l] * Gq[(int64_t)l * ldg + j];
+    r[j] = s;
+    if (neg) neg[j] = -s;
+  }
+}
+
+__global__ void k_add(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a[i] + b[i];
+}
+
+__global__ void k_neg(const double* __restrict__ a, double* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = -a[i];
+}
+
+__global__ void k_sym_lower(double* __restrict__ G, int m) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int i = e / m, j = e - i * m;
+  if (j > i) G[e] = G[j * m + i];
+}
+
+__global__ void k_tril(const double* __restrict__ L, int m, double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int i = e / m, j = e - i * m;
+  out[e] = (j <= i) ? L[e] : 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_axpy(int dtype, const AxpyTask* d_tasks, int ntasks, int64_t max_elems, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  int bx = (int)((max_elems + NT - 1) / NT);
+  if (bx > 4096) bx = 4096;
+  if (bx < 1) bx = 1;
+  dim3 grid(bx, ntasks);
+  if (dtype == 0) hipLaunchKernelGGL(k_axpy<double>, grid, dim3(NT), 0, s, d_tasks);
+  else hipLaunchKernelGGL(k_axpy<float>, grid, dim3(NT), 0, s, d_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int i, double* r, double* neg,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_mgs_correct, dim3(1), dim3(64), 0, s, dots, Gq, ldg, i, r, neg);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(const double* a, const double* b, double* out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add, dim3((n + 255) / 256), dim3(256), 0, s, a, b, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_neg(const double* a, double* out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_neg, dim3((n + 255) / 256), dim3(256), 0, s, a, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_sym_lower(double* G, int m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sym_lower, dim3((m * m + 255) / 256), dim3(256), 0, s, G, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_tril(const double* L, int m, double* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tril, dim3((m * m + 255) / 256), dim3(256), 0, s, L, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(int dtype, const DotTask* d_tasks, int ntasks, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  if (dtype == 0) hipLaunchKernelGGL(k_dot<double>, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+  else hipLaunchKernelGGL(k_dot<float>, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(int dtype, const void* x, int64_t n, double* out, hipStream_t s) {
+  if (dtype == 0) hipLaunchKernelGGL(k_sumsq<double>, dim3(1), dim3(1024), 0, s, (const double*)x, n, out);
+  else hipLaunchKernelGGL(k_sumsq<float>, dim3(1), dim3(1024), 0, s, (const float*)x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(int dtype, void* x, int64_t n, const double* nrm, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)((n + NT - 1) / NT < 1024 ? (n + NT - 1) / NT : 1024);
+  if (dtype == 0) hipLaunchKernelGGL(k_scale<double>, dim3(blocks), dim3(NT), 0, s, (double*)x, n, nrm);
+  else hipLaunchKernelGGL(k_scale<float>, dim3(blocks), dim3(NT), 0, s, (float*)x, n, nrm);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_segs(int dtype, const CopySeg* d_segs, int nsegs, hipStream_t s) {
+  for (int first = 0; first < nsegs; first += 65535) {
+    const int cnt = (nsegs - first) < 65535 ? (nsegs - first) : 65535;
+    dim3 grid(16, cnt);
+    if (dtype == 0) hipLaunchKernelGGL(k_copy_segs<double>, grid, dim3(NT), 0, s, d_segs + first);
+    else hipLaunchKernelGGL(k_copy_segs<float>, grid, dim3(NT), 0, s, d_segs + first);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_segsum(const double* slots, const int32_t* seg, const int32_t* idx, int nout, double* out,
+                         hipStream_t s) {
+  if (nout <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_segsum, dim3((nout + 255) / 256), dim3(256), 0, s, slots, seg, idx, nout, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholinv(double* G, int m, double* Rinv, int32_t* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(NT), 0, s, G, m, Rinv, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_loo_mats(const double* G, int m, double* E, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_loo_mats, dim3(m), dim3(NT), 0, s, G, m, E);
+  return hipGetLastError();
+}
+
+}  // namespace tto

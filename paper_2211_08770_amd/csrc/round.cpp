@@ -1,0 +1,701 @@
+// Batched TT-round (Section 2 of the paper; the two-sweep rounding it cites).
+//
+// All jobs of a batch advance in lock step: every launch gathers the tasks
+// of all jobs that are at the same step, so uneven jobs (different order,
+// mode sizes, ranks and number of sum components) share launches.
+//
+//   right-to-left, core k = d-1..1:
+//     Y_k   = column-major view (n_k s_{k+1}) x R_k of the current core k
+//     Y_k   = Q_k R_k      (TSQR: Householder tiles, FP64 tree, Q_k kept implicit)
+//     core k-1 <- core k-1 x_3 R_k^T   (block-aware GEMM per sum component)
+//   ||x|| = ||G_0||_F ;  eps = delta / sqrt(d-1) * ||x||
+//   left-to-right, core k = 0..d-2:
+//     C_k   = W_k x_1 Q_k-core            (apply Q_k to [W_k^T; 0])
+//     L(C_k) = Q_M R_M                    (TSQR)
+//     R_M   = U S V^T                     (FP64 one-sided Jacobi; rank t_{k+1} on device)
+//     core k of the result = Q_M [U_t; 0] ; W_{k+1} = S_t V_t^T
+//   last core = W_{d-1} x_1 Q_{d-1}-core
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "host.h"
+
+namespace tto {
+
+namespace {
+
+int npanels(int64_t k) { return (int)((k + QR_NB - 1) / QR_NB); }
+
+}  // namespace
+
+void* Carver::take(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  if (base == nullptr && !measure) return ws_alloc(ctx, bytes);
+  void* p = measure ? nullptr : base + off;
+  off += bytes;
+  if (!measure && off > cap) return nullptr;
+  return p;
+}
+
+int Tree::kr() const {
+  const QrTask& r = lvl.back()[0];
+  return (int)std::min<int64_t>(r.m, N);
+}
+
+const double* Tree::root_R() const { return (const double*)lvl.back()[0].tile; }
+
+bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs, int64_t cs,
+               std::string* why) {
+  t.M = M;
+  t.N = N;
+  t.leaf_dtype = dtype;
+  t.lvl.clear();
+  t.leaf_row0.clear();
+  if (M < 1 || N < 1) {
+    if (why) *why = "empty QR shape";
+    return false;
+  }
+  const size_t elt = elt_size(dtype);
+  int64_t b;
+  if (M <= QR_MAXROWS) {
+    b = M;
+  } else {
+    if (N > QR_MAXROWS / 2) {
+      if (why)
+        *why = "QR of a " + std::to_string(M) + " x " + std::to_string(N) +
+               " unfolding exceeds the supported tile shape (rows > " + std::to_string(QR_MAXROWS) +
+               " needs columns <= " + std::to_string(QR_MAXROWS / 2) + ")";
+      return false;
+    }
+    b = std::min<int64_t>(QR_MAXROWS, std::max<int64_t>(2 * N, 64));
+  }
+  const int64_t nleaves = (M + b - 1) / b;
+  std::vector<QrTask> leaves;
+  leaves.reserve(nleaves);
+  for (int64_t j = 0; j < nleaves; ++j) {
+    const int64_t r0 = j * b;
+    const int64_t m = std::min<int64_t>(b, M - r0);
+    const int64_t k = std::min<int64_t>(m, N);
+    QrTask q;
+    std::memset(&q, 0, sizeof(q));
+    q.src = src ? (const char*)src + (size_t)(r0 * rs) * elt : nullptr;
+    q.src_rs = rs;
+    q.src_cs = cs;
+    q.m = (int32_t)m;
+    q.ncol = (int32_t)N;
+    q.tile = cv.take((size_t)m * N * elt);
+    q.tau = (double*)cv.take((size_t)k * 8);
+    q.tmat = cv.take((size_t)npanels(k) * QR_NB * QR_NB * 8);
+    leaves.push_back(q);
+    t.leaf_row0.push_back(r0);
+  }
+  t.lvl.push_back(std::move(leaves));
+  bool need_node = (dtype == TT_F32);   // R factors always end in an FP64 tile
+  const int64_t g = std::max<int64_t>(2, QR_MAXROWS / N);
+  while (t.lvl.back().size() > 1 || need_node) {
+    need_node = false;
+    const std::vector<QrTask>& prev = t.lvl.back();
+    std::vector<QrTask> nodes;
+    for (size_t i = 0; i < prev.size(); i += (size_t)g) {
+      const int cnt = (int)std::min<size_t>((size_t)g, prev.size() - i);
+      int64_t rows = 0;
+      for (int c = 0; c < cnt; ++c) rows += std::min<int64_t>(prev[i + c].m, N);
+      const int64_t k = std::min<int64_t>(rows, N);
+      QrTask q;
+      std::memset(&q, 0, sizeof(q));
+      q.nchild = cnt;
+      q.child0 = (int32_t)i;
+      q.m = (int32_t)rows;
+      q.ncol = (int32_t)N;
+      q.tile = cv.take((size_t)rows * N * 8);
+      q.tau = (double*)cv.take((size_t)k * 8);
+      q.tmat = cv.take((size_t)npanels(k) * QR_NB * QR_NB * 8);
+      nodes.push_back(q);
+    }
+    t.lvl.push_back(std::move(nodes));
+  }
+  return true;
+}
+
+namespace {
+
+// Apply plan of a tree: out = Q [X; 0], tasks grouped top-down.
+struct ApplyLevel {
+  int tile_dtype;
+  std::vector<ApplyTask> tasks;
+};
+
+size_t apply_work_bytes(const Tree& t, int64_t tcols) {
+  size_t s = 0;
+  for (const auto& l : t.lvl)
+    for (const auto& q : l) s += (((size_t)q.m * tcols * 8) + 255) & ~(size_t)255;
+  return s;
+}
+
+void plan_apply(Carver& cv, const Tree& t, const double* X, int64_t x_ld, int64_t tcols, void* out,
+                int out_dtype, int64_t out_rs, int64_t out_cs, std::vector<ApplyLevel>& plan) {
+  const int L = (int)t.lvl.size();
+  const int64_t N = t.N;
+  std::vector<std::vector<double*>> work(L);
+  for (int l = 0; l < L; ++l)
+    for (size_t i = 0; i < t.lvl[l].size(); ++i) work[l].push_back((double*)cv.take((size_t)t.lvl[l][i].m * tcols * 8));
+  plan.clear();
+  // parent of each task and its row offset inside the parent
+  std::vector<std::vector<std::pair<int, int64_t>>> parent(L);
+  for (int l = 0; l + 1 < L; ++l) {
+    parent[l].assign(t.lvl[l].size(), {0, 0});
+    for (size_t p = 0; p < t.lvl[l + 1].size(); ++p) {
+      const QrTask& nd = t.lvl[l + 1][p];
+      int64_t off = 0;
+      for (int c = 0; c < nd.nchild; ++c) {
+        parent[l][nd.child0 + c] = {(int)p, off};
+        off += std::min<int64_t>(t.lvl[l][nd.child0 + c].m, N);
+      }
+    }
+  }
+  for (int l = L - 1; l >= 0; --l) {
+    ApplyLevel al;
+    al.tile_dtype = (l == 0) ? t.leaf_dtype : TT_F64;
+    for (size_t i = 0; i < t.lvl[l].size(); ++i) {
+      const QrTask& q = t.lvl[l][i];
+      ApplyTask a;
+      std::memset(&a, 0, sizeof(a));
+      a.tile = q.tile;
+      a.tau = q.tau;
+      a.tmat = q.tmat;
+      a.m = q.m;
+      a.ncol = q.ncol;
+      a.kq = (int32_t)std::min<int64_t>(q.m, N);
+      a.t = (int32_t)tcols;
+      a.work = work[l][i];
+      if (l == L - 1) {
+        a.x = X;
+        a.x_ld = x_ld;
+        a.k_in = (int32_t)std::min<int64_t>(q.m, N);
+      } else {
+        const auto& pr = parent[l][i];
+        a.x = work[l + 1][pr.first] + pr.second * tcols;
+        a.x_ld = tcols;
+        a.k_in = (int32_t)std::min<int64_t>(q.m, N);
+      }
+      if (l == 0) {
+        a.to_out = 1;
+        a.out = out ? (char*)out + (size_t)(t.leaf_row0[i] * out_rs) * elt_size(out_dtype) : nullptr;
+        a.out_rs = out_rs;
+        a.out_cs = out_cs;
+      }
+      al.tasks.push_back(a);
+    }
+    plan.push_back(std::move(al));
+  }
+}
+
+struct JobState {
+  int64_t s[TT_MAXD + 1];    // right-to-left ranks
+  int64_t tb[TT_MAXD + 1];   // bounds of the truncated ranks
+  int64_t t[TT_MAXD + 1];    // truncated ranks
+  void* Y[TT_MAXD];
+  Tree rl[TT_MAXD];
+  void* C = nullptr;
+  char* lr_block = nullptr;
+  size_t lr_cap = 0;
+  char* ap_block = nullptr;
+  size_t ap_cap = 0;
+  Tree lr;
+  double *A = nullptr, *acc = nullptr, *sig = nullptr, *wt = nullptr, *ur = nullptr;
+  int32_t* perm = nullptr;
+  double* d_norm = nullptr;
+  int64_t out_off = 0;
+  bool alive = true;
+};
+
+// measure the bytes a tree plan needs
+size_t tree_bytes(int64_t M, int64_t N, int dtype) {
+  Carver cv;
+  cv.measure = true;
+  Tree t;
+  if (!plan_tree(cv, t, M, N, dtype, nullptr, 1, 1, nullptr)) return 0;
+  return cv.off;
+}
+
+size_t tree_apply_bytes(int64_t M, int64_t N, int dtype, int64_t tcols) {
+  Carver cv;
+  cv.measure = true;
+  Tree t;
+  if (!plan_tree(cv, t, M, N, dtype, nullptr, 1, 1, nullptr)) return 0;
+  return apply_work_bytes(t, tcols);
+}
+
+// plan buffers of one job (workspace carving); returns false on unsupported shape
+bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why) {
+  const int d = jb.d;
+  const size_t elt = elt_size(jb.dtype);
+  st.s[d] = 1;
+  for (int k = d - 1; k >= 1; --k) st.s[k] = std::min<int64_t>(jb.R[k], jb.n[k] * st.s[k + 1]);
+  st.s[0] = 1;
+  st.tb[0] = 1;
+  for (int k = 0; k + 1 < d; ++k) {
+    int64_t b = std::min<int64_t>(st.tb[k] * jb.n[k], st.s[k + 1]);
+    if (jb.max_rank > 0) b = std::min<int64_t>(b, jb.max_rank);
+    st.tb[k + 1] = std::max<int64_t>(b, 1);
+  }
+  st.tb[d] = 1;
+  Carver ws;
+  ws.ctx = c;
+  for (int k = d - 1; k >= 1; --k) {
+    const int64_t M = jb.n[k] * st.s[k + 1], N = jb.R[k];
+    st.Y[k] = ws.take((size_t)M * N * elt);
+    if (!plan_tree(ws, st.rl[k], M, N, jb.dtype, st.Y[k], 1, M, why)) return false;
+  }
+  // C buffer, L-to-R tree block, SVD buffers, apply scratch
+  size_t cmax = 0, lrmax = 0, apmax = 0;
+  int64_t smax = 1, tmax = 1;
+  for (int k = 0; k + 1 < d; ++k) {
+    const int64_t M = st.tb[k] * jb.n[k], N = st.s[k + 1];
+    cmax = std::max(cmax, (size_t)(M * N));
+    const size_t tb = tree_bytes(M, N, jb.dtype);
+    if (tb == 0) {
+      Carver tmp;
+      tmp.measure = true;
+      Tree tt;
+      plan_tree(tmp, tt, M, N, jb.dtype, nullptr, 1, 1, why);
+      return false;
+    }
+    lrmax = std::max(lrmax, tb);
+    apmax = std::max(apmax, tree_apply_bytes(M, N, jb.dtype, st.tb[k + 1]));
+    smax = std::max(smax, N);
+    tmax = std::max(tmax, st.tb[k + 1]);
+    if (N > 1024) {
+      if (why) *why = "SVD of a " + std::to_string(N) + "-column R factor exceeds 1024";
+      return false;
+    }
+  }
+  for (int k = 1; k < d; ++k) apmax = std::max(apmax, apply_work_bytes(st.rl[k], st.tb[k]));
+  st.C = ws.take(std::max<size_t>(cmax, 1) * elt);
+  st.lr_cap = lrmax;
+  st.lr_block = (char*)ws.take(std::max<size_t>(lrmax, 256));
+  st.ap_cap = apmax;
+  st.ap_block = (char*)ws.take(std::max<size_t>(apmax, 256));
+  st.A = (double*)ws.take((size_t)smax * smax * 8);
+  st.acc = (double*)ws.take((size_t)smax * smax * 8);
+  st.sig = (double*)ws.take((size_t)smax * 8);
+  st.perm = (int32_t*)ws.take((size_t)smax * 4);
+  st.wt = (double*)ws.take((size_t)smax * tmax * 8);
+  st.ur = (double*)ws.take((size_t)smax * tmax * 8);
+  st.d_norm = (double*)ws.take(64);
+  return true;
+}
+
+tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
+  // level by level from the leaves, all trees together (grouped by dtype)
+  int maxL = 0;
+  for (Tree* t : trees) maxL = std::max(maxL, t->depth());
+  for (int l = 0; l < maxL; ++l) {
+    for (int pass = 0; pass < 2; ++pass) {   // pass 0: FP64 tiles, pass 1: FP32 tiles
+      // group by (child dtype) for nodes: children of level-1 nodes are leaves
+      for (int srcd = 0; srcd < 2; ++srcd) {
+        std::vector<QrTask> tasks;
+        std::vector<QrTask> children;
+        for (Tree* t : trees) {
+          if (l >= t->depth()) continue;
+          const int tile_d = (l == 0) ? t->leaf_dtype : TT_F64;
+          const int src_d = (l == 0) ? t->leaf_dtype : (l == 1 ? t->leaf_dtype : TT_F64);
+          if ((tile_d == TT_F64) != (pass == 0) || src_d != srcd) continue;
+          const int base = (int)children.size();
+          if (l > 0) children.insert(children.end(), t->lvl[l - 1].begin(), t->lvl[l - 1].end());
+          for (QrTask q : t->lvl[l]) {
+            if (l > 0) q.child0 += base;
+            tasks.push_back(q);
+          }
+        }
+        if (tasks.empty()) continue;
+        const QrTask* dt = upload(c, tasks);
+        const QrTask* dc = children.empty() ? nullptr : upload(c, children);
+        if (!dt || (!children.empty() && !dc)) return fail(c, TT_ENOMEM, "task upload");
+        hipError_t e = launch_qr_factor(srcd, pass == 0 ? 0 : 1, dt, dc, (int)tasks.size(), c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "qr_factor");
+      }
+    }
+  }
+  return TT_OK;
+}
+
+tt_status launch_apply_plans(tt_ctx* c, std::vector<std::vector<ApplyLevel>>& plans, int out_dtype) {
+  int maxL = 0;
+  for (auto& p : plans) maxL = std::max(maxL, (int)p.size());
+  for (int depth = 0; depth < maxL; ++depth) {
+    for (int tdt = 0; tdt < 2; ++tdt) {
+      std::vector<ApplyTask> tasks;
+      for (auto& p : plans) {
+        if (depth >= (int)p.size()) continue;
+        if (p[depth].tile_dtype != tdt) continue;
+        tasks.insert(tasks.end(), p[depth].tasks.begin(), p[depth].tasks.end());
+      }
+      if (tasks.empty()) continue;
+      const ApplyTask* dt = upload(c, tasks);
+      if (!dt) return fail(c, TT_ENOMEM, "task upload");
+      hipError_t e = launch_qr_apply(tdt, out_dtype, dt, (int)tasks.size(), c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "qr_apply");
+    }
+  }
+  return TT_OK;
+}
+
+}  // namespace
+
+int64_t round_workspace_bytes(const std::vector<RJob>& jobs) {
+  tt_ctx tmp;
+  tmp.ws = nullptr;
+  tmp.ws_bytes = 0;
+  tmp.ws_off = 0;
+  std::vector<JobState> st(jobs.size());
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    RJob jb = jobs[j];
+    if (jb.d >= 2) {
+      std::string why;
+      if (!plan_job(&tmp, jb, st[j], &why)) return -1;
+    }
+  }
+  return (int64_t)tmp.ws_off + 4096;
+}
+
+tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
+  if (jobs.empty()) return TT_OK;
+  const int dtype = jobs[0].dtype;
+  for (const RJob& jb : jobs)
+    if (jb.dtype != dtype) return fail(c, TT_EINVAL, "all jobs of a batch must share one dtype");
+  const size_t elt = elt_size(dtype);
+  hipStream_t s = c->stream;
+  hipError_t e;
+  const int nj = (int)jobs.size();
+  std::vector<JobState> st(nj);
+
+  // ---------------- plan all buffers before any launch (workspace released on return)
+  struct WsMark {
+    tt_ctx* c;
+    size_t off;
+    ~WsMark() { c->ws_off = off; }
+  } mark{c, c->ws_off};
+  c->ws_overflow = false;
+  for (int j = 0; j < nj; ++j) {
+    RJob& jb = jobs[j];
+    int64_t need = 0;
+    if (jb.d == 1) {
+      need = jb.n[0];
+    } else {
+      std::string why;
+      if (!plan_job(c, jb, st[j], &why)) return fail(c, TT_ENOTIMPL, why);
+      int64_t b = 0;
+      for (int k = 0; k < jb.d; ++k) b += st[j].tb[k] * jb.n[k] * st[j].tb[k + 1];
+      need = b;
+    }
+    (void)need;
+  }
+  if (c->ws_overflow) {
+    c->required = std::max(c->required, c->ws_off);
+    return fail(c, TT_ECAPACITY, "workspace too small: need " + std::to_string(c->ws_off) + " bytes, have " +
+                                     std::to_string(c->ws_bytes));
+  }
+  int32_t* d_ranks = (int32_t*)dev_scratch(c, (size_t)nj * (TT_MAXD + 1) * 4);
+  int32_t* h_ranks = (int32_t*)c->pin.alloc((size_t)nj * (TT_MAXD + 1) * 4);
+  double* h_norms = (double*)c->pin.alloc((size_t)nj * 8);
+  if (!d_ranks || !h_ranks || !h_norms) return fail(c, TT_ENOMEM, "small buffers");
+
+  // ---------------- order-1 jobs: the sum itself (components accumulated in order)
+  {
+    size_t maxc = 0;
+    for (int j = 0; j < nj; ++j) {
+      RJob& jb = jobs[j];
+      if (jb.d != 1) continue;
+      st[j].d_norm = (double*)dev_scratch(c, 8);
+      if (jb.out->capacity < jb.n[0]) jb.status = TT_ECAPACITY;
+      else maxc = std::max(maxc, jb.comps.size());
+    }
+    for (size_t ci = 0; ci < maxc; ++ci) {
+      std::vector<CopySeg> g;
+      for (int j = 0; j < nj; ++j) {
+        RJob& jb = jobs[j];
+        if (jb.d != 1 || jb.status != TT_OK || ci >= jb.comps.size()) continue;
+        CopySeg sg;
+        sg.src = jb.comps[ci].data;
+        sg.dst = jb.out->data;
+        sg.count = jb.n[0];
+        sg.coef = jb.comps[ci].coef;
+        sg.accumulate = ci > 0;
+        g.push_back(sg);
+      }
+      if (g.empty()) continue;
+      const CopySeg* dg = upload(c, g);
+      if ((e = launch_copy_segs(dtype, dg, (int)g.size(), s)) != hipSuccess) return hip_fail(c, e, "copy");
+    }
+    for (int j = 0; j < nj; ++j) {
+      RJob& jb = jobs[j];
+      if (jb.d != 1 || jb.status != TT_OK) continue;
+      if ((e = launch_sumsq(dtype, jb.out->data, jb.n[0], st[j].d_norm, s)) != hipSuccess)
+        return hip_fail(c, e, "sumsq");
+    }
+  }
+
+  // ---------------- right-to-left sweep
+  {
+    std::vector<CopySeg> segs;
+    for (int j = 0; j < nj; ++j) {
+      RJob& jb = jobs[j];
+      if (jb.d < 2) continue;
+      const int k = jb.d - 1;
+      for (size_t ci = 0; ci < jb.comps.size(); ++ci) {
+        const Comp& cp = jb.comps[ci];
+        CopySeg sg;
+        sg.src = cp.data + (size_t)cp.core_off[k] * elt;
+        sg.dst = (char*)st[j].Y[k] + (size_t)(jb.roff[ci * (jb.d + 1) + k] * jb.n[k]) * elt;
+        sg.count = cp.r[k] * jb.n[k];
+        sg.coef = 1.0;
+        sg.accumulate = 0;
+        segs.push_back(sg);
+      }
+    }
+    if (!segs.empty()) {
+      const CopySeg* dg = upload(c, segs);
+      if ((e = launch_copy_segs(dtype, dg, (int)segs.size(), s)) != hipSuccess) return hip_fail(c, e, "gather");
+    }
+  }
+  int maxd = 0;
+  for (const RJob& jb : jobs) maxd = std::max(maxd, jb.d);
+  for (int step = 0; step + 1 < maxd; ++step) {
+    std::vector<Tree*> trees;
+    std::vector<int> act;
+    for (int j = 0; j < nj; ++j) {
+      const int k = jobs[j].d - 1 - step;
+      if (jobs[j].d >= 2 && k >= 1) {
+        trees.push_back(&st[j].rl[k]);
+        act.push_back(j);
+      }
+    }
+    if (act.empty()) continue;
+    tt_status rs = launch_levels_factor(c, trees);
+    if (rs != TT_OK) return rs;
+    // contraction into core k-1
+    std::vector<GemmTask> gt;
+    std::vector<GemmPart> gp;
+    int max_m = 0, max_n = 0;
+    for (int j : act) {
+      RJob& jb = jobs[j];
+      JobState& js = st[j];
+      const int k = jb.d - 1 - step;
+      const Tree& tr = js.rl[k];
+      const int D = jb.d + 1;
+      if (k - 1 >= 1) {
+        for (size_t ci = 0; ci < jb.comps.size(); ++ci) {
+          const Comp& cp = jb.comps[ci];
+          GemmTask g;
+          std::memset(&g, 0, sizeof(g));
+          g.M = (int32_t)(cp.r[k - 1] * jb.n[k - 1]);
+          g.N = (int32_t)js.s[k];
+          g.part0 = (int32_t)gp.size();
+          g.nparts = 1;
+          g.B = tr.root_R();
+          g.b_ld = tr.N;
+          g.C = (char*)js.Y[k - 1] + (size_t)(jb.roff[ci * D + (k - 1)] * jb.n[k - 1] * js.s[k]) * elt;
+          g.c_ld = js.s[k];
+          GemmPart p;
+          p.A = cp.data + (size_t)cp.core_off[k - 1] * elt;
+          p.K = (int32_t)cp.r[k];
+          p.b_off = (int32_t)jb.roff[ci * D + k];
+          p.coef = 1.0;
+          gp.push_back(p);
+          gt.push_back(g);
+          max_m = std::max(max_m, g.M);
+          max_n = std::max(max_n, g.N);
+        }
+      } else {
+        GemmTask g;
+        std::memset(&g, 0, sizeof(g));
+        g.M = (int32_t)jb.n[0];
+        g.N = (int32_t)js.s[1];
+        g.part0 = (int32_t)gp.size();
+        g.nparts = (int32_t)jb.comps.size();
+        g.B = tr.root_R();
+        g.b_ld = tr.N;
+        g.C = js.C;
+        g.c_ld = js.s[1];
+        for (size_t ci = 0; ci < jb.comps.size(); ++ci) {
+          const Comp& cp = jb.comps[ci];
+          GemmPart p;
+          p.A = cp.data + (size_t)cp.core_off[0] * elt;
+          p.K = (int32_t)cp.r[1];
+          p.b_off = (int32_t)jb.roff[ci * D + 1];
+          p.coef = cp.coef;
+          gp.push_back(p);
+        }
+        gt.push_back(g);
+        max_m = std::max(max_m, g.M);
+        max_n = std::max(max_n, g.N);
+      }
+    }
+    const GemmTask* dgt = upload(c, gt);
+    const GemmPart* dgp = upload(c, gp);
+    if ((e = launch_gemm(dtype, dgt, dgp, (int)gt.size(), max_m, max_n, s)) != hipSuccess)
+      return hip_fail(c, e, "contraction");
+  }
+
+  // ---------------- norms
+  for (int j = 0; j < nj; ++j) {
+    RJob& jb = jobs[j];
+    if (jb.d < 2) continue;
+    if ((e = launch_sumsq(dtype, st[j].C, jb.n[0] * st[j].s[1], st[j].d_norm, s)) != hipSuccess)
+      return hip_fail(c, e, "norm");
+  }
+
+  // ---------------- left-to-right sweep
+  for (int j = 0; j < nj; ++j) {
+    st[j].t[0] = 1;
+    st[j].out_off = 0;
+    st[j].alive = jobs[j].d >= 2 && jobs[j].status == TT_OK;
+  }
+  for (int k = 0; k + 1 < maxd; ++k) {
+    std::vector<int> act;
+    for (int j = 0; j < nj; ++j)
+      if (st[j].alive && k + 1 < jobs[j].d) act.push_back(j);
+    if (act.empty()) break;
+    // (1) C_k = Q_k [W_k^T; 0]
+    if (k >= 1) {
+      std::vector<std::vector<ApplyLevel>> plans;
+      for (int j : act) {
+        RJob& jb = jobs[j];
+        JobState& js = st[j];
+        Carver cv;
+        cv.base = js.ap_block;
+        cv.cap = js.ap_cap;
+        std::vector<ApplyLevel> pl;
+        plan_apply(cv, js.rl[k], js.wt, js.t[k], js.t[k], js.C, jb.dtype, 1, jb.n[k] * js.s[k + 1], pl);
+        if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "apply scratch");
+        plans.push_back(std::move(pl));
+      }
+      tt_status rs = launch_apply_plans(c, plans, dtype);
+      if (rs != TT_OK) return rs;
+    }
+    // (2) TSQR of L(C_k)
+    std::vector<Tree*> trees;
+    for (int j : act) {
+      RJob& jb = jobs[j];
+      JobState& js = st[j];
+      Carver cv;
+      cv.base = js.lr_block;
+      cv.cap = js.lr_cap;
+      std::string why;
+      const int64_t M = js.t[k] * jb.n[k], N = js.s[k + 1];
+      if (!plan_tree(cv, js.lr, M, N, jb.dtype, js.C, N, 1, &why)) return fail(c, TT_ENOTIMPL, why);
+      if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "left-to-right tree block");
+      trees.push_back(&js.lr);
+    }
+    tt_status rs = launch_levels_factor(c, trees);
+    if (rs != TT_OK) return rs;
+    // (3) SVD + rank
+    std::vector<SvdTask> sv;
+    for (int j : act) {
+      RJob& jb = jobs[j];
+      JobState& js = st[j];
+      SvdTask t;
+      std::memset(&t, 0, sizeof(t));
+      t.R = js.lr.root_R();
+      t.r_ld = js.lr.N;
+      t.kr = js.lr.kr();
+      t.ncol = (int32_t)js.lr.N;
+      t.upper = 1;
+      t.A = js.A;
+      t.acc = js.acc;
+      t.sigma = js.sig;
+      t.perm = js.perm;
+      t.norm = js.d_norm;
+      t.delta_scaled = jb.delta / std::sqrt((double)(jb.d - 1));
+      t.max_rank = jb.max_rank;
+      t.rank_out = d_ranks + (size_t)j * (TT_MAXD + 1) + (k + 1);
+      t.wt = js.wt;
+      t.ur = js.ur;
+      t.info = nullptr;
+      sv.push_back(t);
+    }
+    const SvdTask* dsv = upload(c, sv);
+    if ((e = launch_svd(dsv, (int)sv.size(), s)) != hipSuccess) return hip_fail(c, e, "svd");
+    if ((e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=
+        hipSuccess)
+      return hip_fail(c, e, "rank readback");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "sync");
+    // (4) output core k = Q_M [U_t; 0]
+    std::vector<std::vector<ApplyLevel>> plans;
+    for (int j : act) {
+      RJob& jb = jobs[j];
+      JobState& js = st[j];
+      const int64_t tk1 = h_ranks[(size_t)j * (TT_MAXD + 1) + (k + 1)];
+      if (tk1 < 1 || tk1 > js.tb[k + 1]) return fail(c, TT_EDEVICE, "rank out of range");
+      js.t[k + 1] = tk1;
+      const int64_t sz = js.t[k] * jb.n[k] * tk1;
+      if (js.out_off + sz > jb.out->capacity) {
+        jb.status = TT_ECAPACITY;
+        js.alive = false;
+        continue;
+      }
+      Carver cv;
+      cv.base = js.ap_block;
+      cv.cap = js.ap_cap;
+      std::vector<ApplyLevel> pl;
+      plan_apply(cv, js.lr, js.ur, tk1, tk1, (char*)jb.out->data + (size_t)js.out_off * elt, jb.dtype, tk1, 1, pl);
+      if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "apply scratch");
+      plans.push_back(std::move(pl));
+      js.out_off += sz;
+    }
+    rs = launch_apply_plans(c, plans, dtype);
+    if (rs != TT_OK) return rs;
+  }
+  // ---------------- last core
+  {
+    std::vector<std::vector<ApplyLevel>> plans;
+    for (int j = 0; j < nj; ++j) {
+      RJob& jb = jobs[j];
+      JobState& js = st[j];
+      if (!js.alive) continue;
+      const int k = jb.d - 1;
+      const int64_t sz = js.t[k] * jb.n[k];
+      if (js.out_off + sz > jb.out->capacity) {
+        jb.status = TT_ECAPACITY;
+        js.alive = false;
+        continue;
+      }
+      Carver cv;
+      cv.base = js.ap_block;
+      cv.cap = js.ap_cap;
+      std::vector<ApplyLevel> pl;
+      plan_apply(cv, js.rl[k], js.wt, js.t[k], js.t[k], (char*)jb.out->data + (size_t)js.out_off * elt, jb.dtype, 1,
+                 jb.n[k], pl);
+      if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "apply scratch");
+      plans.push_back(std::move(pl));
+      js.out_off += sz;
+    }
+    tt_status rs = launch_apply_plans(c, plans, dtype);
+    if (rs != TT_OK) return rs;
+  }
+  // ---------------- norms back, ranks out
+  for (int j = 0; j < nj; ++j) {
+    if (jobs[j].status != TT_OK || !st[j].d_norm) continue;
+    if ((e = hipMemcpyAsync(h_norms + j, st[j].d_norm, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return hip_fail(c, e, "norm readback");
+  }
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "sync");
+  for (int j = 0; j < nj; ++j) {
+    RJob& jb = jobs[j];
+    if (jb.status != TT_OK) continue;
+    jb.norm = h_norms[j];
+    if (jb.d == 1) {
+      jb.out->r[0] = 1;
+      jb.out->r[1] = 1;
+      continue;
+    }
+    jb.out->r[0] = 1;
+    for (int k = 1; k < jb.d; ++k) jb.out->r[k] = st[j].t[k];
+    jb.out->r[jb.d] = 1;
+  }
+  return TT_OK;
+}
+
+}  // namespace tto

@@ -1,0 +1,375 @@
+"""Thin Python binding of libttortho (argument marshalling only).
+
+Every operation is one call into the C ABI declared in ``include/ttortho.h``;
+PyTorch provides device memory and the stream.  The library is loaded on
+first use and its absence is an error: there is no fallback path.
+
+TT-vectors are :class:`TT` objects: one packed 1-D device tensor holding the
+cores row-major ``[r_k][n_k][r_{k+1}]`` back to back, plus mode sizes and ranks.
+A lazy sum is a list of ``(coef, TT)`` pairs.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+import torch
+
+__all__ = ["TT", "dot", "dot_batched", "axpy", "round", "round_batched", "orthogonalize", "loo",
+           "TTError", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
+
+TT_MAXD = 64
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBNAME = "libttortho.so"
+
+SCHEMES = {"cgs": 0, "mgs": 1, "cgs2": 2, "mgs2": 3, "gram": 4}
+_F64, _F32 = 0, 1
+_STATUS = {0: "TT_OK", -1: "TT_EINVAL", -2: "TT_ENOMEM", -3: "TT_ECAPACITY", -4: "TT_ENOTSPD",
+           -5: "TT_EBREAKDOWN", -6: "TT_ENONFINITE", -7: "TT_EDEVICE", -8: "TT_EGUARD", -9: "TT_ENOTIMPL"}
+
+
+class TTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = _STATUS.get(status, str(status))
+
+
+class _Vec(C.Structure):
+    _fields_ = [("d", C.c_int32), ("dtype", C.c_int32), ("n", C.c_int64 * TT_MAXD),
+                ("r", C.c_int64 * (TT_MAXD + 1)), ("data", C.c_void_p), ("capacity", C.c_int64)]
+
+
+class _Sum(C.Structure):
+    _fields_ = [("ncomp", C.c_int32), ("coef", C.POINTER(C.c_double)), ("comp", C.POINTER(_Vec))]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("rounds", C.c_int32), ("m_reached", C.c_int32), ("max_pre_rank", C.c_int32),
+                ("max_post_rank", C.c_int32)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, _LIBNAME)
+
+
+def _load():
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with `python -m paper_2211_08770_amd.build`")
+        lib = C.CDLL(path)
+        P = C.c_void_p
+        lib.tt_ctx_create.argtypes = [C.POINTER(P), C.c_int, P]
+        lib.tt_ctx_create.restype = C.c_int
+        lib.tt_ctx_destroy.argtypes = [P]
+        lib.tt_ctx_set_workspace.argtypes = [P, P, C.c_size_t]
+        lib.tt_ctx_set_workspace.restype = C.c_int
+        lib.tt_ctx_required_bytes.argtypes = [P]
+        lib.tt_ctx_required_bytes.restype = C.c_size_t
+        lib.tt_last_error.argtypes = [P]
+        lib.tt_last_error.restype = C.c_char_p
+        lib.tt_status_str.argtypes = [C.c_int]
+        lib.tt_status_str.restype = C.c_char_p
+        lib.tt_dot_batched.argtypes = [P, C.c_int32, C.POINTER(_Sum), C.POINTER(_Sum), C.POINTER(C.c_double)]
+        lib.tt_dot_batched.restype = C.c_int
+        lib.tt_dot.argtypes = [P, C.POINTER(_Sum), C.POINTER(_Sum), C.POINTER(C.c_double)]
+        lib.tt_dot.restype = C.c_int
+        lib.tt_axpy.argtypes = [P, C.c_double, C.POINTER(_Vec), C.POINTER(_Vec), C.POINTER(_Vec)]
+        lib.tt_axpy.restype = C.c_int
+        lib.tt_round.argtypes = [P, C.POINTER(_Sum), C.c_double, C.c_int64, C.POINTER(_Vec), C.POINTER(C.c_double)]
+        lib.tt_round.restype = C.c_int
+        lib.tt_round_batched.argtypes = [P, C.c_int32, C.POINTER(_Sum), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_int64), C.POINTER(_Vec), C.POINTER(C.c_int)]
+        lib.tt_round_batched.restype = C.c_int
+        lib.tt_round_out_capacity.argtypes = [C.POINTER(_Sum)]
+        lib.tt_round_out_capacity.restype = C.c_int64
+        lib.tt_round_workspace_bytes.argtypes = [C.POINTER(_Sum)]
+        lib.tt_round_workspace_bytes.restype = C.c_int64
+        lib.tt_orthogonalize.argtypes = [P, C.c_int, C.c_int32, C.POINTER(_Sum), C.c_double, C.c_int64,
+                                         C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                         C.POINTER(_Stats)]
+        lib.tt_orthogonalize.restype = C.c_int
+        lib.tt_loo.argtypes = [P, C.c_int32, C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        lib.tt_loo.restype = C.c_int
+        _lib = lib
+        return lib
+
+
+class TT:
+    """A TT-vector in packed device storage (cores row-major, back to back)."""
+
+    def __init__(self, data: torch.Tensor, ns, ranks):
+        self.data = data
+        self.n = [int(v) for v in ns]
+        self.r = [int(v) for v in ranks]
+        if len(self.r) != len(self.n) + 1:
+            raise ValueError("ranks must have d+1 entries")
+
+    @property
+    def d(self):
+        return len(self.n)
+
+    @property
+    def dtype(self):
+        return self.data.dtype
+
+    def size(self):
+        return sum(self.r[k] * self.n[k] * self.r[k + 1] for k in range(self.d))
+
+    @classmethod
+    def from_cores(cls, cores, device="cuda", dtype=None):
+        ts = [torch.as_tensor(c) for c in cores]
+        dt = dtype or ts[0].dtype
+        flat = torch.cat([t.reshape(-1).to(dt) for t in ts]).to(device).contiguous()
+        ns = [t.shape[1] for t in ts]
+        ranks = [ts[0].shape[0]] + [t.shape[2] for t in ts]
+        return cls(flat, ns, ranks)
+
+    def cores(self):
+        out, off = [], 0
+        for k in range(self.d):
+            sz = self.r[k] * self.n[k] * self.r[k + 1]
+            out.append(self.data[off:off + sz].view(self.r[k], self.n[k], self.r[k + 1]))
+            off += sz
+        return out
+
+    def numpy_cores(self):
+        return [c.detach().cpu().numpy() for c in self.cores()]
+
+    def _vec(self) -> _Vec:
+        if self.data.dtype not in (torch.float64, torch.float32):
+            raise TypeError("TT data must be float64 or float32")
+        if not self.data.is_cuda or not self.data.is_contiguous():
+            raise ValueError("TT data must be a contiguous device tensor")
+        v = _Vec()
+        v.d = self.d
+        v.dtype = _F64 if self.data.dtype == torch.float64 else _F32
+        for k, n in enumerate(self.n):
+            v.n[k] = n
+        for k, r in enumerate(self.r):
+            v.r[k] = r
+        v.data = self.data.data_ptr()
+        v.capacity = self.data.numel()
+        return v
+
+
+def _as_terms(x):
+    if isinstance(x, TT):
+        return [(1.0, x)]
+    return [(float(a), t) for a, t in x]
+
+
+class _SumHolder:
+    """Keeps the ctypes arrays of a lazy sum alive for the duration of a call."""
+
+    def __init__(self, x):
+        terms = _as_terms(x)
+        self.tts = [t for _, t in terms]
+        self.coef = (C.c_double * len(terms))(*[a for a, _ in terms])
+        self.vecs = (_Vec * len(terms))(*[t._vec() for t in self.tts])
+        self.s = _Sum(len(terms), self.coef, self.vecs)
+
+
+class _Ctx:
+    def __init__(self, device: int):
+        self.lib = _load()
+        self.device = device
+        h = C.c_void_p()
+        st = self.lib.tt_ctx_create(C.byref(h), device, C.c_void_p(torch.cuda.current_stream(device).cuda_stream))
+        if st != 0:
+            raise TTError(st, "tt_ctx_create failed")
+        self.h = h
+        self.ws = None
+        self.ws_bytes = 0
+
+    def ensure_ws(self, nbytes: int):
+        if nbytes <= self.ws_bytes:
+            return
+        nbytes = int(nbytes * 1.25) + (1 << 20)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+        self.ws_bytes = nbytes
+        st = self.lib.tt_ctx_set_workspace(self.h, C.c_void_p(self.ws.data_ptr()), nbytes)
+        if st != 0:
+            raise TTError(st, "set_workspace failed")
+
+    def check(self, st):
+        if st != 0:
+            raise TTError(st, self.lib.tt_last_error(self.h).decode())
+
+    def call_with_ws(self, fn):
+        """Run fn(); grow the workspace and retry once when it reports TT_ECAPACITY."""
+        for _ in range(4):
+            st = fn()
+            if st == -3:
+                need = int(self.lib.tt_ctx_required_bytes(self.h))
+                if need > self.ws_bytes:
+                    self.ensure_ws(need)
+                    continue
+            self.check(st)
+            return
+        self.check(st)
+
+
+_ctxs = {}
+
+
+def _ctx(device=None) -> _Ctx:
+    dev = torch.cuda.current_device() if device is None else int(device)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    key = (dev, stream)
+    if key not in _ctxs:
+        _ctxs[key] = _Ctx(dev)
+    return _ctxs[key]
+
+
+def _device_of(x):
+    return _as_terms(x)[0][1].data.device.index
+
+
+def dot(x, y) -> float:
+    """<x, y> of two TT-vectors or lazy sums."""
+    return dot_batched([(x, y)])[0]
+
+
+def dot_batched(pairs):
+    if not pairs:
+        return np.zeros(0)
+    ctx = _ctx(_device_of(pairs[0][0]))
+    hx = [_SumHolder(x) for x, _ in pairs]
+    hy = [_SumHolder(y) for _, y in pairs]
+    xs = (_Sum * len(pairs))(*[h.s for h in hx])
+    ys = (_Sum * len(pairs))(*[h.s for h in hy])
+    out = (C.c_double * len(pairs))()
+    ctx.ensure_ws(64 << 20)
+    ctx.call_with_ws(lambda: ctx.lib.tt_dot_batched(ctx.h, len(pairs), xs, ys, out))
+    return np.array(out[:], dtype=np.float64)
+
+
+def axpy(alpha: float, x: TT, y: TT) -> TT:
+    """z = alpha * x + y (materialised TT sum, ranks add)."""
+    ctx = _ctx(x.data.device.index)
+    ranks = [1] + [a + b for a, b in zip(x.r[1:-1], y.r[1:-1])] + [1]
+    size = sum(ranks[k] * x.n[k] * ranks[k + 1] for k in range(x.d))
+    z = TT(torch.empty(size, dtype=x.dtype, device=x.data.device), x.n, ranks)
+    vx, vy, vz = x._vec(), y._vec(), z._vec()
+    ctx.check(ctx.lib.tt_axpy(ctx.h, float(alpha), C.byref(vx), C.byref(vy), C.byref(vz)))
+    z.r = [int(vz.r[k]) for k in range(x.d + 1)]
+    return z
+
+
+def round_out_capacity(x) -> int:
+    h = _SumHolder(x)
+    return int(_load().tt_round_out_capacity(C.byref(h.s)))
+
+
+def round_workspace_bytes(x) -> int:
+    h = _SumHolder(x)
+    return int(_load().tt_round_workspace_bytes(C.byref(h.s)))
+
+
+def _new_out(x):
+    first = _as_terms(x)[0][1]
+    cap = max(round_out_capacity(x), 1)
+    return TT(torch.empty(cap, dtype=first.dtype, device=first.data.device), first.n, [1] * (first.d + 1))
+
+
+def _finish_out(out: TT, v: _Vec):
+    out.r = [int(v.r[k]) for k in range(out.d + 1)]
+    out.data = out.data[: out.size()]
+    return out
+
+
+def round(x, delta: float, max_rank: int = 0, return_norm: bool = False):
+    """TT-round(x, delta): ||x - x~|| <= delta ||x||; x is a TT or a lazy sum."""
+    h = _SumHolder(x)
+    ctx = _ctx(h.tts[0].data.device.index)
+    out = _new_out(x)
+    vo = out._vec()
+    nrm = C.c_double(0.0)
+    ws = int(ctx.lib.tt_round_workspace_bytes(C.byref(h.s)))
+    if ws < 0:
+        ctx.check(-9)
+    ctx.ensure_ws(ws)
+    ctx.call_with_ws(lambda: ctx.lib.tt_round(ctx.h, C.byref(h.s), float(delta), int(max_rank), C.byref(vo),
+                                              C.byref(nrm)))
+    out = _finish_out(out, vo)
+    return (out, nrm.value) if return_norm else out
+
+
+def round_batched(xs, deltas, max_ranks=None):
+    """Independent roundings of several TTs / lazy sums in shared launches."""
+    n = len(xs)
+    hs = [_SumHolder(x) for x in xs]
+    ctx = _ctx(hs[0].tts[0].data.device.index)
+    outs = [_new_out(x) for x in xs]
+    vos = (_Vec * n)(*[o._vec() for o in outs])
+    sums = (_Sum * n)(*[h.s for h in hs])
+    if np.isscalar(deltas):
+        deltas = [deltas] * n
+    dl = (C.c_double * n)(*[float(v) for v in deltas])
+    mr = (C.c_int64 * n)(*([int(v) for v in max_ranks] if max_ranks is not None else [0] * n))
+    st = (C.c_int * n)()
+    ws = sum(max(int(ctx.lib.tt_round_workspace_bytes(C.byref(h.s))), 0) for h in hs)
+    ctx.ensure_ws(ws)
+    ctx.call_with_ws(lambda: ctx.lib.tt_round_batched(ctx.h, n, sums, dl, mr, vos, st))
+    return [_finish_out(o, vos[i]) for i, o in enumerate(outs)]
+
+
+def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: bool = True, q_capacity=None):
+    """Q, R (and the LOO curve) of the TT vectors / lazy sums A (Algorithms 1-5)."""
+    m = len(A)
+    hs = [_SumHolder(a) for a in A]
+    first = hs[0].tts[0]
+    ctx = _ctx(first.data.device.index)
+    sums = (_Sum * m)(*[h.s for h in hs])
+    # output capacity: rank caps of the order/mode sizes, bounded by the pre-round ranks
+    if q_capacity is None:
+        caps = [1]
+        for k in range(1, first.d):
+            caps.append(min(int(np.prod(first.n[:k], dtype=object)), int(np.prod(first.n[k:], dtype=object))))
+        caps.append(1)
+        q_capacity = sum(caps[k] * first.n[k] * caps[k + 1] for k in range(first.d))
+        # the pre-round rank of any rounded vector bounds its output ranks
+        tot = [1] + [0] * (first.d - 1) + [1]
+        for h in hs:
+            for t in h.tts:
+                for k in range(1, first.d):
+                    tot[k] += t.r[k]
+        # q ranks never exceed min(caps, sum of all input ranks + previous q's) -> use caps
+        q_capacity = int(min(q_capacity, 1 << 31))
+    Q = [TT(torch.empty(q_capacity, dtype=first.dtype, device=first.data.device), first.n, [1] * (first.d + 1))
+         for _ in range(m)]
+    vq = (_Vec * m)(*[q._vec() for q in Q])
+    R = (C.c_double * (m * m))()
+    L = (C.c_double * m)()
+    stats = _Stats()
+    ctx.ensure_ws(256 << 20)
+    ctx.call_with_ws(lambda: ctx.lib.tt_orthogonalize(ctx.h, SCHEMES[scheme], m, sums, float(delta),
+                                                      int(rank_guard), vq, R, L if with_loo else None,
+                                                      C.byref(stats)))
+    Q = [_finish_out(q, vq[i]) for i, q in enumerate(Q)]
+    Rm = np.array(R[:], dtype=np.float64).reshape(m, m).T.copy()   # column-major -> R[j, i]
+    st = {"rounds": stats.rounds, "m_reached": stats.m_reached, "max_pre_rank": stats.max_pre_rank,
+          "max_post_rank": stats.max_post_rank}
+    return Q, Rm, (np.array(L[:]) if with_loo else None), st
+
+
+def loo(Q):
+    """||I_k - Q_k^T Q_k||_2 for k = 1..m and the Gram matrix Q^T Q."""
+    m = len(Q)
+    ctx = _ctx(Q[0].data.device.index)
+    vq = (_Vec * m)(*[q._vec() for q in Q])
+    out = (C.c_double * m)()
+    G = (C.c_double * (m * m))()
+    ctx.ensure_ws(64 << 20)
+    ctx.call_with_ws(lambda: ctx.lib.tt_loo(ctx.h, m, vq, out, G))
+    return np.array(out[:]), np.array(G[:]).reshape(m, m)

@@ -1,0 +1,36 @@
+"""Batched uneven roundings: each job equals its oracle result and is bitwise
+identical to the same job rounded alone (tile choices depend only on the job)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2211_08770_amd import synth
+from gpu_util import need_gpu, dev_tt, host_cores, diff_norm
+
+pytestmark = pytest.mark.gpu
+
+
+def small_uneven_jobs(seed, njobs):
+    return synth.uneven_jobs(seed=seed, njobs=njobs, d_range=(2, 6), n_choices=(3, 4, 8), r_range=(2, 20),
+                             dtype=np.float64)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_uneven_matches_oracle_and_singles(dtype):
+    tt = need_gpu()
+    delta = 1e-5
+    jobs = small_uneven_jobs(30001, 12)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    cores = [[c.astype(npdt) for c in j[0]] for j in jobs]
+    xs = [dev_tt(c, dtype) for c in cores]
+    outs = tt.round_batched(xs, delta)
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    for c, o, x in zip(cores, outs, xs):
+        c64 = [a.astype(np.float64) for a in c]
+        ref = oracle.tt_round(c64, delta)
+        nx = oracle.tt_norm(c64)
+        assert o.r == oracle.tt_ranks(ref)
+        assert diff_norm(host_cores(o), ref) <= tol * nx
+        single = tt.round(x, delta)
+        assert single.r == o.r and torch.equal(single.data, o.data)

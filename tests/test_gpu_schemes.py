@@ -1,0 +1,102 @@
+"""GPU orthogonalization schemes (Algorithms 1-5) against the oracle.
+
+Compared: R entry by entry, each q_i by the norm of the TT difference, and
+the loss-of-orthogonality curve (within 2x once both are floored at
+10 * k * u).  Tolerances grow with kappa(A_k)^p (p = 1 for MGS/MGS2, 2 for
+CGS/CGS2/Gram), as the schemes' own error propagation does.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from inputs import conditioned_inputs
+from gpu_util import need_gpu, dev_sum, host_cores, diff_norm
+
+pytestmark = pytest.mark.gpu
+
+POW = {"cgs": 2, "mgs": 1, "cgs2": 1, "mgs2": 1, "gram": 2}
+
+
+def run_both(scheme, X, delta, dtype=torch.float64):
+    tt = need_gpu()
+    ref = oracle.orthogonalize(scheme, X, delta)
+    ref_loo = oracle.loo_curve(ref.Q)
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    A = [dev_sum([(a, [c.astype(npdt) for c in x]) for a, x in s], dtype) for s in X]
+    Q, R, loo, st = tt.orthogonalize(scheme, A, delta)
+    return ref, ref_loo, Q, R, loo, st
+
+
+def compare(scheme, X, M, delta, ref, ref_loo, Q, R, loo, st, base_tol):
+    m = len(X)
+    assert st["rounds"] == ref.rounds
+    assert st["m_reached"] == m
+    for k in range(1, m + 1):
+        kap = math.sqrt(np.linalg.cond(M[:k, :k]))
+        tol = base_tol * max(1.0, kap ** POW[scheme])
+        if tol > 1e-3:
+            break
+        i = k - 1
+        assert np.allclose(R[: i + 1, i], ref.R[: i + 1, i], rtol=0, atol=tol * max(1.0, np.abs(ref.R[:, i]).max())), (scheme, i)
+        qd = diff_norm(host_cores(Q[i]), ref.Q[i]) / max(oracle.tt_norm(ref.Q[i]), 1e-300)
+        assert qd <= tol, (scheme, i, qd)
+    floor = lambda v, k: max(v, 10 * k * 1.1e-16)
+    for k in range(1, m + 1):
+        a, b = floor(loo[k - 1], k), floor(ref_loo[k - 1], k)
+        assert a <= 2 * b and b <= 2 * a, (scheme, k, loo[k - 1], ref_loo[k - 1])
+
+
+@pytest.mark.parametrize("scheme", ["cgs", "mgs", "cgs2", "mgs2", "gram"])
+def test_schemes_small(scheme):
+    X, C, M = conditioned_inputs(500, 6, 3, 5, 2, 1e4)
+    ref, ref_loo, Q, R, loo, st = run_both(scheme, X, 1e-8)
+    compare(scheme, X, M, 1e-8, ref, ref_loo, Q, R, loo, st, 1e-10)
+
+
+def test_mgs_twenty_vectors_order4_gram_condition_1e6():
+    # m = 20 TT-vectors of order 4, n = 8, generating ranks 3, cond(Gram) = 1e6, delta = 1e-6
+    X, C, M = conditioned_inputs(10000, 20, 4, 8, 3, 1e6)
+    ref, ref_loo, Q, R, loo, st = run_both("mgs", X, 1e-6)
+    compare("mgs", X, M, 1e-6, ref, ref_loo, Q, R, loo, st, 1e-9)
+
+
+def test_gram_reports_not_spd():
+    tt = need_gpu()
+    X, C, M = conditioned_inputs(510, 3, 3, 4, 2, 1e2)
+    X.append(list(X[1]))
+    A = [dev_sum(s) for s in X]
+    with pytest.raises(tt.TTError) as ei:
+        tt.orthogonalize("gram", A, 1e-8)
+    assert ei.value.status == "TT_ENOTSPD"
+
+
+def test_breakdown_on_dependent_input():
+    tt = need_gpu()
+    X, C, M = conditioned_inputs(520, 3, 3, 4, 2, 1e2)
+    X.append(list(X[0]))
+    A = [dev_sum(s) for s in X]
+    with pytest.raises(tt.TTError):
+        tt.orthogonalize("cgs", A, 0.0)
+
+
+def test_rank_guard_stops_with_status():
+    tt = need_gpu()
+    X, C, M = conditioned_inputs(530, 5, 3, 5, 2, 1e3)
+    A = [dev_sum(s) for s in X]
+    with pytest.raises(tt.TTError) as ei:
+        tt.orthogonalize("gram", A, 1e-8, rank_guard=5)
+    assert ei.value.status == "TT_EGUARD"
+
+
+def test_loo_entry_point_matches_oracle():
+    tt = need_gpu()
+    X, C, M = conditioned_inputs(540, 5, 3, 5, 2, 1e6)
+    ref = oracle.cgs(X, 1e-4)
+    from gpu_util import dev_tt
+    Q = [dev_tt(q) for q in ref.Q]
+    loo, G = tt.loo(Q)
+    assert np.allclose(G, oracle.gram_of(ref.Q), atol=1e-13)
+    assert np.allclose(loo, oracle.loo_curve(ref.Q), rtol=1e-8, atol=1e-14)
