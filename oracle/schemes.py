@@ -15,7 +15,9 @@ Readings taken where the paper is loose:
   * in CGS2/MGS2 R_1 has a zero diagonal and R[i, i] = R_2[i, i] = ||p_2||;
   * Gram forms q_i from column i of R^{-1}: q_i = sum_{k<=i} R^{-1}[k, i] a_k
     (the equation of Section 3.2; the algorithm's R^{-1}(i, j) would read the
-    zero lower triangle) and q_i is not renormalised after rounding.
+    zero lower triangle) and q_i is not renormalised after rounding;
+  * the Gram matrix counts as numerically singular (Cholesky undefined, the
+    remark of Section 3.2) when a pivot L_jj^2 falls to m u G_jj or below.
 """
 from __future__ import annotations
 
@@ -149,10 +151,17 @@ def gram(A, delta):
     m = len(A)
     mats = [tt_sum(a) for a in A]
     G = gram_of(mats)
+    # The Cholesky factorisation is undefined once G is numerically singular
+    # (Section 3.2, remark): a pivot L_jj^2 <= m u G_jj is treated as a failure.
     try:
         L = np.linalg.cholesky(G)
     except np.linalg.LinAlgError as e:
         raise GramBreakdown(str(e)) from e
+    u = np.finfo(np.float64).eps / 2
+    piv = np.diag(L) ** 2
+    bad = np.nonzero(piv <= m * u * np.diag(G))[0]
+    if bad.size:
+        raise GramBreakdown(f"numerically singular Gram matrix at pivot {int(bad[0]) + 1}")
     R = L.T.copy()
     Rinv = sla.solve_triangular(R, np.eye(m), lower=False)
     res = OrthoResult(Q=[], R=R)
