@@ -99,6 +99,17 @@ void tt_ctx_destroy(tt_ctx* ctx);
 tt_status tt_ctx_set_workspace(tt_ctx* ctx, void* workspace, size_t bytes);
 size_t tt_ctx_required_bytes(const tt_ctx* ctx);
 
+/* Per-launch timing of this context (tracing support).  When on, every kernel
+ * launch is bracketed by HIP events on the context's stream and, per kind of
+ * kernel (0 qr_factor_leaf, 1 qr_factor_node, 2 qr_apply, 3 svd_jacobi,
+ * 4 contraction_gemm, 5 tt_dot, 6 other), the elapsed milliseconds, launch
+ * count and algorithmic flops and bytes of the launched work are summed.
+ * tt_ctx_set_profiling resets the sums. */
+tt_status tt_ctx_set_profiling(tt_ctx* ctx, int on);
+tt_status tt_ctx_profile(const tt_ctx* ctx, int kind, double* ms, int64_t* launches, double* flops,
+                         double* bytes);
+const char* tt_profile_kind_name(int kind);
+
 /* Human-readable status and last error message of this context. */
 const char* tt_status_str(tt_status s);
 const char* tt_last_error(const tt_ctx* ctx);

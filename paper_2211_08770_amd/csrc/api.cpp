@@ -89,6 +89,51 @@ void* upload_bytes(tt_ctx* c, const void* src, size_t bytes) {
 
 void* dev_scratch(tt_ctx* c, size_t bytes) { return c->dev.alloc(bytes); }
 
+static hipEvent_t prof_event(tt_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int prof_begin(tt_ctx* c, int kind, double flops, double bytes) {
+  if (!c->prof) return -1;
+  ProfRec r;
+  r.kind = kind;
+  r.flops = flops;
+  r.bytes = bytes;
+  r.start = prof_event(c);
+  r.stop = prof_event(c);
+  if (!r.start || !r.stop) return -1;
+  if (hipEventRecord(r.start, c->stream) != hipSuccess) return -1;
+  c->prof_open.push_back(r);
+  return (int)c->prof_open.size() - 1;
+}
+
+void prof_end(tt_ctx* c, int rec) {
+  if (rec < 0 || !c->prof) return;
+  (void)hipEventRecord(c->prof_open[rec].stop, c->stream);
+}
+
+void prof_collect(tt_ctx* c) {
+  for (ProfRec& r : c->prof_open) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.stop) == hipSuccess && hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+      c->prof_ms[r.kind] += ms;
+      c->prof_flops[r.kind] += r.flops;
+      c->prof_bytes[r.kind] += r.bytes;
+      c->prof_cnt[r.kind] += 1;
+    }
+    c->prof_pool.push_back(r.start);
+    c->prof_pool.push_back(r.stop);
+  }
+  c->prof_open.clear();
+}
+
 }  // namespace tto
 
 namespace {
@@ -103,6 +148,7 @@ struct CallScope {
   }
   ~CallScope() {
     (void)hipStreamSynchronize(c->stream);
+    prof_collect(c);
     c->dev.reset();
     c->pin.reset();
   }
@@ -306,7 +352,18 @@ tt_status dot_pairs_idx(tt_ctx* c, int npairs, const tt_sum* xs, const tt_sum* y
     }
     const DotTask* dt = upload(c, tasks);
     if (!dt) return fail(c, TT_ENOMEM, "dot tasks");
+    double fl = 0.0, by = 0.0;
+    for (size_t i = i0; i < i1; ++i) {
+      const tt_vec* x = pairs[i].x;
+      const tt_vec* y = pairs[i].y;
+      for (int k = 0; k < x->d; ++k) {
+        fl += 2.0 * x->r[k] * x->n[k] * y->r[k + 1] * (double)(y->r[k] + x->r[k + 1]);
+        by += (double)elt * (x->r[k] * x->n[k] * x->r[k + 1] + y->r[k] * y->n[k] * y->r[k + 1]);
+      }
+    }
+    const int pr = prof_begin(c, PK_DOT, fl, by);
     hipError_t e = launch_dot(dtype, dt, (int)tasks.size(), c->stream);
+    prof_end(c, pr);
     if (e != hipSuccess) return hip_fail(c, e, "dot");
     c->ws_off -= bytes;   // chunk scratch is reused by the next chunk (stream ordered)
     c->ws_off = mark.off > c->ws_off ? mark.off : c->ws_off;
@@ -352,7 +409,7 @@ tt_status tt_ctx_create(tt_ctx** ctx, int device, void* stream) {
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return TT_EDEVICE;
   if (hipSetDevice(device) != hipSuccess) return TT_EDEVICE;
-  static bool lds_ready = false;
+  static bool lds_ready = false;  // LDS limits are per kernel, raised once per process
   if (!lds_ready) {
     if (qr_kernels_init() != hipSuccess) return TT_EDEVICE;
     lds_ready = true;
@@ -370,6 +427,8 @@ void tt_ctx_destroy(tt_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  prof_collect(c);
+  for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
   c->dev.release();
   c->pin.release();
   delete c;
@@ -387,6 +446,31 @@ tt_status tt_ctx_set_workspace(tt_ctx* c, void* ws, size_t bytes) {
 size_t tt_ctx_required_bytes(const tt_ctx* c) { return c ? c->required : 0; }
 
 const char* tt_last_error(const tt_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+tt_status tt_ctx_set_profiling(tt_ctx* c, int on) {
+  if (!c) return TT_EINVAL;
+  c->prof = on != 0;
+  for (int k = 0; k < PK_COUNT; ++k) {
+    c->prof_ms[k] = c->prof_flops[k] = c->prof_bytes[k] = 0.0;
+    c->prof_cnt[k] = 0;
+  }
+  return TT_OK;
+}
+
+tt_status tt_ctx_profile(const tt_ctx* c, int kind, double* ms, int64_t* launches, double* flops, double* bytes) {
+  if (!c || kind < 0 || kind >= PK_COUNT) return TT_EINVAL;
+  if (ms) *ms = c->prof_ms[kind];
+  if (launches) *launches = c->prof_cnt[kind];
+  if (flops) *flops = c->prof_flops[kind];
+  if (bytes) *bytes = c->prof_bytes[kind];
+  return TT_OK;
+}
+
+const char* tt_profile_kind_name(int kind) {
+  static const char* names[PK_COUNT] = {"qr_factor_leaf", "qr_factor_node", "qr_apply", "svd_jacobi",
+                                        "contraction_gemm", "tt_dot", "other"};
+  return (kind >= 0 && kind < PK_COUNT) ? names[kind] : "unknown";
+}
 
 tt_status tt_dot_batched(tt_ctx* c, int32_t npairs, const tt_sum* xs, const tt_sum* ys, double* out) {
   if (!c || npairs < 0 || (npairs > 0 && (!xs || !ys || !out))) return fail(c, TT_EINVAL, "dot: bad arguments");
@@ -698,7 +782,8 @@ tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum*
     if (!G || !Rinv || !info) return finish(fail(c, TT_ENOMEM, "gram buffers"));
     if ((s = dot_pairs_idx(c, (int)xs.size(), xs.data(), ys.data(), G, &idx)) != TT_OK) return finish(s);
     if ((e = launch_sym_lower(G, m, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "sym"));
-    if ((e = launch_cholinv(G, m, Rinv, info, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "cholesky"));
+    const double udot = (a[0].comp[0].dtype == TT_F64) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
+    if ((e = launch_cholinv(G, m, Rinv, info, udot, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "cholesky"));
     int32_t* hinfo = (int32_t*)c->pin.alloc(8);
     if ((e = hipMemcpyAsync(hinfo, info, 4, hipMemcpyDeviceToHost, c->stream)) != hipSuccess)
       return finish(hip_fail(c, e, "info"));

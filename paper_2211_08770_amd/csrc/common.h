@@ -22,6 +22,7 @@ struct QrTask {
   int64_t src_rs, src_cs;
   int32_t nchild;         // > 0: tree node stacking the R factors of children[child0 ..]
   int32_t child0;
+  int32_t kc0, kc_last;   // node: rows contributed by each child but the last, and by the last
   int32_t m, ncol;        // tile shape
   void* tile;             // row-major m x ncol
   double* tau;            // [min(m, ncol)]
@@ -35,6 +36,7 @@ struct ApplyTask {
   const double* tau;
   const void* tmat;
   int32_t m, ncol, kq;    // kq = number of reflectors = min(m, ncol)
+  int32_t nchild, kc0, kc_last;   // node structure (stacked triangles); nchild = 0 for a dense leaf
   int32_t k_in, t;
   const double* x;
   int64_t x_ld;
@@ -52,6 +54,7 @@ struct SvdTask {
   int64_t r_ld;
   int32_t kr, ncol;
   int32_t upper;          // 1: R is upper trapezoidal (entries below the diagonal read as 0)
+  double bulk_u;          // unit round-off of the arithmetic that produced R (deflation scale; 0: none)
   double* A;              // scratch ncol x kr, column-major
   double* acc;            // scratch kr x kr, column-major
   double* sigma;          // [kr] sorted decreasing on exit
@@ -130,7 +133,7 @@ hipError_t launch_copy_segs(int dtype, const CopySeg* d_segs, int nsegs, hipStre
 // out[idx ? idx[o] : o] = sum of slots[seg[o] .. seg[o+1])
 hipError_t launch_segsum(const double* slots, const int32_t* seg, const int32_t* idx, int nout, double* out,
                          hipStream_t s);
-hipError_t launch_cholinv(double* G, int m, double* Rinv, int32_t* info, hipStream_t s);
+hipError_t launch_cholinv(double* G, int m, double* Rinv, int32_t* info, double u, hipStream_t s);
 hipError_t launch_loo_mats(const double* G, int m, double* E, hipStream_t s);
 
 // z core = alpha*x core (+) y core in the TT-sum layout (block concatenation).

@@ -24,6 +24,17 @@ struct Arena {
 
 }  // namespace tto
 
+namespace tto {
+// Kinds of launches timed by the context's profiler.
+enum ProfKind { PK_QR_LEAF = 0, PK_QR_NODE, PK_QR_APPLY, PK_SVD, PK_GEMM, PK_DOT, PK_OTHER, PK_COUNT };
+struct ProfRec {
+  int kind;
+  hipEvent_t start, stop;
+  double flops;
+  double bytes;
+};
+}  // namespace tto
+
 struct tt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -35,6 +46,14 @@ struct tt_ctx {
   tto::Arena dev;              // task descriptors, scalars
   tto::Arena pin;              // staging for uploads / readbacks
   std::string err;
+  // profiler: HIP events around each launch on this context's stream
+  bool prof = false;
+  std::vector<tto::ProfRec> prof_open;
+  std::vector<hipEvent_t> prof_pool;
+  double prof_ms[tto::PK_COUNT] = {0};
+  double prof_flops[tto::PK_COUNT] = {0};
+  double prof_bytes[tto::PK_COUNT] = {0};
+  int64_t prof_cnt[tto::PK_COUNT] = {0};
 };
 
 namespace tto {
@@ -63,6 +82,12 @@ T* upload(tt_ctx* c, const std::vector<T>& v) {
 void* dev_scratch(tt_ctx* c, size_t bytes);
 
 inline size_t elt_size(int dtype) { return dtype == TT_F64 ? 8 : 4; }
+
+// Profiler: prof_begin before a launch, prof_end after it (no-ops when off);
+// prof_collect after the stream has drained accumulates the elapsed times.
+int prof_begin(tt_ctx* c, int kind, double flops, double bytes);
+void prof_end(tt_ctx* c, int rec);
+void prof_collect(tt_ctx* c);
 
 // ---- TSQR tree -------------------------------------------------------------
 struct Tree {

@@ -112,18 +112,21 @@ __global__ void k_segsum(const double* __restrict__ slots, const int32_t* __rest
 
 // In-place lower Cholesky of the row-major m x m matrix G, then
 // Rinv = (L^T)^{-1} (upper triangular, row-major).  info = 0 on success,
-// j+1 when the j-th pivot is not positive (G not numerically SPD).
+// j+1 when the j-th pivot is <= m u G_jj (G numerically not SPD; u is the unit
+// round-off of the arithmetic that formed G).
 __global__ __launch_bounds__(NT) void k_cholinv(double* __restrict__ G, int m, double* __restrict__ Rinv,
-                                                int32_t* __restrict__ info) {
+                                                int32_t* __restrict__ info, double u) {
   __shared__ int fail;
   const int tid = threadIdx.x;
   if (tid == 0) fail = 0;
   __syncthreads();
   for (int j = 0; j < m; ++j) {
     if (tid == 0) {
-      double dj = G[j * m + j];
+      const double gjj = G[j * m + j];
+      double dj = gjj;
       for (int k = 0; k < j; ++k) dj -= G[j * m + k] * G[j * m + k];
-      if (!(dj > 0.0)) fail = j + 1;
+      // numerically singular once the pivot falls to the rounding level of G_jj
+      if (!(dj > (double)m * u * gjj)) fail = j + 1;
       else G[j * m + j] = sqrt(dj);
     }
     __syncthreads();
@@ -310,8 +313,8 @@ hipError_t launch_segsum(const double* slots, const int32_t* seg, const int32_t*
   return hipGetLastError();
 }
 
-hipError_t launch_cholinv(double* G, int m, double* Rinv, int32_t* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(NT), 0, s, G, m, Rinv, info);
+hipError_t launch_cholinv(double* G, int m, double* Rinv, int32_t* info, double u, hipStream_t s) {
+  hipLaunchKernelGGL(k_cholinv, dim3(1), dim3(NT), 0, s, G, m, Rinv, info, u);
   return hipGetLastError();
 }
 

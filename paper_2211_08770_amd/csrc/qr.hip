@@ -10,6 +10,11 @@
 //   A <- A - V T^T (V^T A)
 // by a 2-D thread split (columns x row groups) whose partial V^T A sums are
 // combined through LDS.
+//
+// A tree node stacks the upper-triangular R factors of its children.  Row i
+// of a stacked triangle is zero left of column i, so the Householder vectors
+// of the panel starting at column p0 only touch, in each child block, the
+// rows i < p0 + QR_NB: every panel works on that compacted row list only.
 #include "common.h"
 
 namespace tto {
@@ -18,6 +23,7 @@ namespace {
 
 constexpr int NB = QR_NB;
 constexpr int NT = QR_THREADS;
+constexpr int MAXR = QR_MAXROWS;
 
 __device__ inline double block_sum(double v, double* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -31,17 +37,43 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// A (rows x ncols, row-major with leading dimension lda, columns c0..c0+ncols)
-//   <- A - V * op(T) * (V^T A),  op(T) = T^T when trans, else T.
-// V: LDS column-major [NB][ldv] with explicit unit diagonal and zeros above
-// (columns >= nb are zero); T: LDS row-major NB x NB, zero outside nb x nb.
+// Active tile rows of the panel [p0, p0 + nb) in increasing order; returns the count.
+// Dense tile (nchild == 0): rows p0..m-1.  Node: in child block b (offset
+// b*kc0, size kc_b) the local rows i with max(0, p0 - off_b) <= i < min(kc_b, p0 + nb).
+__device__ int panel_rows(int* rowl, int* cnt, int m, int nchild, int kc0, int kc_last, int p0, int nb) {
+  const int tid = threadIdx.x;
+  if (nchild == 0) {
+    for (int r = tid; r < m - p0; r += NT) rowl[r] = p0 + r;
+    __syncthreads();
+    return m - p0;
+  }
+  if (tid == 0) {
+    int c = 0;
+    for (int b = 0; b < nchild; ++b) {
+      const int off = b * kc0;
+      const int kcb = (b == nchild - 1) ? kc_last : kc0;
+      const int lo = (p0 - off) > 0 ? (p0 - off) : 0;
+      const int hi = kcb < (p0 + nb) ? kcb : (p0 + nb);
+      for (int i = lo; i < hi; ++i) rowl[c++] = off + i;
+    }
+    *cnt = c;
+  }
+  __syncthreads();
+  const int c = *cnt;
+  __syncthreads();
+  return c;
+}
+
+// A rows rowl[0..rows) x columns c0..c0+ncols (row-major, leading dimension lda)
+//   <- A - V op(T) (V^T A),  op(T) = T^T when TRANS.
+// V: LDS column-major [NB][ldv] over the compacted rows (explicit unit
+// diagonal, zeros above; columns >= nb are zero); T: LDS NB x NB.
 // wred: LDS scratch of NT * NB doubles.
 template <bool TRANS, typename TA, typename TV>
-__device__ void block_reflect(TA* __restrict__ A, int64_t lda, int c0, int ncols, int rows,
-                              const TV* __restrict__ V, int ldv, const double* __restrict__ T,
+__device__ void block_reflect(TA* __restrict__ A, int64_t lda, const int* __restrict__ rowl, int c0, int ncols,
+                              int rows, const TV* __restrict__ V, int ldv, const double* __restrict__ T,
                               double* __restrict__ wred) {
   const int tid = threadIdx.x;
-  // column threads tc, row groups G (tc * G <= NT)
   const int tc = ncols < NT ? ncols : NT;
   if (tc <= 0) return;
   const int G = NT / tc;
@@ -54,15 +86,27 @@ __device__ void block_reflect(TA* __restrict__ A, int64_t lda, int c0, int ncols
 #pragma unroll
     for (int k = 0; k < NB; ++k) w[k] = 0.0;
     if (active) {
-      const TA* col = A + (c0 + c);
-#pragma unroll 2
-      for (int r = g; r < rows; r += G) {
-        const double a = (double)col[(int64_t)r * lda];
+      TA* col = A + (c0 + c);
+      int r = g;
+      for (; r + 3 * G < rows; r += 4 * G) {
+        const double a0 = (double)col[(int64_t)rowl[r] * lda];
+        const double a1 = (double)col[(int64_t)rowl[r + G] * lda];
+        const double a2 = (double)col[(int64_t)rowl[r + 2 * G] * lda];
+        const double a3 = (double)col[(int64_t)rowl[r + 3 * G] * lda];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const TV* vk = V + k * ldv;
+          w[k] += (double)vk[r] * a0 + (double)vk[r + G] * a1 + (double)vk[r + 2 * G] * a2 +
+                  (double)vk[r + 3 * G] * a3;
+        }
+      }
+      for (; r < rows; r += G) {
+        const double a = (double)col[(int64_t)rowl[r] * lda];
 #pragma unroll
         for (int k = 0; k < NB; ++k) w[k] += (double)V[k * ldv + r] * a;
       }
     }
-    double* slot = wred + (size_t)(g * tc + cl) * NB;   // this thread's LDS slot (g < G)
+    double* slot = wred + (size_t)(g * tc + cl) * NB;
     if (G > 1) {
       if (g < G) {
 #pragma unroll
@@ -80,8 +124,8 @@ __device__ void block_reflect(TA* __restrict__ A, int64_t lda, int c0, int ncols
       }
       __syncthreads();
     }
-    // w2 = op(T) w, one output at a time through the thread's LDS slot
     if (active) {
+      // w2 = op(T) w, one output at a time through the thread's LDS slot
 #pragma unroll 1
       for (int i = 0; i < NB; ++i) {
         double s = 0.0;
@@ -93,12 +137,31 @@ __device__ void block_reflect(TA* __restrict__ A, int64_t lda, int c0, int ncols
 #pragma unroll
       for (int k = 0; k < NB; ++k) w2[k] = slot[k];
       TA* col = A + (c0 + c);
-#pragma unroll 2
-      for (int r = g; r < rows; r += G) {
+      int r = g;
+      for (; r + 3 * G < rows; r += 4 * G) {
+        const int64_t i0 = (int64_t)rowl[r] * lda, i1 = (int64_t)rowl[r + G] * lda;
+        const int64_t i2 = (int64_t)rowl[r + 2 * G] * lda, i3 = (int64_t)rowl[r + 3 * G] * lda;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const TV* vk = V + k * ldv;
+          s0 += (double)vk[r] * w2[k];
+          s1 += (double)vk[r + G] * w2[k];
+          s2 += (double)vk[r + 2 * G] * w2[k];
+          s3 += (double)vk[r + 3 * G] * w2[k];
+        }
+        const double a0 = (double)col[i0], a1 = (double)col[i1], a2 = (double)col[i2], a3 = (double)col[i3];
+        col[i0] = (TA)(a0 - s0);
+        col[i1] = (TA)(a1 - s1);
+        col[i2] = (TA)(a2 - s2);
+        col[i3] = (TA)(a3 - s3);
+      }
+      for (; r < rows; r += G) {
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < NB; ++k) s += (double)V[k * ldv + r] * w2[k];
-        col[(int64_t)r * lda] = (TA)((double)col[(int64_t)r * lda] - s);
+        const int64_t ia = (int64_t)rowl[r] * lda;
+        col[ia] = (TA)((double)col[ia] - s);
       }
     }
     __syncthreads();
@@ -139,6 +202,8 @@ template <typename TS, typename TT>
 __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tasks,
                                                   const QrTask* __restrict__ children) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int rowl[MAXR];
+  __shared__ int rcnt;
   const QrTask tk = tasks[blockIdx.x];
   const int m = tk.m, N = tk.ncol, tid = threadIdx.x;
   TT* A = (TT*)tk.tile;
@@ -168,8 +233,8 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   __syncthreads();
 
   const int kmax = m < N ? m : N;
-  const int ldp = m;  // panel leading dimension (rows of the first panel)
-  TT* P = (TT*)smem;                                               // NB * ldp
+  const int ldp = MAXR;
+  TT* P = (TT*)smem;                                               // NB * MAXR
   double* T = (double*)(smem + (((size_t)NB * ldp * sizeof(TT) + 15) & ~(size_t)15));  // NB*NB
   double* S = T + NB * NB;                                         // NB*NB
   double* red = S + NB * NB;                                       // 16
@@ -178,14 +243,14 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
 
   for (int p0 = 0, pi = 0; p0 < kmax; p0 += NB, ++pi) {
     const int nb = (kmax - p0) < NB ? (kmax - p0) : NB;
-    const int rows = m - p0;
+    const int rows = panel_rows(rowl, &rcnt, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
     // ---- load panel (zero-padded to NB columns)
     for (int idx = tid; idx < rows * NB; idx += NT) {
       const int r = idx / NB, jj = idx - r * NB;
-      P[jj * ldp + r] = (jj < nb) ? A[(int64_t)(p0 + r) * N + p0 + jj] : (TT)0;
+      P[jj * ldp + r] = (jj < nb) ? A[(int64_t)rowl[r] * N + p0 + jj] : (TT)0;
     }
     __syncthreads();
-    // ---- unblocked Householder on the panel
+    // ---- unblocked Householder on the panel (pivot of column jj is compact row jj)
     for (int jj = 0; jj < nb; ++jj) {
       TT* col = P + jj * ldp;
       double part = 0.0;
@@ -233,21 +298,21 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
     // ---- write the factored panel back, keep tau
     for (int idx = tid; idx < rows * nb; idx += NT) {
       const int r = idx / nb, jj = idx - r * nb;
-      A[(int64_t)(p0 + r) * N + p0 + jj] = P[jj * ldp + r];
+      A[(int64_t)rowl[r] * N + p0 + jj] = P[jj * ldp + r];
     }
     if (tid < nb) tk.tau[p0 + tid] = taus[tid];
     __syncthreads();
     // ---- explicit V (unit diagonal, zeros above)
-    for (int idx = tid; idx < rows * NB; idx += NT) {
-      const int jj = idx / rows, r = idx - jj * rows;
-      if (r <= jj) P[jj * ldp + r] = (r == jj && jj < nb) ? (TT)1 : (TT)0;
+    for (int idx = tid; idx < NB * NB; idx += NT) {
+      const int jj = idx / NB, r = idx - jj * NB;
+      if (r <= jj && r < rows) P[jj * ldp + r] = (r == jj && jj < nb) ? (TT)1 : (TT)0;
     }
     __syncthreads();
     form_t<TT>(P, ldp, rows, nb, taus, T, S);
     if (tid < NB * NB) ((double*)tk.tmat)[(size_t)pi * NB * NB + tid] = T[tid];
-    // ---- trailing update  A <- Q_p^T A
+    // ---- trailing update  A <- Q_p^T A  on the panel's rows
     const int c0 = p0 + nb;
-    if (c0 < N) block_reflect<true, TT, TT>(A + (int64_t)p0 * N, N, c0, N - c0, rows, P, ldp, T, wred);
+    if (c0 < N) block_reflect<true, TT, TT>(A, N, rowl, c0, N - c0, rows, P, ldp, T, wred);
     __syncthreads();
   }
 }
@@ -256,6 +321,8 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
 template <typename TT, typename TO>
 __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ tasks) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int rowl[MAXR];
+  __shared__ int rcnt;
   const ApplyTask tk = tasks[blockIdx.x];
   const int m = tk.m, N = tk.ncol, t = tk.t, tid = threadIdx.x;
   const TT* tile = (const TT*)tk.tile;
@@ -266,7 +333,7 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
     W[idx] = (r < tk.k_in) ? tk.x[r * tk.x_ld + c] : 0.0;
   }
   __syncthreads();
-  const int ldp = m;
+  const int ldp = MAXR;
   TT* V = (TT*)smem;
   double* T = (double*)(smem + (((size_t)NB * ldp * sizeof(TT) + 15) & ~(size_t)15));
   double* wred = T + NB * NB;
@@ -274,19 +341,19 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
   for (int pi = np - 1; pi >= 0; --pi) {
     const int p0 = pi * NB;
     const int nb = (tk.kq - p0) < NB ? (tk.kq - p0) : NB;
-    const int rows = m - p0;
+    const int rows = panel_rows(rowl, &rcnt, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
     for (int idx = tid; idx < rows * NB; idx += NT) {
       const int r = idx / NB, jj = idx - r * NB;
       TT v = (TT)0;
       if (jj < nb) {
         if (r == jj) v = (TT)1;
-        else if (r > jj) v = tile[(int64_t)(p0 + r) * N + p0 + jj];
+        else if (r > jj) v = tile[(int64_t)rowl[r] * N + p0 + jj];
       }
       V[jj * ldp + r] = v;
     }
     if (tid < NB * NB) T[tid] = ((const double*)tk.tmat)[(size_t)pi * NB * NB + tid];
     __syncthreads();
-    block_reflect<false, double, TT>(W + (int64_t)p0 * t, t, 0, t, rows, V, ldp, T, wred);
+    block_reflect<false, double, TT>(W, t, rowl, 0, t, rows, V, ldp, T, wred);
     __syncthreads();
   }
   if (tk.to_out) {
@@ -299,10 +366,10 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
 }
 
 size_t factor_smem(int elt) {
-  return (((size_t)NB * QR_MAXROWS * elt + 15) & ~(size_t)15) + sizeof(double) * (2 * NB * NB + 16 + NB + NT * NB);
+  return (((size_t)NB * MAXR * elt + 15) & ~(size_t)15) + sizeof(double) * (2 * NB * NB + 16 + NB + NT * NB);
 }
 size_t apply_smem(int elt) {
-  return (((size_t)NB * QR_MAXROWS * elt + 15) & ~(size_t)15) + sizeof(double) * (NB * NB + NT * NB);
+  return (((size_t)NB * MAXR * elt + 15) & ~(size_t)15) + sizeof(double) * (NB * NB + NT * NB);
 }
 
 template <typename K>

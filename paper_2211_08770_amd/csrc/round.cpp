@@ -106,6 +106,14 @@ bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void*
       std::memset(&q, 0, sizeof(q));
       q.nchild = cnt;
       q.child0 = (int32_t)i;
+      // every child but the last contributes the same number of R rows (the kernels rely on it)
+      q.kc0 = (int32_t)std::min<int64_t>(prev[i].m, N);
+      q.kc_last = (int32_t)std::min<int64_t>(prev[i + cnt - 1].m, N);
+      for (int c = 0; c + 1 < cnt; ++c)
+        if (std::min<int64_t>(prev[i + c].m, N) != q.kc0) {
+          if (why) *why = "internal: uneven TSQR children";
+          return false;
+        }
       q.m = (int32_t)rows;
       q.ncol = (int32_t)N;
       q.tile = cv.take((size_t)rows * N * 8);
@@ -119,6 +127,37 @@ bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void*
 }
 
 namespace {
+
+// rows of column j that the Householder reflector of column j touches
+int64_t active_rows(int64_t m, int nchild, int64_t kc0, int64_t kc_last, int64_t j) {
+  if (nchild == 0) return m - j;
+  int64_t a = 0;
+  for (int b = 0; b < nchild; ++b) {
+    const int64_t off = (int64_t)b * kc0;
+    const int64_t kcb = (b == nchild - 1) ? kc_last : kc0;
+    const int64_t lo = std::max<int64_t>(0, j - off), hi = std::min<int64_t>(kcb - 1, j);
+    if (hi >= lo) a += hi - lo + 1;
+  }
+  return a;
+}
+
+// algorithmic flops of a Householder QR of one tile: sum_j (4 a_j (N-j-1) + 3 a_j)
+double qr_flops(const QrTask& q) {
+  const int64_t kq = std::min<int64_t>(q.m, q.ncol);
+  double f = 0.0;
+  for (int64_t j = 0; j < kq; ++j) {
+    const double a = (double)active_rows(q.m, q.nchild, q.kc0, q.kc_last, j);
+    f += 4.0 * a * (double)(q.ncol - j - 1) + 3.0 * a;
+  }
+  return f;
+}
+
+// algorithmic flops of applying the tile's reflectors to t columns: sum_j 4 a_j t
+double apply_flops(const ApplyTask& t) {
+  double f = 0.0;
+  for (int64_t j = 0; j < t.kq; ++j) f += 4.0 * (double)active_rows(t.m, t.nchild, t.kc0, t.kc_last, j) * t.t;
+  return f;
+}
 
 // Apply plan of a tree: out = Q [X; 0], tasks grouped top-down.
 struct ApplyLevel {
@@ -167,6 +206,9 @@ void plan_apply(Carver& cv, const Tree& t, const double* X, int64_t x_ld, int64_
       a.m = q.m;
       a.ncol = q.ncol;
       a.kq = (int32_t)std::min<int64_t>(q.m, N);
+      a.nchild = q.nchild;
+      a.kc0 = q.kc0;
+      a.kc_last = q.kc_last;
       a.t = (int32_t)tcols;
       a.work = work[l][i];
       if (l == L - 1) {
@@ -313,7 +355,15 @@ tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
         const QrTask* dt = upload(c, tasks);
         const QrTask* dc = children.empty() ? nullptr : upload(c, children);
         if (!dt || (!children.empty() && !dc)) return fail(c, TT_ENOMEM, "task upload");
+        double fl = 0.0, by = 0.0;
+        if (c->prof)
+          for (const QrTask& q : tasks) {
+            fl += qr_flops(q);
+            by += 2.0 * (double)q.m * q.ncol * (pass == 0 ? 8.0 : 4.0);
+          }
+        const int pr = prof_begin(c, l == 0 ? PK_QR_LEAF : PK_QR_NODE, fl, by);
         hipError_t e = launch_qr_factor(srcd, pass == 0 ? 0 : 1, dt, dc, (int)tasks.size(), c->stream);
+        prof_end(c, pr);
         if (e != hipSuccess) return hip_fail(c, e, "qr_factor");
       }
     }
@@ -335,7 +385,15 @@ tt_status launch_apply_plans(tt_ctx* c, std::vector<std::vector<ApplyLevel>>& pl
       if (tasks.empty()) continue;
       const ApplyTask* dt = upload(c, tasks);
       if (!dt) return fail(c, TT_ENOMEM, "task upload");
+      double fl = 0.0, by = 0.0;
+      if (c->prof)
+        for (const ApplyTask& a : tasks) {
+          fl += apply_flops(a);
+          by += (double)a.m * a.ncol * (tdt == 0 ? 8.0 : 4.0) + 2.0 * (double)a.m * a.t * 8.0;
+        }
+      const int pr = prof_begin(c, PK_QR_APPLY, fl, by);
       hipError_t e = launch_qr_apply(tdt, out_dtype, dt, (int)tasks.size(), c->stream);
+      prof_end(c, pr);
       if (e != hipSuccess) return hip_fail(c, e, "qr_apply");
     }
   }
@@ -535,8 +593,17 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     }
     const GemmTask* dgt = upload(c, gt);
     const GemmPart* dgp = upload(c, gp);
-    if ((e = launch_gemm(dtype, dgt, dgp, (int)gt.size(), max_m, max_n, s)) != hipSuccess)
-      return hip_fail(c, e, "contraction");
+    double gfl = 0.0, gby = 0.0;
+    for (const GemmTask& g : gt)
+      for (int pi = 0; pi < g.nparts; ++pi) {
+        gfl += 2.0 * g.M * g.N * (double)gp[g.part0 + pi].K;
+        gby += (double)elt * ((double)g.M * gp[g.part0 + pi].K) + 8.0 * g.N * (double)gp[g.part0 + pi].K;
+      }
+    for (const GemmTask& g : gt) gby += (double)elt * g.M * g.N;
+    const int gpr = prof_begin(c, PK_GEMM, gfl, gby);
+    e = launch_gemm(dtype, dgt, dgp, (int)gt.size(), max_m, max_n, s);
+    prof_end(c, gpr);
+    if (e != hipSuccess) return hip_fail(c, e, "contraction");
   }
 
   // ---------------- norms
@@ -603,6 +670,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       t.kr = js.lr.kr();
       t.ncol = (int32_t)js.lr.N;
       t.upper = 1;
+      t.bulk_u = (jb.dtype == TT_F64) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
       t.A = js.A;
       t.acc = js.acc;
       t.sigma = js.sig;
@@ -617,7 +685,16 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       sv.push_back(t);
     }
     const SvdTask* dsv = upload(c, sv);
-    if ((e = launch_svd(dsv, (int)sv.size(), s)) != hipSuccess) return hip_fail(c, e, "svd");
+    double sfl = 0.0, sby = 0.0;
+    for (const SvdTask& t : sv) {
+      const double mn = std::min(t.kr, t.ncol), mx = std::max(t.kr, t.ncol);
+      sfl += 4.0 * mx * mn * mn + 22.0 * mn * mn * mn;   // R-SVD operation count (Golub-Van Loan)
+      sby += 8.0 * (double)t.kr * t.ncol;
+    }
+    const int spr = prof_begin(c, PK_SVD, sfl, sby);
+    e = launch_svd(dsv, (int)sv.size(), s);
+    prof_end(c, spr);
+    if (e != hipSuccess) return hip_fail(c, e, "svd");
     if ((e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=
         hipSuccess)
       return hip_fail(c, e, "rank readback");

@@ -3,11 +3,16 @@
 //
 // One-sided (Hestenes) Jacobi: the columns of A are rotated pairwise until
 // every pair is orthogonal to relative precision; the accumulated rotations
-// are kept.  For a square R (tall unfolding) A = R and the accumulated
-// rotations are V; for a wide R (fewer rows than columns) A = R^T and the
-// accumulated rotations are the left singular vectors.  Pairs follow a
-// round-robin tournament so that each round's pairs are disjoint and run on
-// different waves.
+// J are kept.  For a square R (tall unfolding) A = R and J = V; for a wide R
+// (fewer rows than columns) A = R^T and J holds the left singular vectors.
+// Pairs follow a round-robin tournament, so the pairs of one round are
+// disjoint and run on different waves.
+//
+// Deflation: columns of A whose squared norms add up to at most
+// tau^2 = (2 sqrt(nc) u ||A||_F)^2 (u = unit round-off of the arithmetic that
+// produced R) are set aside before the sweeps; they change A by less than the
+// rounding noise already in R.  Their energy is still counted in the
+// discarded tail.  When the remaining problem fits, A and J live in LDS.
 //
 // Rank: the smallest t >= 1 whose discarded tail sqrt(sum_{i>t} sigma_i^2) is
 // <= eps = delta/sqrt(d-1) * ||x|| (tail accumulated from the smallest
@@ -18,52 +23,48 @@ namespace tto {
 
 namespace {
 
-constexpr int NT = 512;
+constexpr int NT = 1024;
+constexpr int NW = NT / 64;
 constexpr int MAXC = 1024;
+constexpr int LDS_DOUBLES = 18000;   // 140.6 KiB for A and J (plus ~16 KiB static)
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-__global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
-  const SvdTask tk = tasks[blockIdx.x];
-  const int kr = tk.kr, N = tk.ncol;
-  const bool tall = (kr == N);
-  const int len = N, nc = kr;
-  double* A = tk.A;
-  double* J = tk.acc;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = NT / 64;
-
-  __shared__ int perm[MAXC + 2];
-  __shared__ double sig[MAXC];
-  __shared__ int rots;
-  __shared__ int tsel;
-
-  for (int64_t idx = tid; idx < (int64_t)nc * len; idx += NT) {
-    const int j = (int)(idx / len), i = (int)(idx - (int64_t)j * len);
-    // an upper-trapezoidal R stores Householder vectors below its diagonal: read them as zero
-    const int rr = tall ? i : j, cc = tall ? j : i;
-    A[idx] = (tk.upper && cc < rr) ? 0.0 : tk.R[(int64_t)rr * tk.r_ld + cc];
-  }
-  for (int64_t idx = tid; idx < (int64_t)nc * nc; idx += NT) {
-    const int j = (int)(idx / nc), i = (int)(idx - (int64_t)j * nc);
-    J[idx] = (i == j) ? 1.0 : 0.0;
-  }
-  const int ncp = nc + (nc & 1);
-  for (int i = tid; i < ncp; i += NT) perm[i] = i;
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < NW; ++i) s += red[i];
+  return s;
+}
 
+// One-sided Jacobi on A (len x k, column-major, lda = len) with accumulation
+// into J (k x k, column-major).  Returns the number of sweeps used.
+__device__ int jacobi(double* A, int len, double* J, int k, int* perm, int* rots) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int kp = k + (k & 1);
+  for (int i = tid; i < kp; i += NT) perm[i] = i;
+  __syncthreads();
   const double tol = sqrt((double)len) * 1.1102230246251565e-16;
   int sweep = 0;
-  for (; sweep < 64 && ncp >= 2; ++sweep) {
-    if (tid == 0) rots = 0;
+  for (; sweep < 64 && kp >= 2; ++sweep) {
+    if (tid == 0) *rots = 0;
     __syncthreads();
-    for (int round = 0; round < ncp - 1; ++round) {
-      for (int pair = wave; pair < ncp / 2; pair += nwaves) {
-        int p = perm[pair], q = perm[ncp - 1 - pair];
-        if (p >= nc || q >= nc) continue;
-        if (p > q) { const int tmp = p; p = q; q = tmp; }
+    for (int round = 0; round < kp - 1; ++round) {
+      for (int pair = wave; pair < kp / 2; pair += NW) {
+        int p = perm[pair], q = perm[kp - 1 - pair];
+        if (p >= k || q >= k) continue;
+        if (p > q) {
+          const int tmp = p;
+          p = q;
+          q = tmp;
+        }
         double* ap = A + (int64_t)p * len;
         double* aq = A + (int64_t)q * len;
         double al = 0.0, be = 0.0, ga = 0.0;
@@ -87,44 +88,127 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
             ap[i] = c * x - s * y;
             aq[i] = s * x + c * y;
           }
-          double* jp = J + (int64_t)p * nc;
-          double* jq = J + (int64_t)q * nc;
-          for (int i = lane; i < nc; i += 64) {
+          double* jp = J + (int64_t)p * k;
+          double* jq = J + (int64_t)q * k;
+          for (int i = lane; i < k; i += 64) {
             const double x = jp[i], y = jq[i];
             jp[i] = c * x - s * y;
             jq[i] = s * x + c * y;
           }
-          if (lane == 0) atomicAdd(&rots, 1);
+          if (lane == 0) atomicAdd(rots, 1);
         }
       }
       __syncthreads();
-      if (tid == 0 && ncp > 2) {
-        const int last = perm[ncp - 1];
-        for (int i = ncp - 1; i >= 2; --i) perm[i] = perm[i - 1];
+      if (tid == 0 && kp > 2) {
+        const int last = perm[kp - 1];
+        for (int i = kp - 1; i >= 2; --i) perm[i] = perm[i - 1];
         perm[1] = last;
       }
       __syncthreads();
     }
-    const int r = rots;
+    const int r = *rots;
     __syncthreads();
     if (r == 0) break;
   }
+  return sweep;
+}
 
-  // singular values = column norms
-  for (int j = wave; j < nc; j += nwaves) {
+__global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
+  extern __shared__ __align__(16) double lds[];
+  __shared__ int perm[MAXC + 2];
+  __shared__ int act[MAXC];
+  __shared__ double nrm2[MAXC];
+  __shared__ double red[NW];
+  __shared__ int rots, kact, lenact, tsel;
+  __shared__ double edrop;
+
+  const SvdTask tk = tasks[blockIdx.x];
+  const int kr = tk.kr, N = tk.ncol;
+  const bool tall = (kr == N);
+  const int nc = kr;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  // element (i, j) of A = (R or R^T); R entries below the diagonal read as zero when upper
+  auto aval = [&](int i, int j) -> double {
+    const int rr = tall ? i : j, cc = tall ? j : i;
+    if (tk.upper && cc < rr) return 0.0;
+    return tk.R[(int64_t)rr * tk.r_ld + cc];
+  };
+
+  // ---- column norms and deflation
+  for (int j = wave; j < nc; j += NW) {
+    double s = 0.0;
+    for (int i = lane; i < N; i += 64) {
+      const double v = aval(i, j);
+      s += v * v;
+    }
+    s = wave_sum(s);
+    if (lane == 0) nrm2[j] = s;
+  }
+  __syncthreads();
+  double tot = 0.0;
+  for (int j = tid; j < nc; j += NT) tot += nrm2[j];
+  tot = block_sum(tot, red);
+  const double tau = 2.0 * sqrt((double)nc) * tk.bulk_u;
+  const double tau2 = tau * tau * tot;
+  // a column is set aside when it and every smaller column (ties by index) fit in tau^2 together
+  for (int j = tid; j < nc; j += NT) {
+    const double v = nrm2[j];
+    double below = 0.0;
+    for (int i = 0; i < nc; ++i) {
+      const double w = nrm2[i];
+      if (w < v || (w == v && i <= j)) below += w;
+    }
+    perm[j] = ((below <= tau2 && tau2 > 0.0) || v == 0.0) ? 0 : 1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int k = 0, mx = -1;
+    double e = 0.0;
+    for (int j = 0; j < nc; ++j) {
+      if (perm[j]) {
+        act[k++] = j;
+        mx = j;
+      } else {
+        e += nrm2[j];
+      }
+    }
+    kact = k;
+    edrop = e;
+    lenact = (tall && tk.upper) ? (mx + 1) : N;
+  }
+  __syncthreads();
+  const int k = kact, len = lenact > 0 ? lenact : 1;
+
+  // ---- A_active (len x k) and J (k x k): LDS when they fit, else global scratch
+  const bool in_lds = (int64_t)len * k + (int64_t)k * k <= LDS_DOUBLES;
+  double* A = in_lds ? lds : tk.A;
+  double* J = in_lds ? lds + (int64_t)len * k : tk.acc;
+  for (int64_t idx = tid; idx < (int64_t)k * len; idx += NT) {
+    const int a = (int)(idx / len), i = (int)(idx - (int64_t)a * len);
+    A[idx] = aval(i, act[a]);
+  }
+  for (int64_t idx = tid; idx < (int64_t)k * k; idx += NT) {
+    const int j = (int)(idx / k), i = (int)(idx - (int64_t)j * k);
+    J[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int sweeps = (k > 0) ? jacobi(A, len, J, k, perm, &rots) : 0;
+
+  // ---- singular values, order, rank
+  for (int j = wave; j < k; j += NW) {
     const double* aj = A + (int64_t)j * len;
     double s = 0.0;
     for (int i = lane; i < len; i += 64) s += aj[i] * aj[i];
     s = wave_sum(s);
-    if (lane == 0) sig[j] = sqrt(s);
+    if (lane == 0) nrm2[j] = sqrt(s);
   }
   __syncthreads();
-  // rank sort (decreasing, ties by index) -> perm[rank] = column
-  for (int j = tid; j < nc; j += NT) {
-    const double sj = sig[j];
+  for (int j = tid; j < k; j += NT) {
+    const double sj = nrm2[j];
     int rk = 0;
-    for (int i = 0; i < nc; ++i) {
-      const double si = sig[i];
+    for (int i = 0; i < k; ++i) {
+      const double si = nrm2[i];
       rk += (si > sj) || (si == sj && i < j);
     }
     perm[rk] = j;
@@ -132,38 +216,62 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   }
   __syncthreads();
   if (tid == 0) {
+    for (int i = k; i < nc; ++i) tk.sigma[i] = 0.0;
     const double eps = tk.delta_scaled * (*tk.norm);
     const double eps2 = eps * eps;
-    int t = nc;
-    double tail = 0.0;
-    for (int i = nc - 1; i >= 1; --i) {
+    int t = k > 0 ? k : 1;
+    double tail = edrop;
+    for (int i = k - 1; i >= 1; --i) {
       tail += tk.sigma[i] * tk.sigma[i];
       if (tail <= eps2) t = i;
       else break;
     }
     if (tk.max_rank > 0 && t > tk.max_rank) t = (int)tk.max_rank;
     if (t < 1) t = 1;
-    if (tk.sigma[0] == 0.0) t = 1;
+    if (k == 0 || tk.sigma[0] == 0.0) t = 1;
     tsel = t;
     *tk.rank_out = t;
-    if (tk.info) *tk.info = sweep;
+    if (tk.info) *tk.info = sweeps;
   }
   __syncthreads();
   const int t = tsel;
+  // position of each original column in the active list (-1 when set aside)
+  for (int j = tid; j < nc; j += NT) nrm2[j] = -1.0;
+  __syncthreads();
+  for (int a = tid; a < k; a += NT) nrm2[act[a]] = (double)a;
+  __syncthreads();
+  const bool degenerate = (k == 0);
+  // W^T: ncol x t
   for (int64_t idx = tid; idx < (int64_t)N * t; idx += NT) {
     const int col = (int)(idx / t), i = (int)(idx - (int64_t)col * t);
-    const int j = perm[i];
-    tk.wt[idx] = tall ? tk.sigma[i] * J[(int64_t)j * nc + col] : A[(int64_t)j * len + col];
+    double v = 0.0;
+    if (!degenerate && i < k) {
+      const int j = perm[i];
+      if (tall) {
+        const int a = (int)nrm2[col];
+        v = (a >= 0) ? tk.sigma[i] * J[(int64_t)j * k + a] : 0.0;
+      } else {
+        v = (col < len) ? A[(int64_t)j * len + col] : 0.0;
+      }
+    }
+    tk.wt[idx] = v;
   }
+  // U_R: kr x t
   for (int64_t idx = tid; idx < (int64_t)kr * t; idx += NT) {
     const int row = (int)(idx / t), i = (int)(idx - (int64_t)row * t);
-    const int j = perm[i];
     double v;
-    if (tall) {
-      const double s = tk.sigma[i];
-      v = (s > 0.0) ? A[(int64_t)j * len + row] / s : (row == i ? 1.0 : 0.0);
+    if (degenerate || i >= k) {
+      v = (row == i) ? 1.0 : 0.0;
     } else {
-      v = J[(int64_t)j * nc + row];
+      const int j = perm[i];
+      if (tall) {
+        const double s = tk.sigma[i];
+        if (s > 0.0) v = (row < len) ? A[(int64_t)j * len + row] / s : 0.0;
+        else v = (row == i) ? 1.0 : 0.0;
+      } else {
+        const int a = (int)nrm2[row];
+        v = (a >= 0) ? J[(int64_t)j * k + a] : 0.0;
+      }
     }
     tk.ur[idx] = v;
   }
@@ -173,7 +281,14 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
 
 hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_svd, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+  static bool ready = false;
+  if (!ready) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_svd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       LDS_DOUBLES * 8);
+    if (e != hipSuccess) return e;
+    ready = true;
+  }
+  hipLaunchKernelGGL(k_svd, dim3(ntasks), dim3(NT), LDS_DOUBLES * 8, s, d_tasks);
   return hipGetLastError();
 }
 
