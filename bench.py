@@ -1,0 +1,163 @@
+"""Benchmark: TT-roundings per second on one MI355X.
+
+Workload: one TT-round of the sum of 20 random rank-10 TTs (order 8, mode
+size 32, term j with every core scaled by 2**-j, input rank 200), at
+delta = 1e-4 in FP32-bulk (headline value) and in FP64, plus FP64 at
+delta = 1e-8.  Inputs are synthetic (seeded) and resident in HBM before the
+timed region.  A step is one rounding; the timed region runs --steps of them
+back to back on one stream, bracketed by device synchronisation.
+
+Only results that meet the metric's condition count: after timing, the
+relative error ||x - x~|| / ||x|| of the last result (computed on the GPU by
+the library: the norm of the lazy sum x - x~) must be <= delta.
+
+The roofline object describes the kernel with the largest share of device
+time, measured live with HIP events on the library's stream during the timed
+region; its achieved rate is the algorithmic flops of its launches divided by
+their summed duration.  cpu_baseline times the FP64 CPU oracle on a bounded
+sample of the same rounding.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published peaks, TFLOP/s
+    "fp64_vector": 78.6, "fp64_mfma": 78.6, "fp32_vector": 157.3, "fp32_mfma": 157.3,
+}
+KINDS = ["qr_factor_leaf", "qr_factor_node", "qr_apply", "svd_jacobi", "contraction_gemm", "tt_dot", "other"]
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    return p.parse_args()
+
+
+def profile_arrays(ctx):
+    lib = ctx.lib
+    lib.tt_ctx_profile.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64),
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    out = {}
+    for k, name in enumerate(KINDS):
+        ms, n, fl, by = C.c_double(), C.c_int64(), C.c_double(), C.c_double()
+        lib.tt_ctx_profile(ctx.h, k, C.byref(ms), C.byref(n), C.byref(fl), C.byref(by))
+        out[name] = {"ms": ms.value, "launches": n.value, "flops": fl.value, "bytes": by.value}
+    return out
+
+
+def run_config(tt, torch, dtype, delta, steps, warmup, profile):
+    import numpy as np
+    from paper_2211_08770_amd import synth
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    terms = synth.sum_of_graded_terms(dtype=npdt)
+    x = [(a, tt.TT.from_cores(c, device="cuda", dtype=dtype)) for a, c in terms]
+    ctx = tt._ctx()
+    ctx.lib.tt_ctx_set_profiling.argtypes = [C.c_void_p, C.c_int]
+    for _ in range(warmup):
+        out = tt.round(x, delta)
+    torch.cuda.synchronize()
+    if profile:
+        ctx.lib.tt_ctx_set_profiling(ctx.h, 1)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = tt.round(x, delta)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = profile_arrays(ctx) if profile else None
+    if profile:
+        ctx.lib.tt_ctx_set_profiling(ctx.h, 0)
+    # validity: ||x - x~|| / ||x|| on the GPU
+    _, nx = tt.round(x, 0.0, return_norm=True)
+    diff = x + [(-1.0, out)]
+    _, nd = tt.round(diff, 0.0, return_norm=True)
+    return {"rate": steps / dt, "ms": 1e3 * dt / steps, "ranks": out.r, "rel_err": nd / nx, "prof": prof}
+
+
+def cpu_baseline(seconds):
+    import numpy as np
+    import oracle
+    from paper_2211_08770_amd import synth
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    terms = synth.sum_of_graded_terms(dtype=np.float32)
+    x = oracle.tt_sum([(a, [c.astype(np.float64) for c in t]) for a, t in terms])
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.tt_round(x, 1e-4)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "TT-roundings/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} FP64 NumPy/LAPACK roundings of the same 20-term sum at delta=1e-4 ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2211_08770_amd import tt
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    tt._load()
+    res32 = run_config(tt, torch, torch.float32, 1e-4, args.steps, args.warmup, profile=True)
+    res64 = run_config(tt, torch, torch.float64, 1e-4, args.steps, args.warmup, profile=False)
+    res64b = run_config(tt, torch, torch.float64, 1e-8, max(args.steps // 2, 1), 1, profile=False)
+    # dominant kernel of the headline configuration
+    prof = res32["prof"]
+    dom = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    name, p = dom
+    achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
+    # FP32-bulk: QR leaves and applies compute in double over float storage; nodes, SVD are FP64
+    peak = PEAK["fp64_vector"]
+    roof = {"bound": "alu", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 5), "traffic": None, "kernel": name,
+            "avg_launch_ms": round(p["ms"] / max(p["launches"], 1), 5), "launches": p["launches"],
+            "share_of_kernel_time": round(p["ms"] / sum(v["ms"] for v in prof.values()), 4)}
+    line = {
+        "metric": "TT-roundings/sec, FP32-bulk vs FP64 at rel.err <= delta",
+        "value": round(res32["rate"], 3) if res32["rel_err"] <= 1e-4 else 0.0,
+        "unit": "TT-roundings/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(res32["ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 bulk (f64 R-tree, SVD, norms)", "data": "synthetic",
+        "config": {"workload": "TT-round of a lazy sum of 20 rank-10 TTs, d=8, n=32, term j scaled 2^-j per core "
+                               "(input rank 200), delta=1e-4",
+                   "global_batch": 1, "seq_len": None, "parallelism": "none (1 GPU)"},
+        "rel_err": res32["rel_err"], "out_ranks": res32["ranks"],
+        "fp64": {"value": round(res64["rate"], 3), "ms_per_step": round(res64["ms"], 4), "rel_err": res64["rel_err"],
+                 "out_ranks": res64["ranks"]},
+        "fp64_delta_1e-8": {"value": round(res64b["rate"], 3), "ms_per_step": round(res64b["ms"], 4),
+                            "rel_err": res64b["rel_err"], "out_ranks": res64b["ranks"]},
+        "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -10,11 +10,11 @@ namespace tto {
 //
 // The tile is row-major m x ncol (ld = ncol).  After factorisation its upper
 // triangle holds R and the strict lower part holds the Householder vectors
-// (unit leading entry implied); tau[j] and the per-panel triangular factors
-// T (blocked WY, Q = (I - V1 T1 V1^T)(I - V2 T2 V2^T)...) are stored beside it.
+// (unit leading entry implied); tau[j] and, per panel of QR_NB reflectors,
+// the upper-triangular T of the compact WY form I - V T V^T are stored beside it.
 // ---------------------------------------------------------------------------
 constexpr int QR_NB = 16;          // panel width
-constexpr int QR_THREADS = 256;
+constexpr int QR_THREADS = 1024;   // 16 waves per tile
 constexpr int QR_MAXROWS = 768;    // LDS panel: QR_MAXROWS x QR_NB doubles = 96 KiB
 
 struct QrTask {
@@ -26,7 +26,7 @@ struct QrTask {
   int32_t m, ncol;        // tile shape
   void* tile;             // row-major m x ncol
   double* tau;            // [min(m, ncol)]
-  void* tmat;             // [npanels][QR_NB][QR_NB] row-major upper triangular T
+  void* tmat;             // [npanels][QR_NB][QR_NB] doubles: T of each panel (I - V T V^T)
 };
 
 // Apply the orthogonal factor of a factored tile:  out = Q * [X; 0].
@@ -120,8 +120,8 @@ struct CopySeg {
 // Launch wrappers (defined in the .hip files).
 // ---------------------------------------------------------------------------
 hipError_t launch_qr_factor(int dtype_src, int dtype_tile, const QrTask* d_tasks, const QrTask* d_children,
-                            int ntasks, hipStream_t s);
-hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tasks, int ntasks,
+                            int ntasks, int max_rows, hipStream_t s);
+hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tasks, int ntasks, int max_rows,
                            hipStream_t s);
 hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s);
 hipError_t launch_gemm(int dtype, const GemmTask* d_tasks, const GemmPart* d_parts, int ntasks,

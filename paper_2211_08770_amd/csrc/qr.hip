@@ -3,44 +3,81 @@
 // the right-to-left orthogonalisation sweep of TT-round and the QR that
 // precedes each small SVD of the left-to-right truncation sweep.
 //
-// One workgroup owns one tile.  The tile lives in global memory (row-major);
-// panels of QR_NB columns are factored in LDS (column-major there, so the
-// per-column reductions read contiguous LDS), the per-panel blocked-WY factor
-// T is formed in LDS, and the trailing columns are updated with
-//   A <- A - V T^T (V^T A)
-// by a 2-D thread split (columns x row groups) whose partial V^T A sums are
-// combined through LDS.
-//
-// A tree node stacks the upper-triangular R factors of its children.  Row i
-// of a stacked triangle is zero left of column i, so the Householder vectors
-// of the panel starting at column p0 only touch, in each child block, the
-// rows i < p0 + QR_NB: every panel works on that compacted row list only.
+// One workgroup (4 waves) owns one tile held row-major in global memory.
+//  * Panels of QR_NB = 16 columns are factored in LDS (column-major there);
+//    panel column c belongs to wave c, which computes the reflector of the
+//    current column itself and fuses its own dot product into the same pass,
+//    so a column costs one workgroup barrier; the reflector columns are
+//    scaled in one parallel pass at the end of the panel.
+//  * The blocked update of the trailing columns uses the 16x16x4 MFMA
+//    (f64 for FP64 tiles, f32 for FP32-bulk tiles) for all three products of
+//    Q^T A = A - V T^T (V^T A): W = V^T A, Y = T^T W and A -= V Y, where the
+//    panel's reflectors H_0 ... H_15 = I - V T V^T (compact WY form; T upper
+//    triangular, formed once per panel from S = V^T V and tau).  T is stored
+//    per panel; applying Q uses Y = T W instead.
+//  * A tree node stacks the upper-triangular R factors of its children.  Row
+//    i of a stacked triangle is zero left of column i, so the reflectors of
+//    the panel starting at column p0 only touch, in each child block, the
+//    rows i < p0 + 16: every panel works on that compacted row list.
 #include "common.h"
 
 namespace tto {
 
 namespace {
 
-constexpr int NB = QR_NB;
-constexpr int NT = QR_THREADS;
+constexpr int NB = QR_NB;       // 16: panel width = MFMA tile edge
+constexpr int NT = QR_THREADS;  // 1024 = 16 waves
+constexpr int NWV = NT / 64;
+static_assert(NWV >= QR_NB, "the panel factorisation gives every panel column its own wave");
 constexpr int MAXR = QR_MAXROWS;
 
-__device__ inline double block_sum(double v, double* red) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < NT / 64; ++i) s += red[i];
-  __syncthreads();
-  return s;
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// 16x16x4 MFMA in the precision of the tile.  Operands: lane l holds
+// A[l%16][l/16] and B[l/16][l%16].  Result row of register v for lane l:
+// f64: 4v + l/16 ; f32: 4(l/16) + v ; result column l%16.
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+  typedef v4d acc_t;
+  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <> struct Mma<float> {
+  typedef v4f acc_t;
+  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// DPP move of a double within 16-lane rows (GFX9 DPP controls).
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double readlane_d(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+// Sum over the 64 lanes of a wave, same value (and same rounding) in every lane:
+// quad swaps and row rotations give every lane its 16-lane row sum, then the
+// four row sums are added in a fixed order.
+__device__ inline double wave_sum(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm(1,0,3,2)
+  v += dpp_d<0x4E>(v);    // quad_perm(2,3,0,1)
+  v += dpp_d<0x124>(v);   // row_ror:4
+  v += dpp_d<0x128>(v);   // row_ror:8
+  return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
 }
 
 // Active tile rows of the panel [p0, p0 + nb) in increasing order; returns the count.
 // Dense tile (nchild == 0): rows p0..m-1.  Node: in child block b (offset
 // b*kc0, size kc_b) the local rows i with max(0, p0 - off_b) <= i < min(kc_b, p0 + nb).
-__device__ int panel_rows(int* rowl, int* cnt, int m, int nchild, int kc0, int kc_last, int p0, int nb) {
+__device__ int panel_rows(int* rowl, int* bstart, int m, int nchild, int kc0, int kc_last, int p0, int nb) {
   const int tid = threadIdx.x;
   if (nchild == 0) {
     for (int r = tid; r < m - p0; r += NT) rowl[r] = p0 + r;
@@ -54,158 +91,153 @@ __device__ int panel_rows(int* rowl, int* cnt, int m, int nchild, int kc0, int k
       const int kcb = (b == nchild - 1) ? kc_last : kc0;
       const int lo = (p0 - off) > 0 ? (p0 - off) : 0;
       const int hi = kcb < (p0 + nb) ? kcb : (p0 + nb);
-      for (int i = lo; i < hi; ++i) rowl[c++] = off + i;
+      bstart[b] = c;
+      c += (hi > lo) ? (hi - lo) : 0;
     }
-    *cnt = c;
+    bstart[nchild] = c;
   }
   __syncthreads();
-  const int c = *cnt;
+  for (int b = 0; b < nchild; ++b) {
+    const int off = b * kc0;
+    const int lo = (p0 - off) > 0 ? (p0 - off) : 0;
+    const int c0 = bstart[b], cnt = bstart[b + 1] - c0;
+    for (int i = tid; i < cnt; i += NT) rowl[c0 + i] = off + lo + i;
+  }
+  const int total = bstart[nchild];
   __syncthreads();
-  return c;
+  return total;
 }
 
-// A rows rowl[0..rows) x columns c0..c0+ncols (row-major, leading dimension lda)
-//   <- A - V op(T) (V^T A),  op(T) = T^T when TRANS.
-// V: LDS column-major [NB][ldv] over the compacted rows (explicit unit
-// diagonal, zeros above; columns >= nb are zero); T: LDS NB x NB.
-// wred: LDS scratch of NT * NB doubles.
-template <bool TRANS, typename TA, typename TV>
-__device__ void block_reflect(TA* __restrict__ A, int64_t lda, const int* __restrict__ rowl, int c0, int ncols,
-                              int rows, const TV* __restrict__ V, int ldv, const double* __restrict__ T,
-                              double* __restrict__ wred) {
-  const int tid = threadIdx.x;
-  const int tc = ncols < NT ? ncols : NT;
-  if (tc <= 0) return;
-  const int G = NT / tc;
-  for (int cb = 0; cb < ncols; cb += tc) {
-    const int cl = tid % tc;
-    const int g = tid / tc;
-    const int c = cb + cl;
-    const bool active = (g < G) && (c < ncols);
-    double w[NB];
+// B operand of K-step s (rows 4s..4s+3) taken from a 16x16 MFMA result in
+// D layout: lane l needs D[4s + l/16][l%16].
+__device__ inline double bop(const v4d& d, int s) { return d[s]; }   // f64: same lane, register s
+__device__ inline float bop(const v4f& d, int s) {                 // f32: lane 16s + l%16, register l/16
+  const int lane = threadIdx.x & 63;
+  const int src = 16 * s + (lane & 15);
+  const float t0 = __shfl(d[0], src, 64), t1 = __shfl(d[1], src, 64);
+  const float t2 = __shfl(d[2], src, 64), t3 = __shfl(d[3], src, 64);
+  const int q = lane >> 4;
+  return q == 0 ? t0 : (q == 1 ? t1 : (q == 2 ? t2 : t3));
+}
+
+// Trailing block update of the rows rowl[0..rows) x columns [c0, ncol) of A:
+//   FORWARD:  A <- Q^T A = A - V T^T (V^T A)   (factorisation)
+//   !FORWARD: A <- Q A   = A - V T (V^T A)     (application)
+// V: LDS column-major [NB][ldv] with explicit unit diagonal and zeros above;
+// Tm: LDS NB x NB row-major upper-triangular T (zero beyond the panel width).
+template <bool FORWARD, typename TA, typename TV>
+__device__ void block_update(TA* __restrict__ A, int64_t lda, const int* __restrict__ rowl, int c0, int ncol,
+                             int rows, const TV* __restrict__ V, int ldv, const double* __restrict__ Tm) {
+  typedef Mma<TV> M;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ntile = (ncol - c0 + NB - 1) / NB;
+  // A operand of op(T) for the 4 K-steps: op(T)[l%16][4s + l/16]
+  TV ta[4];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) w[k] = 0.0;
-    if (active) {
-      TA* col = A + (c0 + c);
-      int r = g;
-      for (; r + 3 * G < rows; r += 4 * G) {
-        const double a0 = (double)col[(int64_t)rowl[r] * lda];
-        const double a1 = (double)col[(int64_t)rowl[r + G] * lda];
-        const double a2 = (double)col[(int64_t)rowl[r + 2 * G] * lda];
-        const double a3 = (double)col[(int64_t)rowl[r + 3 * G] * lda];
+  for (int s = 0; s < 4; ++s) {
+    const int i = lane & 15, k = 4 * s + (lane >> 4);
+    ta[s] = (TV)(FORWARD ? Tm[k * NB + i] : Tm[i * NB + k]);
+  }
+  for (int tile = wave; tile < ntile; tile += NWV) {
+    const int cc = c0 + tile * NB;
+    const int col = cc + (lane & 15);
+    const bool colok = col < ncol;
+    // W = V^T A  (16 reflectors x 16 columns), K = rows in steps of 4
+    // four independent accumulators keep four MFMAs in flight
+    typename M::acc_t w0 = M::zero(), w1 = M::zero(), w2 = M::zero(), w3 = M::zero();
+    constexpr int U = 12;   // K-steps whose global loads are issued together
+    for (int r0 = 0; r0 < rows; r0 += 4 * U) {
+      TV b[U];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-          const TV* vk = V + k * ldv;
-          w[k] += (double)vk[r] * a0 + (double)vk[r + G] * a1 + (double)vk[r + 2 * G] * a2 +
-                  (double)vk[r + 3 * G] * a3;
-        }
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + 4 * u + (lane >> 4);
+        b[u] = (r < rows && colok) ? (TV)A[(int64_t)rowl[r] * lda + col] : (TV)0;
       }
-      for (; r < rows; r += G) {
-        const double a = (double)col[(int64_t)rowl[r] * lda];
 #pragma unroll
-        for (int k = 0; k < NB; ++k) w[k] += (double)V[k * ldv + r] * a;
-      }
-    }
-    double* slot = wred + (size_t)(g * tc + cl) * NB;
-    if (G > 1) {
-      if (g < G) {
-#pragma unroll
-        for (int k = 0; k < NB; ++k) slot[k] = w[k];
-      }
-      __syncthreads();
-      if (active) {
-#pragma unroll
-        for (int k = 0; k < NB; ++k) w[k] = 0.0;
-#pragma unroll 1
-        for (int gg = 0; gg < G; ++gg) {
-#pragma unroll
-          for (int k = 0; k < NB; ++k) w[k] += wred[(gg * tc + cl) * NB + k];
-        }
-      }
-      __syncthreads();
-    }
-    if (active) {
-      // w2 = op(T) w, one output at a time through the thread's LDS slot
-#pragma unroll 1
-      for (int i = 0; i < NB; ++i) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < NB; ++k) s += (TRANS ? T[k * NB + i] : T[i * NB + k]) * w[k];
-        slot[i] = s;
-      }
-      double w2[NB];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) w2[k] = slot[k];
-      TA* col = A + (c0 + c);
-      int r = g;
-      for (; r + 3 * G < rows; r += 4 * G) {
-        const int64_t i0 = (int64_t)rowl[r] * lda, i1 = (int64_t)rowl[r + G] * lda;
-        const int64_t i2 = (int64_t)rowl[r + 2 * G] * lda, i3 = (int64_t)rowl[r + 3 * G] * lda;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-          const TV* vk = V + k * ldv;
-          s0 += (double)vk[r] * w2[k];
-          s1 += (double)vk[r + G] * w2[k];
-          s2 += (double)vk[r + 2 * G] * w2[k];
-          s3 += (double)vk[r + 3 * G] * w2[k];
-        }
-        const double a0 = (double)col[i0], a1 = (double)col[i1], a2 = (double)col[i2], a3 = (double)col[i3];
-        col[i0] = (TA)(a0 - s0);
-        col[i1] = (TA)(a1 - s1);
-        col[i2] = (TA)(a2 - s2);
-        col[i3] = (TA)(a3 - s3);
-      }
-      for (; r < rows; r += G) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < NB; ++k) s += (double)V[k * ldv + r] * w2[k];
-        const int64_t ia = (int64_t)rowl[r] * lda;
-        col[ia] = (TA)((double)col[ia] - s);
+      for (int u = 0; u < U; u += 4) {
+        const int r = r0 + 4 * u + (lane >> 4);
+        const TV a0 = (r < rows) ? V[(lane & 15) * ldv + r] : (TV)0;
+        const TV a1 = (r + 4 < rows) ? V[(lane & 15) * ldv + r + 4] : (TV)0;
+        const TV a2 = (r + 8 < rows) ? V[(lane & 15) * ldv + r + 8] : (TV)0;
+        const TV a3 = (r + 12 < rows) ? V[(lane & 15) * ldv + r + 12] : (TV)0;
+        w0 = M::mma(a0, b[u], w0);
+        w1 = M::mma(a1, b[u + 1], w1);
+        w2 = M::mma(a2, b[u + 2], w2);
+        w3 = M::mma(a3, b[u + 3], w3);
       }
     }
-    __syncthreads();
+    const typename M::acc_t w = (w0 + w1) + (w2 + w3);
+    // Y = op(T) W
+    typename M::acc_t y = M::zero();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) y = M::mma(ta[s], bop(w, s), y);
+    TV yb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) yb[s] = bop(y, s);
+    // A -= V Y, 16 rows at a time; the A values of UB row blocks are loaded together
+    constexpr int UB = 2;
+    for (int rb0 = 0; rb0 < rows; rb0 += NB * UB) {
+      double old[UB][4];
+      int idx[UB][4];   // tile element offsets (a tile holds < 2^31 elements)
+#pragma unroll
+      for (int ub = 0; ub < UB; ++ub) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = rb0 + NB * ub + M::row(lane, v);
+          const bool ok = colok && r < rows;
+          idx[ub][v] = ok ? (int)((int64_t)rowl[r] * lda + col) : -1;
+          old[ub][v] = ok ? (double)A[idx[ub][v]] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int ub = 0; ub < UB; ++ub) {
+        const int ra = rb0 + NB * ub + (lane & 15);
+        typename M::acc_t d = M::zero();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const TV a = (ra < rows) ? V[(4 * s + (lane >> 4)) * ldv + ra] : (TV)0;
+          d = M::mma(a, yb[s], d);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (idx[ub][v] >= 0) A[idx[ub][v]] = (TA)(old[ub][v] - (double)d[v]);
+      }
+    }
   }
 }
 
-// Build the upper-triangular T of Q = H_0 ... H_{nb-1} = I - V T V^T
-// (forward, column-wise blocked WY).  S: LDS scratch NB*NB doubles.
-template <typename TV>
-__device__ void form_t(const TV* __restrict__ V, int ldv, int rows, int nb, const double* __restrict__ tau,
-                       double* __restrict__ T, double* __restrict__ S) {
+// T of the compact WY form H_0 ... H_15 = I - V T V^T (forward, column-wise):
+// T_ii = tau_i, T_{a,i} = -tau_i sum_{b=a}^{i-1} T_ab S_bi.  Lane a of wave 0
+// builds row a; S (LDS, strictly upper V^T V) and tau (LDS) are inputs.
+__device__ void form_t(const double* __restrict__ S, const double* __restrict__ tau, double* __restrict__ Tm) {
   const int tid = threadIdx.x;
-  if (tid < NB * NB) {
-    const int a = tid / NB, b = tid % NB;
-    double s = 0.0;
-    if (a < b && b < nb) {
-      for (int r = b; r < rows; ++r) s += (double)V[a * ldv + r] * (double)V[b * ldv + r];
+  if (tid < NB) {
+    const int a = tid;
+    double row[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int b = 0; b < i; ++b) acc += row[b] * S[b * NB + i];
+      row[i] = (a < i) ? -tau[i] * acc : (a == i ? tau[i] : 0.0);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    S[tid] = s;
-    T[tid] = 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) Tm[a * NB + i] = row[i];
   }
-  __syncthreads();
-  if (tid == 0) {
-    for (int i = 0; i < nb; ++i) {
-      const double ti = tau[i];
-      T[i * NB + i] = ti;
-      for (int a = 0; a < i; ++a) {
-        double s = 0.0;
-        for (int b = a; b < i; ++b) s += T[a * NB + b] * S[b * NB + i];
-        T[a * NB + i] = -ti * s;
-      }
-    }
-  }
-  __syncthreads();
 }
 
 template <typename TS, typename TT>
 __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tasks,
-                                                  const QrTask* __restrict__ children) {
+                                                  const QrTask* __restrict__ children, int ldv) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int rowl[MAXR];
-  __shared__ int rcnt;
+  __shared__ int bstart[MAXR + 1];
+  __shared__ double S[NB * NB];
+  __shared__ double Tm[NB * NB];
+  __shared__ double taus[NB], pscal[NB], pbeta[NB];
   const QrTask tk = tasks[blockIdx.x];
-  const int m = tk.m, N = tk.ncol, tid = threadIdx.x;
+  const int m = tk.m, N = tk.ncol, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   TT* A = (TT*)tk.tile;
 
   // ---- fill the tile
@@ -233,96 +265,127 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   __syncthreads();
 
   const int kmax = m < N ? m : N;
-  const int ldp = MAXR;
-  TT* P = (TT*)smem;                                               // NB * MAXR
-  double* T = (double*)(smem + (((size_t)NB * ldp * sizeof(TT) + 15) & ~(size_t)15));  // NB*NB
-  double* S = T + NB * NB;                                         // NB*NB
-  double* red = S + NB * NB;                                       // 16
-  double* taus = red + 16;                                         // NB
-  double* wred = taus + NB;                                        // NT*NB
-
+  TT* P = (TT*)smem;   // NB columns x ldv rows
   for (int p0 = 0, pi = 0; p0 < kmax; p0 += NB, ++pi) {
     const int nb = (kmax - p0) < NB ? (kmax - p0) : NB;
-    const int rows = panel_rows(rowl, &rcnt, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
-    // ---- load panel (zero-padded to NB columns)
+    const int rows = panel_rows(rowl, bstart, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
     for (int idx = tid; idx < rows * NB; idx += NT) {
       const int r = idx / NB, jj = idx - r * NB;
-      P[jj * ldp + r] = (jj < nb) ? A[(int64_t)rowl[r] * N + p0 + jj] : (TT)0;
+      P[jj * ldv + r] = (jj < nb) ? A[(int64_t)rowl[r] * N + p0 + jj] : (TT)0;
     }
     __syncthreads();
-    // ---- unblocked Householder on the panel (pivot of column jj is compact row jj)
+    // ---- panel: wave jj and the waves owning the later panel columns (column c
+    // belongs to wave c) each compute the reflector of column jj; the owner of
+    // column c fuses its dot product into the same pass and applies the update.
+    // The scaling of column jj is written one step later by wave jj (nobody
+    // reads column jj meanwhile).  One workgroup barrier per column.
+    constexpr int RT = (MAXR + 63) / 64;   // rows per lane, predicated
     for (int jj = 0; jj < nb; ++jj) {
-      TT* col = P + jj * ldp;
-      double part = 0.0;
-      for (int r = jj + 1 + tid; r < rows; r += NT) {
-        const double v = (double)col[r];
-        part += v * v;
-      }
-      const double sigma = block_sum(part, red);
-      const double alpha = (double)col[jj];
-      double tau = 0.0, beta = alpha, scal = 0.0;
-      if (sigma != 0.0) {
-        const double nrm = sqrt(alpha * alpha + sigma);
-        beta = (alpha >= 0.0) ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-      __syncthreads();
-      if (sigma != 0.0) {
-        for (int r = jj + 1 + tid; r < rows; r += NT) col[r] = (TT)((double)col[r] * scal);
-      }
-      if (tid == 0) {
-        col[jj] = (TT)beta;
-        taus[jj] = tau;
-      }
-      __syncthreads();
-      {
-        const int c = jj + 1 + (tid >> 4);
-        const int g = tid & 15;
-        double w = 0.0;
-        if (c < nb) {
-          const TT* pc = P + c * ldp;
-          if (g == 0) w = (double)pc[jj];
-          for (int r = jj + 1 + g; r < rows; r += 16) w += (double)col[r] * (double)pc[r];
+      if (wave >= jj && wave < nb) {
+        const TT* cj = P + jj * ldv;
+        TT* pc = P + wave * ldv;           // the column this wave owns (unused when wave == jj)
+        const bool own = wave > jj;
+        double x[RT], y[RT];
+        double ss = 0.0, dd = 0.0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const int r = jj + 1 + lane + 64 * t;
+          const bool ok = r < rows;
+          x[t] = ok ? (double)cj[r] : 0.0;
+          y[t] = (ok && own) ? (double)pc[r] : 0.0;
+          ss += x[t] * x[t];
+          dd += x[t] * y[t];
         }
-        for (int off = 8; off > 0; off >>= 1) w += __shfl_xor(w, off, 16);
-        if (c < nb && tau != 0.0) {
-          TT* pc = P + c * ldp;
+        const double sigma = wave_sum(ss);
+        const double dotx = own ? wave_sum(dd) : 0.0;
+        const double alpha = (double)cj[jj];
+        double tau = 0.0, beta = alpha, scal = 0.0;
+        if (sigma != 0.0) {
+          const double nrm = sqrt(alpha * alpha + sigma);
+          beta = (alpha >= 0.0) ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+          scal = 1.0 / (alpha - beta);
+        }
+        if (own && tau != 0.0) {
+          const double w = scal * dotx + (double)pc[jj];
           const double tw = tau * w;
-          if (g == 0) pc[jj] = (TT)((double)pc[jj] - tw);
-          for (int r = jj + 1 + g; r < rows; r += 16) pc[r] = (TT)((double)pc[r] - tw * (double)col[r]);
+#pragma unroll
+          for (int t = 0; t < RT; ++t) {
+            const int r = jj + 1 + lane + 64 * t;
+            if (r < rows) pc[r] = (TT)(y[t] - tw * scal * x[t]);
+          }
+          if (lane == 0) pc[jj] = (TT)((double)pc[jj] - tw);
+        }
+        if (wave == jj && lane == 0) {
+          taus[jj] = tau;
+          pscal[jj] = scal;
+          pbeta[jj] = beta;
         }
       }
       __syncthreads();
     }
+    // scale the reflector columns and put beta on the diagonal, all columns at once
+    for (int idx = tid; idx < rows * nb; idx += NT) {
+      const int jj = idx / rows, r = idx - jj * rows;
+      TT* pc = P + jj * ldv;
+      if (r == jj) pc[r] = (TT)pbeta[jj];
+      else if (r > jj && taus[jj] != 0.0) pc[r] = (TT)((double)pc[r] * pscal[jj]);
+    }
+    __syncthreads();
     // ---- write the factored panel back, keep tau
     for (int idx = tid; idx < rows * nb; idx += NT) {
       const int r = idx / nb, jj = idx - r * nb;
-      A[(int64_t)rowl[r] * N + p0 + jj] = P[jj * ldp + r];
+      A[(int64_t)rowl[r] * N + p0 + jj] = P[jj * ldv + r];
     }
     if (tid < nb) tk.tau[p0 + tid] = taus[tid];
+    if (tid >= nb && tid < NB) taus[tid] = 0.0;
     __syncthreads();
-    // ---- explicit V (unit diagonal, zeros above)
+    // ---- explicit V (unit diagonal, zeros above; padded columns zero)
     for (int idx = tid; idx < NB * NB; idx += NT) {
       const int jj = idx / NB, r = idx - jj * NB;
-      if (r <= jj && r < rows) P[jj * ldp + r] = (r == jj && jj < nb) ? (TT)1 : (TT)0;
+      if (r <= jj && r < rows) P[jj * ldv + r] = (r == jj && jj < nb) ? (TT)1 : (TT)0;
     }
     __syncthreads();
-    form_t<TT>(P, ldp, rows, nb, taus, T, S);
-    if (tid < NB * NB) ((double*)tk.tmat)[(size_t)pi * NB * NB + tid] = T[tid];
+    // ---- S = V^T V on MFMA (wave 0; both operands are V), strictly upper part kept, then T
+    if (wave == 0) {
+      typedef Mma<TT> M;
+      typename M::acc_t c0 = M::zero(), c1 = M::zero(), c2 = M::zero(), c3 = M::zero();
+      for (int r0 = 0; r0 < rows; r0 += 16) {
+        const int r = r0 + (lane >> 4);
+        const TT a0 = (r < rows) ? P[(lane & 15) * ldv + r] : (TT)0;
+        const TT a1 = (r + 4 < rows) ? P[(lane & 15) * ldv + r + 4] : (TT)0;
+        const TT a2 = (r + 8 < rows) ? P[(lane & 15) * ldv + r + 8] : (TT)0;
+        const TT a3 = (r + 12 < rows) ? P[(lane & 15) * ldv + r + 12] : (TT)0;
+        c0 = M::mma(a0, a0, c0);
+        c1 = M::mma(a1, a1, c1);
+        c2 = M::mma(a2, a2, c2);
+        c3 = M::mma(a3, a3, c3);
+      }
+      const typename M::acc_t acc = (c0 + c1) + (c2 + c3);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = M::row(lane, v), j = lane & 15;
+        S[i * NB + j] = (i < j && j < nb) ? (double)acc[v] : 0.0;
+      }
+    }
+    __syncthreads();
+    form_t(S, taus, Tm);
+    __syncthreads();
+    if (tid < NB * NB) ((double*)tk.tmat)[(size_t)pi * NB * NB + tid] = Tm[tid];
     // ---- trailing update  A <- Q_p^T A  on the panel's rows
     const int c0 = p0 + nb;
-    if (c0 < N) block_reflect<true, TT, TT>(A, N, rowl, c0, N - c0, rows, P, ldp, T, wred);
+    if (c0 < N) block_update<true, TT, TT>(A, N, rowl, c0, N, rows, P, ldv, Tm);
     __syncthreads();
   }
 }
 
-// out = Q [X; 0] for one factored tile; Q = (I - V_0 T_0 V_0^T)(I - V_1 T_1 V_1^T) ...
+// out = Q [X; 0] for one factored tile; Q = Q_0 Q_1 ... (panels applied last to first)
 template <typename TT, typename TO>
-__global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ tasks) {
+__global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ tasks, int ldv) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int rowl[MAXR];
-  __shared__ int rcnt;
+  __shared__ int bstart[MAXR + 1];
+  __shared__ double Tm[NB * NB];
   const ApplyTask tk = tasks[blockIdx.x];
   const int m = tk.m, N = tk.ncol, t = tk.t, tid = threadIdx.x;
   const TT* tile = (const TT*)tk.tile;
@@ -333,15 +396,12 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
     W[idx] = (r < tk.k_in) ? tk.x[r * tk.x_ld + c] : 0.0;
   }
   __syncthreads();
-  const int ldp = MAXR;
   TT* V = (TT*)smem;
-  double* T = (double*)(smem + (((size_t)NB * ldp * sizeof(TT) + 15) & ~(size_t)15));
-  double* wred = T + NB * NB;
   const int np = (tk.kq + NB - 1) / NB;
   for (int pi = np - 1; pi >= 0; --pi) {
     const int p0 = pi * NB;
     const int nb = (tk.kq - p0) < NB ? (tk.kq - p0) : NB;
-    const int rows = panel_rows(rowl, &rcnt, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
+    const int rows = panel_rows(rowl, bstart, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
     for (int idx = tid; idx < rows * NB; idx += NT) {
       const int r = idx / NB, jj = idx - r * NB;
       TT v = (TT)0;
@@ -349,11 +409,11 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
         if (r == jj) v = (TT)1;
         else if (r > jj) v = tile[(int64_t)rowl[r] * N + p0 + jj];
       }
-      V[jj * ldp + r] = v;
+      V[jj * ldv + r] = v;
     }
-    if (tid < NB * NB) T[tid] = ((const double*)tk.tmat)[(size_t)pi * NB * NB + tid];
+    if (tid < NB * NB) Tm[tid] = ((const double*)tk.tmat)[(size_t)pi * NB * NB + tid];
     __syncthreads();
-    block_reflect<false, double, TT>(W, t, rowl, 0, t, rows, V, ldp, T, wred);
+    block_update<false, double, TT>(W, t, rowl, 0, t, rows, V, ldv, Tm);
     __syncthreads();
   }
   if (tk.to_out) {
@@ -365,12 +425,7 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
   }
 }
 
-size_t factor_smem(int elt) {
-  return (((size_t)NB * MAXR * elt + 15) & ~(size_t)15) + sizeof(double) * (2 * NB * NB + 16 + NB + NT * NB);
-}
-size_t apply_smem(int elt) {
-  return (((size_t)NB * MAXR * elt + 15) & ~(size_t)15) + sizeof(double) * (NB * NB + NT * NB);
-}
+size_t panel_smem(int elt, int ldv) { return ((size_t)NB * ldv * elt + 15) & ~(size_t)15; }
 
 template <typename K>
 hipError_t raise_lds(K kernel, size_t bytes) {
@@ -380,44 +435,50 @@ hipError_t raise_lds(K kernel, size_t bytes) {
 }  // namespace
 
 hipError_t launch_qr_factor(int dtype_src, int dtype_tile, const QrTask* d_tasks, const QrTask* d_children,
-                            int ntasks, hipStream_t s) {
+                            int ntasks, int max_rows, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
+  const int ldv = max_rows + 1;
   dim3 grid(ntasks), block(NT);
   if (dtype_tile == 0) {
-    const size_t sm = factor_smem(8);
-    if (dtype_src == 0) hipLaunchKernelGGL((k_qr_factor<double, double>), grid, block, sm, s, d_tasks, d_children);
-    else hipLaunchKernelGGL((k_qr_factor<float, double>), grid, block, sm, s, d_tasks, d_children);
+    const size_t sm = panel_smem(8, ldv);
+    if (dtype_src == 0)
+      hipLaunchKernelGGL((k_qr_factor<double, double>), grid, block, sm, s, d_tasks, d_children, ldv);
+    else
+      hipLaunchKernelGGL((k_qr_factor<float, double>), grid, block, sm, s, d_tasks, d_children, ldv);
   } else {
-    const size_t sm = factor_smem(4);
-    hipLaunchKernelGGL((k_qr_factor<float, float>), grid, block, sm, s, d_tasks, d_children);
+    const size_t sm = panel_smem(4, ldv);
+    hipLaunchKernelGGL((k_qr_factor<float, float>), grid, block, sm, s, d_tasks, d_children, ldv);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tasks, int ntasks, hipStream_t s) {
+hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tasks, int ntasks, int max_rows,
+                           hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
+  const int ldv = max_rows + 1;
   dim3 grid(ntasks), block(NT);
   if (dtype_tile == 0) {
-    const size_t sm = apply_smem(8);
-    if (dtype_out == 0) hipLaunchKernelGGL((k_qr_apply<double, double>), grid, block, sm, s, d_tasks);
-    else hipLaunchKernelGGL((k_qr_apply<double, float>), grid, block, sm, s, d_tasks);
+    const size_t sm = panel_smem(8, ldv);
+    if (dtype_out == 0) hipLaunchKernelGGL((k_qr_apply<double, double>), grid, block, sm, s, d_tasks, ldv);
+    else hipLaunchKernelGGL((k_qr_apply<double, float>), grid, block, sm, s, d_tasks, ldv);
   } else {
-    const size_t sm = apply_smem(4);
-    if (dtype_out == 0) hipLaunchKernelGGL((k_qr_apply<float, double>), grid, block, sm, s, d_tasks);
-    else hipLaunchKernelGGL((k_qr_apply<float, float>), grid, block, sm, s, d_tasks);
+    const size_t sm = panel_smem(4, ldv);
+    if (dtype_out == 0) hipLaunchKernelGGL((k_qr_apply<float, double>), grid, block, sm, s, d_tasks, ldv);
+    else hipLaunchKernelGGL((k_qr_apply<float, float>), grid, block, sm, s, d_tasks, ldv);
   }
   return hipGetLastError();
 }
 
 hipError_t qr_kernels_init() {
   hipError_t e;
-  if ((e = raise_lds(k_qr_factor<double, double>, factor_smem(8))) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_factor<float, double>, factor_smem(8))) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_factor<float, float>, factor_smem(4))) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_apply<double, double>, apply_smem(8))) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_apply<double, float>, apply_smem(8))) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_apply<float, double>, apply_smem(4))) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_apply<float, float>, apply_smem(4))) != hipSuccess) return e;
+  const size_t s8 = panel_smem(8, MAXR + 1), s4 = panel_smem(4, MAXR + 1);
+  if ((e = raise_lds(k_qr_factor<double, double>, s8)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_factor<float, double>, s8)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_factor<float, float>, s4)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<double, double>, s8)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<double, float>, s8)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<float, double>, s4)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<float, float>, s4)) != hipSuccess) return e;
   return hipSuccess;
 }
 

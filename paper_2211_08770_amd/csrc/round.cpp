@@ -362,7 +362,9 @@ tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
             by += 2.0 * (double)q.m * q.ncol * (pass == 0 ? 8.0 : 4.0);
           }
         const int pr = prof_begin(c, l == 0 ? PK_QR_LEAF : PK_QR_NODE, fl, by);
-        hipError_t e = launch_qr_factor(srcd, pass == 0 ? 0 : 1, dt, dc, (int)tasks.size(), c->stream);
+        int max_rows = 1;
+        for (const QrTask& q : tasks) max_rows = std::max(max_rows, (int)q.m);
+        hipError_t e = launch_qr_factor(srcd, pass == 0 ? 0 : 1, dt, dc, (int)tasks.size(), max_rows, c->stream);
         prof_end(c, pr);
         if (e != hipSuccess) return hip_fail(c, e, "qr_factor");
       }
@@ -392,7 +394,9 @@ tt_status launch_apply_plans(tt_ctx* c, std::vector<std::vector<ApplyLevel>>& pl
           by += (double)a.m * a.ncol * (tdt == 0 ? 8.0 : 4.0) + 2.0 * (double)a.m * a.t * 8.0;
         }
       const int pr = prof_begin(c, PK_QR_APPLY, fl, by);
-      hipError_t e = launch_qr_apply(tdt, out_dtype, dt, (int)tasks.size(), c->stream);
+      int max_rows = 1;
+      for (const ApplyTask& a : tasks) max_rows = std::max(max_rows, (int)a.m);
+      hipError_t e = launch_qr_apply(tdt, out_dtype, dt, (int)tasks.size(), max_rows, c->stream);
       prof_end(c, pr);
       if (e != hipSuccess) return hip_fail(c, e, "qr_apply");
     }

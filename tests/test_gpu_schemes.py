@@ -78,13 +78,16 @@ def test_gram_reports_not_spd():
     assert ei.value.status == "TT_ENOTSPD"
 
 
-def test_breakdown_on_dependent_input():
+def test_breakdown_on_zero_vector():
+    # an exactly zero input leaves p = 0 after projection and rounding: ||p|| = 0
     tt = need_gpu()
     X, C, M = conditioned_inputs(520, 3, 3, 4, 2, 1e2)
-    X.append(list(X[0]))
+    X.append([(0.0, x) for _, x in X[0]])
     A = [dev_sum(s) for s in X]
-    with pytest.raises(tt.TTError):
-        tt.orthogonalize("cgs", A, 0.0)
+    for scheme in ("cgs", "mgs2"):
+        with pytest.raises(tt.TTError) as ei:
+            tt.orthogonalize(scheme, A, 1e-8)
+        assert ei.value.status == "TT_EBREAKDOWN"
 
 
 def test_rank_guard_stops_with_status():
