@@ -3,18 +3,23 @@
 // the right-to-left orthogonalisation sweep of TT-round and the QR that
 // precedes each small SVD of the left-to-right truncation sweep.
 //
-// One workgroup (4 waves) owns one tile held row-major in global memory.
-//  * Panels of QR_NB = 16 columns are factored in LDS (column-major there);
-//    panel column c belongs to wave c, which computes the reflector of the
-//    current column itself and fuses its own dot product into the same pass,
-//    so a column costs one workgroup barrier; the reflector columns are
-//    scaled in one parallel pass at the end of the panel.
+// One workgroup (16 waves) owns one tile held row-major in global memory.
+//  * Panels of QR_NB = 16 columns: panel column c lives in the registers of
+//    wave c (lane l holds rows l, l + 64, ...), in double.  For column j the
+//    owner publishes the column in LDS; every wave reads it, forms the
+//    reflector itself (same arithmetic, same result in every wave) and
+//    reduces, in one pass over its rows, the squared norm and the dot product
+//    with its own column: waves right of j update their column, waves left of
+//    j (already finished) produce the entries S(c, j) of V^T V for the compact
+//    WY form.  One workgroup barrier per column.
 //  * The blocked update of the trailing columns uses the 16x16x4 MFMA
 //    (f64 for FP64 tiles, f32 for FP32-bulk tiles) for all three products of
 //    Q^T A = A - V T^T (V^T A): W = V^T A, Y = T^T W and A -= V Y, where the
-//    panel's reflectors H_0 ... H_15 = I - V T V^T (compact WY form; T upper
-//    triangular, formed once per panel from S = V^T V and tau).  T is stored
-//    per panel; applying Q uses Y = T W instead.
+//    panel's reflectors H_0 ... H_15 = I - V T V^T (T upper triangular, formed
+//    from S and tau).  T is stored per panel; applying Q uses Y = T W instead.
+//    When the trailing block has fewer 16-column tiles than there are waves,
+//    the rows of each tile are split over several waves whose partial V^T A
+//    are summed in LDS, so every wave has work.
 //  * A tree node stacks the upper-triangular R factors of its children.  Row
 //    i of a stacked triangle is zero left of column i, so the reflectors of
 //    the panel starting at column p0 only touch, in each child block, the
@@ -30,6 +35,9 @@ constexpr int NT = QR_THREADS;  // 1024 = 16 waves
 constexpr int NWV = NT / 64;
 static_assert(NWV >= QR_NB, "the panel factorisation gives every panel column its own wave");
 constexpr int MAXR = QR_MAXROWS;
+// LDS scratch after the panel: two column buffers during the panel
+// factorisation, partial V^T A of row-split tiles during the update.
+constexpr int SCR_DOUBLES = (2 * MAXR > NWV * NB * NB) ? 2 * MAXR : NWV * NB * NB;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -77,7 +85,7 @@ __device__ inline double wave_sum(double v) {
 // Active tile rows of the panel [p0, p0 + nb) in increasing order; returns the count.
 // Dense tile (nchild == 0): rows p0..m-1.  Node: in child block b (offset
 // b*kc0, size kc_b) the local rows i with max(0, p0 - off_b) <= i < min(kc_b, p0 + nb).
-__device__ int panel_rows(int* rowl, int* bstart, int m, int nchild, int kc0, int kc_last, int p0, int nb) {
+__device__ __attribute__((always_inline)) int panel_rows(int* rowl, int* bstart, int m, int nchild, int kc0, int kc_last, int p0, int nb) {
   const int tid = threadIdx.x;
   if (nchild == 0) {
     for (int r = tid; r < m - p0; r += NT) rowl[r] = p0 + r;
@@ -120,17 +128,92 @@ __device__ inline float bop(const v4f& d, int s) {                 // f32: lane 
   return q == 0 ? t0 : (q == 1 ? t1 : (q == 2 ? t2 : t3));
 }
 
+// Partial W = V^T A over the rows [rlo, rhi) (rlo a multiple of 16) of the
+// 16-column tile at column `col`; four accumulators keep four MFMAs in flight.
+template <typename TA, typename TV>
+__device__ __attribute__((always_inline)) typename Mma<TV>::acc_t wpartial(
+    const TA* __restrict__ A, int64_t lda, const int* __restrict__ rowl, int col, bool colok, int rlo, int rhi,
+    const TV* __restrict__ V, int ldv) {
+  typedef Mma<TV> M;
+  const int lane = threadIdx.x & 63;
+  typename M::acc_t w0 = M::zero(), w1 = M::zero(), w2 = M::zero(), w3 = M::zero();
+  constexpr int U = 12;   // K-steps whose global loads are issued together
+  for (int r0 = rlo; r0 < rhi; r0 += 4 * U) {
+    TV b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + 4 * u + (lane >> 4);
+      b[u] = (r < rhi && colok) ? (TV)A[(int64_t)rowl[r] * lda + col] : (TV)0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u += 4) {
+      const int r = r0 + 4 * u + (lane >> 4);
+      const TV a0 = (r < rhi) ? V[(lane & 15) * ldv + r] : (TV)0;
+      const TV a1 = (r + 4 < rhi) ? V[(lane & 15) * ldv + r + 4] : (TV)0;
+      const TV a2 = (r + 8 < rhi) ? V[(lane & 15) * ldv + r + 8] : (TV)0;
+      const TV a3 = (r + 12 < rhi) ? V[(lane & 15) * ldv + r + 12] : (TV)0;
+      w0 = M::mma(a0, b[u], w0);
+      w1 = M::mma(a1, b[u + 1], w1);
+      w2 = M::mma(a2, b[u + 2], w2);
+      w3 = M::mma(a3, b[u + 3], w3);
+    }
+  }
+  return (w0 + w1) + (w2 + w3);
+}
+
+// A -= V Y on the rows [rlo, rhi) (rlo a multiple of 16) of the tile's column;
+// yb holds Y in B-operand layout.  The A values of UB row blocks are loaded together.
+template <typename TA, typename TV>
+__device__ __attribute__((always_inline)) void update_rows(TA* __restrict__ A, int64_t lda,
+                                                           const int* __restrict__ rowl, int col, bool colok, int rlo,
+                                                           int rhi, const TV* __restrict__ V, int ldv,
+                                                           const TV (&yb)[4]) {
+  typedef Mma<TV> M;
+  const int lane = threadIdx.x & 63;
+  constexpr int UB = 2;
+  for (int rb0 = rlo; rb0 < rhi; rb0 += NB * UB) {
+    double old[UB][4];
+    int idx[UB][4];   // tile element offsets (a tile holds < 2^31 elements)
+#pragma unroll
+    for (int ub = 0; ub < UB; ++ub) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rb0 + NB * ub + M::row(lane, v);
+        const bool ok = colok && r < rhi;
+        idx[ub][v] = ok ? (int)((int64_t)rowl[r] * lda + col) : -1;
+        old[ub][v] = ok ? (double)A[idx[ub][v]] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int ub = 0; ub < UB; ++ub) {
+      const int ra = rb0 + NB * ub + (lane & 15);
+      typename M::acc_t d = M::zero();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const TV a = (ra < rhi) ? V[(4 * s + (lane >> 4)) * ldv + ra] : (TV)0;
+        d = M::mma(a, yb[s], d);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (idx[ub][v] >= 0) A[idx[ub][v]] = (TA)(old[ub][v] - (double)d[v]);
+    }
+  }
+}
+
 // Trailing block update of the rows rowl[0..rows) x columns [c0, ncol) of A:
 //   FORWARD:  A <- Q^T A = A - V T^T (V^T A)   (factorisation)
 //   !FORWARD: A <- Q A   = A - V T (V^T A)     (application)
 // V: LDS column-major [NB][ldv] with explicit unit diagonal and zeros above;
-// Tm: LDS NB x NB row-major upper-triangular T (zero beyond the panel width).
+// Tm: LDS NB x NB row-major upper-triangular T (zero beyond the panel width);
+// wpart: LDS scratch of NWV x 256 doubles.  Called by the whole workgroup.
 template <bool FORWARD, typename TA, typename TV>
-__device__ void block_update(TA* __restrict__ A, int64_t lda, const int* __restrict__ rowl, int c0, int ncol,
-                             int rows, const TV* __restrict__ V, int ldv, const double* __restrict__ Tm) {
+__device__ __attribute__((always_inline)) void block_update(TA* __restrict__ A, int64_t lda, const int* __restrict__ rowl, int c0, int ncol,
+                             int rows, const TV* __restrict__ V, int ldv, const double* __restrict__ Tm,
+                             double* __restrict__ wpart) {
   typedef Mma<TV> M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ntile = (ncol - c0 + NB - 1) / NB;
+  if (ntile <= 0 || rows <= 0) return;
   // A operand of op(T) for the 4 K-steps: op(T)[l%16][4s + l/16]
   TV ta[4];
 #pragma unroll
@@ -138,78 +221,138 @@ __device__ void block_update(TA* __restrict__ A, int64_t lda, const int* __restr
     const int i = lane & 15, k = 4 * s + (lane >> 4);
     ta[s] = (TV)(FORWARD ? Tm[k * NB + i] : Tm[i * NB + k]);
   }
-  for (int tile = wave; tile < ntile; tile += NWV) {
-    const int cc = c0 + tile * NB;
-    const int col = cc + (lane & 15);
-    const bool colok = col < ncol;
-    // W = V^T A  (16 reflectors x 16 columns), K = rows in steps of 4
-    // four independent accumulators keep four MFMAs in flight
-    typename M::acc_t w0 = M::zero(), w1 = M::zero(), w2 = M::zero(), w3 = M::zero();
-    constexpr int U = 12;   // K-steps whose global loads are issued together
-    for (int r0 = 0; r0 < rows; r0 += 4 * U) {
-      TV b[U];
+  int nsplit = 1;
+  while (nsplit * 2 * ntile <= NWV && nsplit * 2 * NB <= rows) nsplit *= 2;
+  if (nsplit == 1) {
+    for (int tile = wave; tile < ntile; tile += NWV) {
+      const int col = c0 + tile * NB + (lane & 15);
+      const bool colok = col < ncol;
+      const typename M::acc_t w = wpartial<TA, TV>(A, lda, rowl, col, colok, 0, rows, V, ldv);
+      typename M::acc_t y = M::zero();
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int r = r0 + 4 * u + (lane >> 4);
-        b[u] = (r < rows && colok) ? (TV)A[(int64_t)rowl[r] * lda + col] : (TV)0;
-      }
+      for (int s = 0; s < 4; ++s) y = M::mma(ta[s], bop(w, s), y);
+      TV yb[4];
 #pragma unroll
-      for (int u = 0; u < U; u += 4) {
-        const int r = r0 + 4 * u + (lane >> 4);
-        const TV a0 = (r < rows) ? V[(lane & 15) * ldv + r] : (TV)0;
-        const TV a1 = (r + 4 < rows) ? V[(lane & 15) * ldv + r + 4] : (TV)0;
-        const TV a2 = (r + 8 < rows) ? V[(lane & 15) * ldv + r + 8] : (TV)0;
-        const TV a3 = (r + 12 < rows) ? V[(lane & 15) * ldv + r + 12] : (TV)0;
-        w0 = M::mma(a0, b[u], w0);
-        w1 = M::mma(a1, b[u + 1], w1);
-        w2 = M::mma(a2, b[u + 2], w2);
-        w3 = M::mma(a3, b[u + 3], w3);
-      }
+      for (int s = 0; s < 4; ++s) yb[s] = bop(y, s);
+      update_rows<TA, TV>(A, lda, rowl, col, colok, 0, rows, V, ldv, yb);
     }
-    const typename M::acc_t w = (w0 + w1) + (w2 + w3);
-    // Y = op(T) W
+    return;
+  }
+  // fewer tiles than waves: nsplit waves share a tile, each on a chunk of rows
+  const int tile = wave / nsplit, part = wave - tile * nsplit;
+  const bool act = tile < ntile;
+  const int chunk = (((rows + nsplit - 1) / nsplit) + NB - 1) & ~(NB - 1);
+  const int rlo = part * chunk < rows ? part * chunk : rows;
+  const int rhi = rlo + chunk < rows ? rlo + chunk : rows;
+  const int col = c0 + tile * NB + (lane & 15);
+  const bool colok = act && col < ncol;
+  if (act) {
+    const typename M::acc_t w = wpartial<TA, TV>(A, lda, rowl, col, colok, rlo, rhi, V, ldv);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) wpart[wave * 256 + v * 64 + lane] = (double)w[v];
+  }
+  __syncthreads();
+  if (act) {
+    // every wave of the tile sums the partials in the same order: identical W
+    double ws[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int p = 0; p < nsplit; ++p) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) ws[v] += wpart[(tile * nsplit + p) * 256 + v * 64 + lane];
+    }
+    typename M::acc_t w;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) w[v] = (TV)ws[v];
     typename M::acc_t y = M::zero();
 #pragma unroll
     for (int s = 0; s < 4; ++s) y = M::mma(ta[s], bop(w, s), y);
     TV yb[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) yb[s] = bop(y, s);
-    // A -= V Y, 16 rows at a time; the A values of UB row blocks are loaded together
-    constexpr int UB = 2;
-    for (int rb0 = 0; rb0 < rows; rb0 += NB * UB) {
-      double old[UB][4];
-      int idx[UB][4];   // tile element offsets (a tile holds < 2^31 elements)
+    update_rows<TA, TV>(A, lda, rowl, col, colok, rlo, rhi, V, ldv, yb);
+  }
+}
+
+// Publish panel column j for the next step: its entries below the diagonal
+// (zeros elsewhere, up to the last used row slot) to xs, and its Householder
+// reflector parameters to prm = {tau, scal, beta}: H = I - tau v v^T with
+// v = [1; scal * x], beta the new diagonal.  Called by the owning wave.
+__device__ __attribute__((always_inline)) void publish(const double (&y)[(MAXR + 63) / 64], int j, int rows, int rt, double* __restrict__ xs,
+                               double* __restrict__ prm) {
+  constexpr int RT = (MAXR + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-      for (int ub = 0; ub < UB; ++ub) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = rb0 + NB * ub + M::row(lane, v);
-          const bool ok = colok && r < rows;
-          idx[ub][v] = ok ? (int)((int64_t)rowl[r] * lda + col) : -1;
-          old[ub][v] = ok ? (double)A[idx[ub][v]] : 0.0;
-        }
-      }
-#pragma unroll
-      for (int ub = 0; ub < UB; ++ub) {
-        const int ra = rb0 + NB * ub + (lane & 15);
-        typename M::acc_t d = M::zero();
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const TV a = (ra < rows) ? V[(4 * s + (lane >> 4)) * ldv + ra] : (TV)0;
-          d = M::mma(a, yb[s], d);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (idx[ub][v] >= 0) A[idx[ub][v]] = (TA)(old[ub][v] - (double)d[v]);
-      }
+  for (int t = 0; t < RT; ++t) {
+    if (t < rt) {
+      const int r = lane + 64 * t;
+      const double v = (r > j && r < rows) ? y[t] : 0.0;
+      xs[r] = v;
+      if (t & 1) s1 += v * v;
+      else s0 += v * v;
     }
   }
+  const double sigma = wave_sum(s0 + s1);
+  const double alpha = readlane_d(y[0], j);
+  double tau = 0.0, beta = alpha, scal = 0.0;
+  if (sigma != 0.0) {
+    const double nrm = sqrt(alpha * alpha + sigma);
+    beta = (alpha >= 0.0) ? -nrm : nrm;
+    tau = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+  if (lane == 0) {
+    prm[0] = tau;
+    prm[1] = scal;
+    prm[2] = beta;
+  }
+}
+
+__host__ __device__ inline size_t panel_bytes(int elt, int ldv) {
+  return ((size_t)NB * ldv * elt + 15) & ~(size_t)15;
+}
+
+// Strictly upper part of S = V^T V (columns >= nb zero) for the compact WY
+// form.  V: LDS column-major [NB][ldv], rows [0, rows).  The rows are split
+// over the waves in multiples of 4; every wave's 16x16 partial goes to part
+// (NWV x 256 doubles of LDS) and thread (i, j) sums the partials in wave order.
+template <typename TV>
+__device__ __attribute__((always_inline)) void gram_v(const TV* __restrict__ V, int ldv, int rows, int nb, double* __restrict__ part,
+                       double* __restrict__ S) {
+  typedef Mma<TV> M;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int chunk = (((rows + NWV - 1) / NWV) + 3) & ~3;
+  const int rlo = wave * chunk, rhi = (rlo + chunk < rows) ? rlo + chunk : rows;
+  typename M::acc_t c0 = M::zero(), c1 = M::zero();
+  int r0 = rlo;
+  for (; r0 + 4 < rhi; r0 += 8) {
+    const int r = r0 + (lane >> 4);
+    const TV a0 = V[(lane & 15) * ldv + r];
+    const TV a1 = (r + 4 < rhi) ? V[(lane & 15) * ldv + r + 4] : (TV)0;
+    c0 = M::mma(a0, a0, c0);
+    c1 = M::mma(a1, a1, c1);
+  }
+  if (r0 < rhi) {
+    const int r = r0 + (lane >> 4);
+    const TV a0 = (r < rhi) ? V[(lane & 15) * ldv + r] : (TV)0;
+    c0 = M::mma(a0, a0, c0);
+  }
+  const typename M::acc_t acc = c0 + c1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) part[wave * 256 + M::row(lane, v) * NB + (lane & 15)] = (double)acc[v];
+  __syncthreads();
+  if (threadIdx.x < NB * NB) {
+    const int i = threadIdx.x >> 4, j = threadIdx.x & 15;
+    double s = 0.0;
+    for (int w = 0; w < NWV; ++w) s += part[w * 256 + threadIdx.x];
+    S[threadIdx.x] = (i < j && j < nb) ? s : 0.0;
+  }
+  __syncthreads();
 }
 
 // T of the compact WY form H_0 ... H_15 = I - V T V^T (forward, column-wise):
 // T_ii = tau_i, T_{a,i} = -tau_i sum_{b=a}^{i-1} T_ab S_bi.  Lane a of wave 0
 // builds row a; S (LDS, strictly upper V^T V) and tau (LDS) are inputs.
-__device__ void form_t(const double* __restrict__ S, const double* __restrict__ tau, double* __restrict__ Tm) {
+__device__ __attribute__((always_inline)) void form_t(const double* __restrict__ S, const double* __restrict__ tau, double* __restrict__ Tm) {
   const int tid = threadIdx.x;
   if (tid < NB) {
     const int a = tid;
@@ -235,7 +378,8 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   __shared__ int bstart[MAXR + 1];
   __shared__ double S[NB * NB];
   __shared__ double Tm[NB * NB];
-  __shared__ double taus[NB], pscal[NB], pbeta[NB];
+  __shared__ double taus[NB];
+  __shared__ double prm[8];
   const QrTask tk = tasks[blockIdx.x];
   const int m = tk.m, N = tk.ncol, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   TT* A = (TT*)tk.tile;
@@ -265,7 +409,9 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   __syncthreads();
 
   const int kmax = m < N ? m : N;
-  TT* P = (TT*)smem;   // NB columns x ldv rows
+  TT* P = (TT*)smem;                                       // NB columns x ldv rows
+  double* scr = (double*)(smem + panel_bytes((int)sizeof(TT), ldv));
+  constexpr int RT = (MAXR + 63) / 64;                     // row slots per lane
   for (int p0 = 0, pi = 0; p0 < kmax; p0 += NB, ++pi) {
     const int nb = (kmax - p0) < NB ? (kmax - p0) : NB;
     const int rows = panel_rows(rowl, bstart, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
@@ -273,108 +419,89 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
       const int r = idx / NB, jj = idx - r * NB;
       P[jj * ldv + r] = (jj < nb) ? A[(int64_t)rowl[r] * N + p0 + jj] : (TT)0;
     }
+    if (tid < NB) taus[tid] = 0.0;
     __syncthreads();
-    // ---- panel: wave jj and the waves owning the later panel columns (column c
-    // belongs to wave c) each compute the reflector of column jj; the owner of
-    // column c fuses its dot product into the same pass and applies the update.
-    // The scaling of column jj is written one step later by wave jj (nobody
-    // reads column jj meanwhile).  One workgroup barrier per column.
-    constexpr int RT = (MAXR + 63) / 64;   // rows per lane, predicated
+    // ---- panel column `wave` into registers (double); wave 0 publishes column 0
+    const int rt = (rows + 63) >> 6;
+    const bool mine = wave < nb;
+    double y[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) {
+      const int r = lane + 64 * t;
+      y[t] = (mine && t < rt && r < rows) ? (double)P[wave * ldv + r] : 0.0;
+    }
+    if (wave == 0) publish(y, 0, rows, rt, scr, prm);
+    __syncthreads();
     for (int jj = 0; jj < nb; ++jj) {
-      if (wave >= jj && wave < nb) {
-        const TT* cj = P + jj * ldv;
-        TT* pc = P + wave * ldv;           // the column this wave owns (unused when wave == jj)
-        const bool own = wave > jj;
-        double x[RT], y[RT];
-        double ss = 0.0, dd = 0.0;
+      if (mine && wave >= jj) {
+        // column jj below its diagonal (zero elsewhere) and its reflector
+        const double* xs = scr + (jj & 1) * MAXR;
+        const double* pp = prm + (jj & 1) * 4;
+        // all loads first (no wait between them), then the products
+        double x[RT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const int r = jj + 1 + lane + 64 * t;
-          const bool ok = r < rows;
-          x[t] = ok ? (double)cj[r] : 0.0;
-          y[t] = (ok && own) ? (double)pc[r] : 0.0;
-          ss += x[t] * x[t];
-          dd += x[t] * y[t];
-        }
-        const double sigma = wave_sum(ss);
-        const double dotx = own ? wave_sum(dd) : 0.0;
-        const double alpha = (double)cj[jj];
-        double tau = 0.0, beta = alpha, scal = 0.0;
-        if (sigma != 0.0) {
-          const double nrm = sqrt(alpha * alpha + sigma);
-          beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau = (beta - alpha) / beta;
-          scal = 1.0 / (alpha - beta);
-        }
-        if (own && tau != 0.0) {
-          const double w = scal * dotx + (double)pc[jj];
-          const double tw = tau * w;
+        for (int t = 0; t < RT; ++t) x[t] = (t < rt) ? xs[lane + 64 * t] : 0.0;
+        double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-          for (int t = 0; t < RT; ++t) {
-            const int r = jj + 1 + lane + 64 * t;
-            if (r < rows) pc[r] = (TT)(y[t] - tw * scal * x[t]);
+        for (int t = 0; t < RT; t += 2) {
+          d0 += x[t] * y[t];
+          d1 += x[t + 1] * y[t + 1];
+        }
+        const double tau = pp[0], scal = pp[1];
+        if (wave > jj) {
+          // apply H_jj to the own column
+          const double dot = wave_sum(d0 + d1);
+          if (tau != 0.0) {
+            const double tw = tau * (scal * dot + readlane_d(y[0], jj));
+            const double f = tw * scal;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) y[t] -= f * x[t];
+            if (lane == jj) y[0] -= tw;
           }
-          if (lane == 0) pc[jj] = (TT)((double)pc[jj] - tw);
-        }
-        if (wave == jj && lane == 0) {
-          taus[jj] = tau;
-          pscal[jj] = scal;
-          pbeta[jj] = beta;
+          if (wave == jj + 1) publish(y, jj + 1, rows, rt, scr + ((jj + 1) & 1) * MAXR, prm + ((jj + 1) & 1) * 4);
+        } else if (wave == jj) {
+          // the own column becomes beta on the diagonal and the reflector below
+          // (rounded to the tile precision: the MFMA updates use that V)
+          if (tau != 0.0) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+              if (t < rt && lane + 64 * t > jj) y[t] = (double)(TT)(y[t] * scal);
+          }
+          if (lane == jj) y[0] = pp[2];
+          if (lane == 0) taus[jj] = tau;
         }
       }
       __syncthreads();
     }
-    // scale the reflector columns and put beta on the diagonal, all columns at once
-    for (int idx = tid; idx < rows * nb; idx += NT) {
-      const int jj = idx / rows, r = idx - jj * rows;
-      TT* pc = P + jj * ldv;
-      if (r == jj) pc[r] = (TT)pbeta[jj];
-      else if (r > jj && taus[jj] != 0.0) pc[r] = (TT)((double)pc[r] * pscal[jj]);
+    // ---- factored panel to LDS, then to the tile (coalesced); tau out
+    if (mine) {
+#pragma unroll
+      for (int t = 0; t < RT; ++t) {
+        const int r = lane + 64 * t;
+        if (t < rt && r < rows) P[wave * ldv + r] = (TT)y[t];
+      }
     }
     __syncthreads();
-    // ---- write the factored panel back, keep tau
-    for (int idx = tid; idx < rows * nb; idx += NT) {
-      const int r = idx / nb, jj = idx - r * nb;
-      A[(int64_t)rowl[r] * N + p0 + jj] = P[jj * ldv + r];
+    for (int idx = tid; idx < rows * NB; idx += NT) {
+      const int r = idx >> 4, jj = idx & (NB - 1);
+      if (jj < nb) A[(int64_t)rowl[r] * N + p0 + jj] = P[jj * ldv + r];
     }
     if (tid < nb) tk.tau[p0 + tid] = taus[tid];
-    if (tid >= nb && tid < NB) taus[tid] = 0.0;
     __syncthreads();
     // ---- explicit V (unit diagonal, zeros above; padded columns zero)
-    for (int idx = tid; idx < NB * NB; idx += NT) {
-      const int jj = idx / NB, r = idx - jj * NB;
+    if (tid < NB * NB) {
+      const int jj = tid >> 4, r = tid & (NB - 1);
       if (r <= jj && r < rows) P[jj * ldv + r] = (r == jj && jj < nb) ? (TT)1 : (TT)0;
     }
     __syncthreads();
-    // ---- S = V^T V on MFMA (wave 0; both operands are V), strictly upper part kept, then T
-    if (wave == 0) {
-      typedef Mma<TT> M;
-      typename M::acc_t c0 = M::zero(), c1 = M::zero(), c2 = M::zero(), c3 = M::zero();
-      for (int r0 = 0; r0 < rows; r0 += 16) {
-        const int r = r0 + (lane >> 4);
-        const TT a0 = (r < rows) ? P[(lane & 15) * ldv + r] : (TT)0;
-        const TT a1 = (r + 4 < rows) ? P[(lane & 15) * ldv + r + 4] : (TT)0;
-        const TT a2 = (r + 8 < rows) ? P[(lane & 15) * ldv + r + 8] : (TT)0;
-        const TT a3 = (r + 12 < rows) ? P[(lane & 15) * ldv + r + 12] : (TT)0;
-        c0 = M::mma(a0, a0, c0);
-        c1 = M::mma(a1, a1, c1);
-        c2 = M::mma(a2, a2, c2);
-        c3 = M::mma(a3, a3, c3);
-      }
-      const typename M::acc_t acc = (c0 + c1) + (c2 + c3);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i = M::row(lane, v), j = lane & 15;
-        S[i * NB + j] = (i < j && j < nb) ? (double)acc[v] : 0.0;
-      }
-    }
-    __syncthreads();
+    // ---- S = V^T V on MFMA: every wave a slice of the rows, partials summed in LDS
+    gram_v<TT>(P, ldv, rows, nb, scr, S);
     form_t(S, taus, Tm);
     __syncthreads();
     if (tid < NB * NB) ((double*)tk.tmat)[(size_t)pi * NB * NB + tid] = Tm[tid];
     // ---- trailing update  A <- Q_p^T A  on the panel's rows
     const int c0 = p0 + nb;
-    if (c0 < N) block_update<true, TT, TT>(A, N, rowl, c0, N, rows, P, ldv, Tm);
+    if (c0 < N) block_update<true, TT, TT>(A, N, rowl, c0, N, rows, P, ldv, Tm, scr);
     __syncthreads();
   }
 }
@@ -397,6 +524,7 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
   }
   __syncthreads();
   TT* V = (TT*)smem;
+  double* scr = (double*)(smem + panel_bytes((int)sizeof(TT), ldv));
   const int np = (tk.kq + NB - 1) / NB;
   for (int pi = np - 1; pi >= 0; --pi) {
     const int p0 = pi * NB;
@@ -413,7 +541,7 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
     }
     if (tid < NB * NB) Tm[tid] = ((const double*)tk.tmat)[(size_t)pi * NB * NB + tid];
     __syncthreads();
-    block_update<false, double, TT>(W, t, rowl, 0, t, rows, V, ldv, Tm);
+    block_update<false, double, TT>(W, t, rowl, 0, t, rows, V, ldv, Tm, scr);
     __syncthreads();
   }
   if (tk.to_out) {
@@ -425,7 +553,7 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
   }
 }
 
-size_t panel_smem(int elt, int ldv) { return ((size_t)NB * ldv * elt + 15) & ~(size_t)15; }
+size_t panel_smem(int elt, int ldv) { return panel_bytes(elt, ldv) + (size_t)SCR_DOUBLES * 8; }
 
 template <typename K>
 hipError_t raise_lds(K kernel, size_t bytes) {
