@@ -130,6 +130,12 @@ tt_status tt_dot_batched(tt_ctx* ctx, int32_t npairs, const tt_sum* xs, const tt
  * least the packed size of the result. */
 tt_status tt_axpy(tt_ctx* ctx, double alpha, const tt_vec* x, const tt_vec* y, tt_vec* z);
 
+/* ||x|| of a lazy sum (Section 2: Frobenius norm of the full tensor),
+ * computed stably by the right-to-left QR sweep of TT-round: after it,
+ * ||x|| = ||G_0||_F.  With a sum x + (-1) y this gives ||x - y|| without the
+ * cancellation of sqrt(<x,x> - 2<x,y> + <y,y>).  out: HOST double. */
+tt_status tt_norm(tt_ctx* ctx, const tt_sum* x, double* out);
+
 /* TT-round(x, delta) (Section 2): returns x~ with ||x - x~|| <= delta ||x||.
  * Right-to-left QR sweep, then left-to-right truncated SVD at per-bond
  * threshold delta / sqrt(d-1) * ||x||, keeping the smallest rank whose

@@ -598,6 +598,22 @@ tt_status tt_round_batched(tt_ctx* c, int32_t njobs, const tt_sum* xs, const dou
   return first;
 }
 
+tt_status tt_norm(tt_ctx* c, const tt_sum* x, double* out) {
+  if (!c) return TT_EINVAL;
+  tt_status s;
+  if ((s = check_sum(c, x, "x")) != TT_OK) return s;
+  if (!out) return fail(c, TT_EINVAL, "norm: out is NULL");
+  CallScope scope(c);
+  std::vector<RJob> jobs(1);
+  make_job(c, x, 0.0, 0, nullptr, jobs[0]);
+  jobs[0].orth_only = true;
+  s = round_jobs(c, jobs);
+  if (s != TT_OK) return s;
+  if (jobs[0].status != TT_OK) return fail(c, jobs[0].status, "norm failed");
+  *out = jobs[0].norm;
+  return TT_OK;
+}
+
 tt_status tt_round(tt_ctx* c, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out, double* norm_x) {
   if (!c) return TT_EINVAL;
   tt_status s;

@@ -133,6 +133,7 @@ struct RJob {
   tt_vec* out = nullptr;
   double norm = 0.0;
   tt_status status = TT_OK;
+  bool orth_only = false;         // right-to-left sweep and norm only (no output TT)
 };
 
 tt_status make_job(tt_ctx* c, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out, RJob& job);

@@ -445,6 +445,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     int64_t need = 0;
     if (jb.d == 1) {
       need = jb.n[0];
+      if (jb.orth_only) st[j].C = ws_alloc(c, (size_t)jb.n[0] * elt);   // the materialised sum
     } else {
       std::string why;
       if (!plan_job(c, jb, st[j], &why)) return fail(c, TT_ENOTIMPL, why);
@@ -471,7 +472,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       RJob& jb = jobs[j];
       if (jb.d != 1) continue;
       st[j].d_norm = (double*)dev_scratch(c, 8);
-      if (jb.out->capacity < jb.n[0]) jb.status = TT_ECAPACITY;
+      if (!jb.orth_only && jb.out->capacity < jb.n[0]) jb.status = TT_ECAPACITY;
       else maxc = std::max(maxc, jb.comps.size());
     }
     for (size_t ci = 0; ci < maxc; ++ci) {
@@ -481,7 +482,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
         if (jb.d != 1 || jb.status != TT_OK || ci >= jb.comps.size()) continue;
         CopySeg sg;
         sg.src = jb.comps[ci].data;
-        sg.dst = jb.out->data;
+        sg.dst = jb.orth_only ? st[j].C : jb.out->data;
         sg.count = jb.n[0];
         sg.coef = jb.comps[ci].coef;
         sg.accumulate = ci > 0;
@@ -494,7 +495,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     for (int j = 0; j < nj; ++j) {
       RJob& jb = jobs[j];
       if (jb.d != 1 || jb.status != TT_OK) continue;
-      if ((e = launch_sumsq(dtype, jb.out->data, jb.n[0], st[j].d_norm, s)) != hipSuccess)
+      if ((e = launch_sumsq(dtype, jb.orth_only ? st[j].C : jb.out->data, jb.n[0], st[j].d_norm, s)) != hipSuccess)
         return hip_fail(c, e, "sumsq");
     }
   }
@@ -622,7 +623,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
   for (int j = 0; j < nj; ++j) {
     st[j].t[0] = 1;
     st[j].out_off = 0;
-    st[j].alive = jobs[j].d >= 2 && jobs[j].status == TT_OK;
+    st[j].alive = jobs[j].d >= 2 && jobs[j].status == TT_OK && !jobs[j].orth_only;
   }
   for (int k = 0; k + 1 < maxd; ++k) {
     std::vector<int> act;
@@ -767,6 +768,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     RJob& jb = jobs[j];
     if (jb.status != TT_OK) continue;
     jb.norm = h_norms[j];
+    if (jb.orth_only) continue;
     if (jb.d == 1) {
       jb.out->r[0] = 1;
       jb.out->r[1] = 1;

@@ -86,6 +86,8 @@ def _load():
         lib.tt_axpy.argtypes = [P, C.c_double, C.POINTER(_Vec), C.POINTER(_Vec), C.POINTER(_Vec)]
         lib.tt_axpy.restype = C.c_int
         lib.tt_round.argtypes = [P, C.POINTER(_Sum), C.c_double, C.c_int64, C.POINTER(_Vec), C.POINTER(C.c_double)]
+        lib.tt_norm.argtypes = [P, C.POINTER(_Sum), C.POINTER(C.c_double)]
+        lib.tt_norm.restype = C.c_int
         lib.tt_round.restype = C.c_int
         lib.tt_round_batched.argtypes = [P, C.c_int32, C.POINTER(_Sum), C.POINTER(C.c_double),
                                          C.POINTER(C.c_int64), C.POINTER(_Vec), C.POINTER(C.c_int)]
@@ -286,6 +288,19 @@ def _finish_out(out: TT, v: _Vec):
     out.r = [int(v.r[k]) for k in range(out.d + 1)]
     out.data = out.data[: out.size()]
     return out
+
+
+def norm(x) -> float:
+    """||x|| of a TT or lazy sum by the right-to-left QR sweep (no cancellation)."""
+    h = _SumHolder(x)
+    ctx = _ctx(h.tts[0].data.device.index)
+    out = C.c_double(0.0)
+    ws = int(ctx.lib.tt_round_workspace_bytes(C.byref(h.s)))
+    if ws < 0:
+        ctx.check(-9)
+    ctx.ensure_ws(ws)
+    ctx.call_with_ws(lambda: ctx.lib.tt_norm(ctx.h, C.byref(h.s), C.byref(out)))
+    return out.value
 
 
 def round(x, delta: float, max_rank: int = 0, return_norm: bool = False):

@@ -63,3 +63,30 @@ def test_axpy_matches_oracle_exactly_in_structure(dtype):
         for a, b in zip(host_cores(z), ref):
             # block copies; only the first core is scaled (one multiply, rounded in the storage dtype)
             assert np.allclose(a, b, rtol=(1e-15 if dtype == torch.float64 else 1e-7), atol=0)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_norm_of_lazy_sums(dtype, tol):
+    """tt_norm: right-to-left sweep then ||G_0||_F, against the oracle's orthogonalisation."""
+    tt = need_gpu()
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    up = lambda v: [c.astype(np.float64) for c in v]
+    ns = [5, 6, 4, 3]
+    a = [c.astype(npdt) for c in rand(41, ns, [1, 3, 4, 2, 1])]
+    b = [c.astype(npdt) for c in rand(42, ns, [1, 2, 2, 3, 1])]
+    # a plain TT, a sum, and a difference that nearly cancels (a - (a + 1e-6 b))
+    cases = [[(1.0, a)], [(0.7, a), (-1.3, b)], [(1.0, a), (-1.0, a), (-1e-6, b)]]
+    for terms in cases:
+        ref_sum = oracle.tt_sum([(c, up(v)) for c, v in terms])
+        ref = float(np.linalg.norm(oracle.tt_orth_rl(ref_sum)[0][0]))
+        got = tt.norm(dev_sum(terms, dtype))
+        scale = sum(abs(c) * oracle.tt_norm(up(v)) for c, v in terms)
+        assert abs(got - ref) <= tol * scale, (got, ref)
+    # order one: the plain vector norm of the summed components
+    v1 = [np.arange(1.0, 8.0).reshape(1, 7, 1).astype(npdt)]
+    v2 = [np.full((1, 7, 1), 0.5, dtype=npdt)]
+    got = tt.norm(dev_sum([(2.0, v1), (-1.0, v2)], dtype))
+    assert abs(got - np.linalg.norm(2.0 * np.arange(1.0, 8.0) - 0.5)) <= tol * 30
+    # zero tensor
+    z = [np.zeros((1, 4, 2)), np.zeros((2, 4, 1))]
+    assert tt.norm(dev_tt([c.astype(npdt) for c in z], dtype)) == 0.0
