@@ -2,11 +2,14 @@
 // TT-round, with the truncation-rank decision made on the device.
 //
 // One-sided (Hestenes) Jacobi: the columns of A are rotated pairwise until
-// every pair is orthogonal to relative precision; the accumulated rotations
-// J are kept.  For a square R (tall unfolding) A = R and J = V; for a wide R
-// (fewer rows than columns) A = R^T and J holds the left singular vectors.
-// Pairs follow a round-robin tournament, so the pairs of one round are
-// disjoint and run on different waves.
+// every pair is orthogonal to relative precision.  For a square R (tall
+// unfolding) A = R; its final columns are U Sigma, and W = Sigma_t V_t^T is
+// formed afterwards as U_t^T R, so no rotations are accumulated.  For a wide
+// R (fewer rows than columns) A = R^T, whose final columns are V Sigma, and
+// the rotations are accumulated in J = U (small: k x k with k <= rows of R).
+// Pairs follow the round-robin (circle) schedule in closed form, so the pairs
+// of one round are disjoint and run on different waves; one workgroup
+// barrier per round.
 //
 // Deflation: columns of A whose squared norms add up to at most
 // tau^2 = (2 sqrt(nc) u ||A||_F)^2 (u = unit round-off of the arithmetic that
@@ -18,6 +21,7 @@
 // <= eps = delta/sqrt(d-1) * ||x|| (tail accumulated from the smallest
 // singular value), capped by max_rank.
 #include "common.h"
+#include "wave.h"
 
 namespace tto {
 
@@ -27,11 +31,6 @@ constexpr int NT = 1024;
 constexpr int NW = NT / 64;
 constexpr int MAXC = 1024;
 constexpr int LDS_DOUBLES = 18000;   // 140.6 KiB for A and J (plus ~16 KiB static)
-
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 __device__ inline double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -44,13 +43,30 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// One-sided Jacobi on A (len x k, column-major, lda = len) with accumulation
-// into J (k x k, column-major).  Returns the number of sweeps used.
-__device__ int jacobi(double* A, int len, double* J, int k, int* perm, int* rots) {
+// Pair `pair` of round `round` of the circle schedule on kp (even) players:
+// player kp-1 stays, the others rotate.
+__device__ inline void rr_pair(int round, int pair, int kp, int& p, int& q) {
+  const int m = kp - 1;
+  if (pair == 0) {
+    p = m;
+    q = round;
+  } else {
+    p = (round + pair) % m;
+    q = (round - pair + m) % m;
+  }
+  if (p > q) {
+    const int t = p;
+    p = q;
+    q = t;
+  }
+}
+
+// One-sided Jacobi on A (len x k, column-major, lda = len); when J is not
+// null the rotations are accumulated into J (k x k, column-major).  Returns
+// the number of sweeps used.
+__device__ int jacobi(double* A, int len, double* J, int k, int* rots) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kp = k + (k & 1);
-  for (int i = tid; i < kp; i += NT) perm[i] = i;
-  __syncthreads();
   const double tol = sqrt((double)len) * 1.1102230246251565e-16;
   int sweep = 0;
   for (; sweep < 64 && kp >= 2; ++sweep) {
@@ -58,13 +74,9 @@ __device__ int jacobi(double* A, int len, double* J, int k, int* perm, int* rots
     __syncthreads();
     for (int round = 0; round < kp - 1; ++round) {
       for (int pair = wave; pair < kp / 2; pair += NW) {
-        int p = perm[pair], q = perm[kp - 1 - pair];
-        if (p >= k || q >= k) continue;
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
+        int p, q;
+        rr_pair(round, pair, kp, p, q);
+        if (q >= k) continue;
         double* ap = A + (int64_t)p * len;
         double* aq = A + (int64_t)q * len;
         double al = 0.0, be = 0.0, ga = 0.0;
@@ -88,21 +100,17 @@ __device__ int jacobi(double* A, int len, double* J, int k, int* perm, int* rots
             ap[i] = c * x - s * y;
             aq[i] = s * x + c * y;
           }
-          double* jp = J + (int64_t)p * k;
-          double* jq = J + (int64_t)q * k;
-          for (int i = lane; i < k; i += 64) {
-            const double x = jp[i], y = jq[i];
-            jp[i] = c * x - s * y;
-            jq[i] = s * x + c * y;
+          if (J) {
+            double* jp = J + (int64_t)p * k;
+            double* jq = J + (int64_t)q * k;
+            for (int i = lane; i < k; i += 64) {
+              const double x = jp[i], y = jq[i];
+              jp[i] = c * x - s * y;
+              jq[i] = s * x + c * y;
+            }
           }
-          if (lane == 0) atomicAdd(rots, 1);
+          if (lane == 0) *rots = 1;
         }
-      }
-      __syncthreads();
-      if (tid == 0 && kp > 2) {
-        const int last = perm[kp - 1];
-        for (int i = kp - 1; i >= 2; --i) perm[i] = perm[i - 1];
-        perm[1] = last;
       }
       __syncthreads();
     }
@@ -180,20 +188,21 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   __syncthreads();
   const int k = kact, len = lenact > 0 ? lenact : 1;
 
-  // ---- A_active (len x k) and J (k x k): LDS when they fit, else global scratch
-  const bool in_lds = (int64_t)len * k + (int64_t)k * k <= LDS_DOUBLES;
+  // ---- A_active (len x k) and, for a wide R, J (k x k): LDS when they fit, else global scratch
+  const int64_t jsz = tall ? 0 : (int64_t)k * k;
+  const bool in_lds = (int64_t)len * k + jsz <= LDS_DOUBLES;
   double* A = in_lds ? lds : tk.A;
-  double* J = in_lds ? lds + (int64_t)len * k : tk.acc;
+  double* J = tall ? nullptr : (in_lds ? lds + (int64_t)len * k : tk.acc);
   for (int64_t idx = tid; idx < (int64_t)k * len; idx += NT) {
     const int a = (int)(idx / len), i = (int)(idx - (int64_t)a * len);
     A[idx] = aval(i, act[a]);
   }
-  for (int64_t idx = tid; idx < (int64_t)k * k; idx += NT) {
+  for (int64_t idx = tid; idx < jsz; idx += NT) {
     const int j = (int)(idx / k), i = (int)(idx - (int64_t)j * k);
     J[idx] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int sweeps = (k > 0) ? jacobi(A, len, J, k, perm, &rots) : 0;
+  const int sweeps = (k > 0) ? jacobi(A, len, J, k, &rots) : 0;
 
   // ---- singular values, order, rank
   for (int j = wave; j < k; j += NW) {
@@ -248,8 +257,15 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
     if (!degenerate && i < k) {
       const int j = perm[i];
       if (tall) {
-        const int a = (int)nrm2[col];
-        v = (a >= 0) ? tk.sigma[i] * J[(int64_t)j * k + a] : 0.0;
+        // row i of W = Sigma_t V_t^T = U_t^T R, with U_t = (final column)/sigma
+        const double s = tk.sigma[i];
+        if (s > 0.0) {
+          const double* aj = A + (int64_t)j * len;
+          const int rmax = (tk.upper && col + 1 < len) ? col + 1 : len;   // R(row, col) = 0 below the diagonal
+          double acc = 0.0;
+          for (int row = 0; row < rmax; ++row) acc += aj[row] * aval(row, col);
+          v = acc / s;
+        }
       } else {
         v = (col < len) ? A[(int64_t)j * len + col] : 0.0;
       }
