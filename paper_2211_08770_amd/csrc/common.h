@@ -50,8 +50,9 @@ struct ApplyTask {
 // One-sided Jacobi SVD of a (kr x ncol) upper-trapezoidal R factor, FP64.
 // ---------------------------------------------------------------------------
 struct SvdTask {
-  const double* R;        // row-major kr x ncol, ld = r_ld (root tile of a TSQR)
+  const void* R;          // row-major kr x ncol, ld = r_ld (root tile of a TSQR)
   int64_t r_ld;
+  int32_t r_f32;          // 1: R is float (root of a one-tile FP32 tree), 0: double
   int32_t kr, ncol;
   int32_t upper;          // 1: R is upper trapezoidal (entries below the diagonal read as 0)
   double bulk_u;          // unit round-off of the arithmetic that produced R (deflation scale; 0: none)
@@ -84,8 +85,9 @@ struct GemmPart {
 struct GemmTask {
   int32_t M, N;
   int32_t part0, nparts;
-  const double* B;        // entries B[c][j] with j < c read as zero (R factor of a tile)
+  const void* B;          // entries B[c][j] with j < c read as zero (R factor of a tile)
   int64_t b_ld;
+  int32_t b_f32;          // 1: B is float (root of a one-tile FP32 tree), 0: double
   void* C;
   int64_t c_ld;
 };

@@ -40,7 +40,12 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* __restrict__ tasks,
       for (int e = threadIdx.x; e < TN * TK; e += NT) {
         const int c = e / TK, kk = e % TK;
         const int gc = col0 + c, gk = k0 + kk;
-        Bs[kk][c] = (gc < tk.N && gk < K && pt.b_off + gk >= gc) ? (T)tk.B[(int64_t)gc * tk.b_ld + pt.b_off + gk] : (T)0;
+        T bv = (T)0;
+        if (gc < tk.N && gk < K && pt.b_off + gk >= gc) {
+          const int64_t bi = (int64_t)gc * tk.b_ld + pt.b_off + gk;
+          bv = tk.b_f32 ? (T)((const float*)tk.B)[bi] : (T)((const double*)tk.B)[bi];
+        }
+        Bs[kk][c] = bv;
       }
       __syncthreads();
 #pragma unroll

@@ -96,7 +96,8 @@ struct Tree {
   std::vector<std::vector<QrTask>> lvl;         // lvl[0] = leaves
   std::vector<int64_t> leaf_row0;               // first row of each leaf
   int kr() const;                               // rows of the root R factor
-  const double* root_R() const;                 // FP64 root tile (row-major, ld = N)
+  const void* root_R() const;                   // root tile (row-major, ld = N)
+  int root_f32() const { return lvl.size() == 1 && leaf_dtype == TT_F32 ? 1 : 0; }   // dtype of root_R
   int depth() const { return (int)lvl.size(); }
 };
 

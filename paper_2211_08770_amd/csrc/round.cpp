@@ -43,7 +43,7 @@ int Tree::kr() const {
   return (int)std::min<int64_t>(r.m, N);
 }
 
-const double* Tree::root_R() const { return (const double*)lvl.back()[0].tile; }
+const void* Tree::root_R() const { return lvl.back()[0].tile; }
 
 bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs, int64_t cs,
                std::string* why) {
@@ -91,10 +91,8 @@ bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void*
     t.leaf_row0.push_back(r0);
   }
   t.lvl.push_back(std::move(leaves));
-  bool need_node = (dtype == TT_F32);   // R factors always end in an FP64 tile
   const int64_t g = std::max<int64_t>(2, QR_MAXROWS / N);
-  while (t.lvl.back().size() > 1 || need_node) {
-    need_node = false;
+  while (t.lvl.back().size() > 1) {
     const std::vector<QrTask>& prev = t.lvl.back();
     std::vector<QrTask> nodes;
     for (size_t i = 0; i < prev.size(); i += (size_t)g) {
@@ -559,6 +557,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
           g.nparts = 1;
           g.B = tr.root_R();
           g.b_ld = tr.N;
+          g.b_f32 = tr.root_f32();
           g.C = (char*)js.Y[k - 1] + (size_t)(jb.roff[ci * D + (k - 1)] * jb.n[k - 1] * js.s[k]) * elt;
           g.c_ld = js.s[k];
           GemmPart p;
@@ -580,6 +579,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
         g.nparts = (int32_t)jb.comps.size();
         g.B = tr.root_R();
         g.b_ld = tr.N;
+        g.b_f32 = tr.root_f32();
         g.C = js.C;
         g.c_ld = js.s[1];
         for (size_t ci = 0; ci < jb.comps.size(); ++ci) {
@@ -672,6 +672,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       std::memset(&t, 0, sizeof(t));
       t.R = js.lr.root_R();
       t.r_ld = js.lr.N;
+      t.r_f32 = js.lr.root_f32();
       t.kr = js.lr.kr();
       t.ncol = (int32_t)js.lr.N;
       t.upper = 1;

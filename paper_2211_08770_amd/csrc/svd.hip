@@ -61,41 +61,56 @@ __device__ inline void rr_pair(int round, int pair, int kp, int& p, int& q) {
   }
 }
 
-// One-sided Jacobi on A (len x k, column-major, lda = len); when J is not
-// null the rotations are accumulated into J (k x k, column-major).  Returns
-// the number of sweeps used.
-__device__ int jacobi(double* A, int len, double* J, int k, int* rots) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+extern __shared__ __align__(16) double svd_lds[];
+
+// One-sided Jacobi on A (len x k, column-major, lda = len); when J is
+// requested the rotations are accumulated into J (k x k, column-major).
+// SH: A (and J right after it) live in the dynamic LDS block, so the
+// accesses compile to LDS instructions; otherwise Ag / Jg in global memory.
+// Returns the number of sweeps used.
+template <bool SH>
+__device__ __attribute__((always_inline)) int jacobi(double* Ag, double* Jg, bool with_j, int len, int k,
+                                                     int* rots) {
+  double* A = SH ? svd_lds : Ag;
+  double* J = with_j ? (SH ? svd_lds + (int64_t)len * k : Jg) : nullptr;
+  // a 16-lane row of a wave handles one pair: reductions stay inside the row
+  const int tid = threadIdx.x, gl = tid & 15, grp = tid >> 4;
+  constexpr int NG = NT / 16;
   const int kp = k + (k & 1);
-  const double tol = sqrt((double)len) * 1.1102230246251565e-16;
+  const double tol = (double)len * 1.1102230246251565e-16;
+  const double tol2 = tol * tol;
   int sweep = 0;
   for (; sweep < 64 && kp >= 2; ++sweep) {
     if (tid == 0) *rots = 0;
     __syncthreads();
     for (int round = 0; round < kp - 1; ++round) {
-      for (int pair = wave; pair < kp / 2; pair += NW) {
-        int p, q;
-        rr_pair(round, pair, kp, p, q);
-        if (q >= k) continue;
+      for (int pb = 0; pb < kp / 2; pb += NG) {   // uniform trip count: every row takes part in the sums
+        const int pair = pb + grp;
+        int p = 0, q = 0;
+        if (pair < kp / 2) rr_pair(round, pair, kp, p, q);
+        const bool live = pair < kp / 2 && q < k;
         double* ap = A + (int64_t)p * len;
         double* aq = A + (int64_t)q * len;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < len; i += 64) {
-          const double x = ap[i], y = aq[i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
+        if (live) {
+          for (int i = gl; i < len; i += 16) {
+            const double x = ap[i], y = aq[i];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
         }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+        al = row16_sum(al);
+        be = row16_sum(be);
+        ga = row16_sum(ga);
+        // rotate unless the pair is orthogonal to relative precision tol
+        if (live && ga != 0.0 && ga * ga > tol2 * al * be) {
           const double zeta = (be - al) / (2.0 * ga);
           double t;
           if (fabs(zeta) > 1e150) t = 0.5 / zeta;
           else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          for (int i = lane; i < len; i += 64) {
+          for (int i = gl; i < len; i += 16) {
             const double x = ap[i], y = aq[i];
             ap[i] = c * x - s * y;
             aq[i] = s * x + c * y;
@@ -103,13 +118,13 @@ __device__ int jacobi(double* A, int len, double* J, int k, int* rots) {
           if (J) {
             double* jp = J + (int64_t)p * k;
             double* jq = J + (int64_t)q * k;
-            for (int i = lane; i < k; i += 64) {
+            for (int i = gl; i < k; i += 16) {
               const double x = jp[i], y = jq[i];
               jp[i] = c * x - s * y;
               jq[i] = s * x + c * y;
             }
           }
-          if (lane == 0) *rots = 1;
+          if (gl == 0) *rots = 1;
         }
       }
       __syncthreads();
@@ -122,7 +137,6 @@ __device__ int jacobi(double* A, int len, double* J, int k, int* rots) {
 }
 
 __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
-  extern __shared__ __align__(16) double lds[];
   __shared__ int perm[MAXC + 2];
   __shared__ int act[MAXC];
   __shared__ double nrm2[MAXC];
@@ -140,7 +154,8 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   auto aval = [&](int i, int j) -> double {
     const int rr = tall ? i : j, cc = tall ? j : i;
     if (tk.upper && cc < rr) return 0.0;
-    return tk.R[(int64_t)rr * tk.r_ld + cc];
+    const int64_t e = (int64_t)rr * tk.r_ld + cc;
+    return tk.r_f32 ? (double)((const float*)tk.R)[e] : ((const double*)tk.R)[e];
   };
 
   // ---- column norms and deflation
@@ -191,8 +206,10 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   // ---- A_active (len x k) and, for a wide R, J (k x k): LDS when they fit, else global scratch
   const int64_t jsz = tall ? 0 : (int64_t)k * k;
   const bool in_lds = (int64_t)len * k + jsz <= LDS_DOUBLES;
-  double* A = in_lds ? lds : tk.A;
-  double* J = tall ? nullptr : (in_lds ? lds + (int64_t)len * k : tk.acc);
+  double* A = in_lds ? svd_lds : tk.A;
+  double* J = tall ? nullptr : (in_lds ? svd_lds + (int64_t)len * k : tk.acc);
+  // (the Jacobi sweeps are called with the LDS or the global pointer written
+  // out, so that each copy uses LDS or global instructions, not flat ones)
   for (int64_t idx = tid; idx < (int64_t)k * len; idx += NT) {
     const int a = (int)(idx / len), i = (int)(idx - (int64_t)a * len);
     A[idx] = aval(i, act[a]);
@@ -202,7 +219,11 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
     J[idx] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  const int sweeps = (k > 0) ? jacobi(A, len, J, k, &rots) : 0;
+  int sweeps = 0;
+  if (k > 0) {
+    if (in_lds) sweeps = jacobi<true>(nullptr, nullptr, !tall, len, k, &rots);
+    else sweeps = jacobi<false>(tk.A, tk.acc, !tall, len, k, &rots);
+  }
 
   // ---- singular values, order, rank
   for (int j = wave; j < k; j += NW) {

@@ -19,6 +19,15 @@ __device__ inline double readlane_d(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum over each 16-lane row of a wave (every lane gets its row's sum).
+__device__ inline double row16_sum(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm(1,0,3,2)
+  v += dpp_d<0x4E>(v);    // quad_perm(2,3,0,1)
+  v += dpp_d<0x124>(v);   // row_ror:4
+  v += dpp_d<0x128>(v);   // row_ror:8
+  return v;
+}
+
 // Sum over the 64 lanes of a wave, the same value (and the same rounding) in
 // every lane: quad swaps and row rotations give every lane its 16-lane row
 // sum, then the four row sums are added in a fixed order.
