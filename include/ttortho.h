@@ -178,6 +178,60 @@ tt_status tt_orthogonalize(tt_ctx* ctx, tt_scheme scheme, int32_t m, const tt_su
  * gram (HOST m*m, nullable) receives Q^T Q. */
 tt_status tt_loo(tt_ctx* ctx, int32_t m, const tt_vec* q, double* loo, double* gram);
 
+/* ---------------------------------------------------------------------------
+ * Serving engine: continuous batching of orthogonalization requests.
+ *
+ * A request orthogonalizes one new TT-vector w (a lazy sum) against an
+ * orthonormal basis q_0..q_{b-1} that stays resident on the device (the
+ * Krylov basis of a TT-GMRES solver): one step i = b of TT-CGS (Algorithm 1),
+ * TT-MGS (Algorithm 2), TT-CGS2 (Algorithm 3) or TT-MGS2 (Algorithm 4).
+ * Every tt_engine_step advances each request in flight by one stage -- the
+ * batched inner products and projection coefficients of a pass, the
+ * rounding of a pass, or the final normalisation -- and all requests at the
+ * same kind of stage share the same launches.  Requests submitted between
+ * steps join the next step while older ones are still in flight.  A
+ * request's results do not depend on the other requests in flight.
+ * ------------------------------------------------------------------------- */
+typedef struct tt_request {
+  int32_t scheme;             /* TT_CGS, TT_MGS, TT_CGS2 or TT_MGS2                         */
+  int32_t b;                  /* basis size >= 0                                           */
+  const tt_vec* basis;        /* [b] orthonormal basis (device data, not modified)         */
+  const double* basis_gram;   /* HOST b*b row-major <q_l, q_j>, used by the MGS schemes;
+                                 NULL means the identity                                    */
+  tt_sum w;                   /* the new vector                                           */
+  double delta;               /* rounding accuracy                                        */
+  tt_vec* q_out;              /* result q_b = p / ||p|| (capacity >= tt_request_out_capacity) */
+  double* r_out;              /* HOST [b + 1]: column b of R (projections, then ||p||)    */
+  double* gram_out;           /* HOST [b] or NULL: <q_b, q_j>, j < b (next basis Gram row) */
+  void* scratch;              /* device memory of tt_request_scratch_bytes bytes,
+                                 owned by the caller until the request completes           */
+  int64_t scratch_bytes;
+} tt_request;
+
+typedef struct tt_engine tt_engine;
+
+/* Element capacity q_out needs, and device scratch bytes a request needs
+ * (the basis Gram, the first-pass vector of CGS2/MGS2).  -1 on bad input. */
+int64_t tt_request_out_capacity(const tt_request* r);
+int64_t tt_request_scratch_bytes(const tt_request* r);
+
+/* An engine works on the context's stream and workspace; one host thread. */
+tt_status tt_engine_create(tt_ctx* ctx, tt_engine** e);
+void tt_engine_destroy(tt_engine* e);
+/* Validate and enqueue a request (copied; the pointed-to buffers must stay
+ * valid until it completes).  *id identifies it in tt_engine_step. */
+tt_status tt_engine_submit(tt_engine* e, const tt_request* r, int64_t* id);
+/* Advance every request in flight by one stage.  Up to max_done completed
+ * requests are reported in done_ids / done_status (HOST arrays); *ndone
+ * receives their number.  A failed request (TT_EBREAKDOWN when ||p|| = 0,
+ * TT_ECAPACITY, TT_ENOTIMPL for unsupported shapes) is reported with its
+ * status; the others continue.  The return value is TT_OK unless the engine
+ * itself failed (device error). */
+tt_status tt_engine_step(tt_engine* e, int32_t max_done, int64_t* done_ids, tt_status* done_status,
+                         int32_t* ndone);
+/* Requests submitted and not yet reported. */
+int32_t tt_engine_pending(const tt_engine* e);
+
 #ifdef __cplusplus
 }
 #endif

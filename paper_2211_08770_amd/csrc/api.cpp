@@ -942,3 +942,352 @@ tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum*
 }
 
 }  // extern "C"
+
+// ============================================================================
+// Serving engine (continuous batching of Gram-Schmidt steps, Algorithms 1-4)
+// ============================================================================
+namespace {
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int scheme_passes(int s) { return (s == TT_CGS2 || s == TT_MGS2) ? 2 : 1; }
+bool scheme_modified(int s) { return s == TT_MGS || s == TT_MGS2; }
+
+// Packed size of a TT with bond ranks c_k = min(R_k, caps_k).
+int64_t capped_size(const tt_vec& shape, const int64_t* R) {
+  int64_t caps[TT_MAXD + 1];
+  rank_caps(shape, caps);
+  int64_t c[TT_MAXD + 1];
+  for (int k = 0; k <= shape.d; ++k) c[k] = std::min(R[k], caps[k]);
+  c[0] = c[shape.d] = 1;
+  int64_t s = 0;
+  for (int k = 0; k < shape.d; ++k) s += c[k] * shape.n[k] * c[k + 1];
+  return s;
+}
+
+// Rank bounds of a request: first-pass sum w + basis, and second-pass sum
+// p_1 + basis (p_1 itself capped).
+void request_ranks(const tt_request* r, int64_t* R1, int64_t* R2) {
+  const tt_vec& s0 = r->w.comp[0];
+  const int d = s0.d;
+  int64_t caps[TT_MAXD + 1];
+  rank_caps(s0, caps);
+  for (int k = 0; k <= d; ++k) {
+    int64_t rw = 0, rq = 0;
+    for (int i = 0; i < r->w.ncomp; ++i) rw += r->w.comp[i].r[k];
+    for (int j = 0; j < r->b; ++j) rq += r->basis[j].r[k];
+    R1[k] = (k == 0 || k == d) ? 1 : rw + rq;
+    R2[k] = (k == 0 || k == d) ? 1 : std::min(R1[k], caps[k]) + rq;
+  }
+}
+
+bool request_valid(const tt_request* r) {
+  if (!r || r->scheme < TT_CGS || r->scheme > TT_MGS2 || r->b < 0 || (r->b > 0 && !r->basis)) return false;
+  if (r->w.ncomp < 1 || !r->w.comp || !r->w.coef) return false;
+  return true;
+}
+
+struct EngReq {
+  int64_t id = 0;
+  tt_request r;
+  std::vector<tt_vec> basis;
+  std::vector<double> wcoef;
+  std::vector<tt_vec> wcomp;
+  int passes = 1;
+  bool modified = false;
+  int stage = 0;                 // 0 dots (pass 1), 1 round (pass 1), 2 dots (pass 2), 3 round (pass 2), 4 normalise
+  std::vector<double> rsum;      // column b of R, summed over the passes
+  std::vector<double> rpass;     // coefficients of the current pass
+  tt_vec p1;                     // first-pass result (in the request scratch)
+  double* gram_dev = nullptr;    // basis Gram in the scratch (MGS), or null = identity
+  int dtype = 0;
+};
+
+}  // namespace
+
+struct tt_engine {
+  tt_ctx* c = nullptr;
+  int64_t next_id = 1;
+  std::vector<EngReq*> live;
+  std::vector<std::pair<int64_t, tt_status>> done;
+};
+
+extern "C" {
+
+int64_t tt_request_out_capacity(const tt_request* r) {
+  if (!request_valid(r)) return -1;
+  int64_t R1[TT_MAXD + 1], R2[TT_MAXD + 1];
+  request_ranks(r, R1, R2);
+  return capped_size(r->w.comp[0], scheme_passes(r->scheme) == 2 ? R2 : R1);
+}
+
+int64_t tt_request_scratch_bytes(const tt_request* r) {
+  if (!request_valid(r)) return -1;
+  int64_t R1[TT_MAXD + 1], R2[TT_MAXD + 1];
+  request_ranks(r, R1, R2);
+  size_t bytes = 256;   // alignment slack
+  if (scheme_modified(r->scheme) && r->b > 0) bytes += al256((size_t)r->b * r->b * 8);
+  if (scheme_passes(r->scheme) == 2) bytes += al256((size_t)capped_size(r->w.comp[0], R1) * elt_size(r->w.comp[0].dtype));
+  return (int64_t)bytes;
+}
+
+tt_status tt_engine_create(tt_ctx* c, tt_engine** e) {
+  if (!c || !e) return TT_EINVAL;
+  *e = new tt_engine();
+  (*e)->c = c;
+  return TT_OK;
+}
+
+void tt_engine_destroy(tt_engine* e) {
+  if (!e) return;
+  for (EngReq* q : e->live) delete q;
+  delete e;
+}
+
+int32_t tt_engine_pending(const tt_engine* e) { return e ? (int32_t)(e->live.size() + e->done.size()) : 0; }
+
+tt_status tt_engine_submit(tt_engine* e, const tt_request* r, int64_t* id) {
+  if (!e || !id) return TT_EINVAL;
+  tt_ctx* c = e->c;
+  if (!request_valid(r)) return fail(c, TT_EINVAL, "engine: bad request");
+  tt_status s;
+  if ((s = check_sum(c, &r->w, "w")) != TT_OK) return s;
+  const tt_vec& shape = r->w.comp[0];
+  for (int j = 0; j < r->b; ++j) {
+    if ((s = check_vec(c, &r->basis[j], "basis", true)) != TT_OK) return s;
+    if (!same_shape(r->basis[j], shape)) return fail(c, TT_EINVAL, "engine: basis shape differs from w");
+  }
+  if ((s = check_vec(c, r->q_out, "q_out", false)) != TT_OK) return s;
+  if (!same_shape(*r->q_out, shape)) return fail(c, TT_EINVAL, "engine: q_out shape differs from w");
+  if (!r->r_out) return fail(c, TT_EINVAL, "engine: r_out is NULL");
+  if (!(r->delta >= 0.0) || !std::isfinite(r->delta)) return fail(c, TT_EINVAL, "engine: delta must be >= 0");
+  if (r->q_out->capacity < tt_request_out_capacity(r)) return fail(c, TT_ECAPACITY, "engine: q_out capacity");
+  const int64_t need = tt_request_scratch_bytes(r);
+  if (!r->scratch || r->scratch_bytes < need)
+    return fail(c, TT_ECAPACITY, "engine: request scratch needs " + std::to_string(need) + " bytes");
+  CallScope scope(c);
+  EngReq* q = new EngReq();
+  q->id = e->next_id++;
+  q->r = *r;
+  q->basis.assign(r->basis, r->basis + r->b);
+  q->wcoef.assign(r->w.coef, r->w.coef + r->w.ncomp);
+  q->wcomp.assign(r->w.comp, r->w.comp + r->w.ncomp);
+  q->passes = scheme_passes(r->scheme);
+  q->modified = scheme_modified(r->scheme);
+  q->dtype = shape.dtype;
+  q->rsum.assign(r->b, 0.0);
+  char* base = (char*)(((uintptr_t)r->scratch + 255) & ~(uintptr_t)255);
+  if (q->modified && r->b > 0 && r->basis_gram) {
+    q->gram_dev = (double*)base;
+    const size_t gb = (size_t)r->b * r->b * 8;
+    double* h = (double*)c->pin.alloc(gb);
+    if (!h) {
+      delete q;
+      return fail(c, TT_ENOMEM, "engine: staging");
+    }
+    std::memcpy(h, r->basis_gram, gb);
+    hipError_t he = hipMemcpyAsync(q->gram_dev, h, gb, hipMemcpyHostToDevice, c->stream);
+    if (he != hipSuccess) {
+      delete q;
+      return hip_fail(c, he, "engine: gram upload");
+    }
+  }
+  if (q->modified && r->b > 0) base += al256((size_t)r->b * r->b * 8);
+  if (q->passes == 2) {
+    int64_t R1[TT_MAXD + 1], R2[TT_MAXD + 1];
+    request_ranks(r, R1, R2);
+    q->p1 = *r->q_out;
+    q->p1.data = base;
+    q->p1.capacity = capped_size(shape, R1);
+  }
+  e->live.push_back(q);
+  *id = q->id;
+  return TT_OK;
+}
+
+tt_status tt_engine_step(tt_engine* e, int32_t max_done, int64_t* done_ids, tt_status* done_status,
+                         int32_t* ndone) {
+  if (!e || !ndone || (max_done > 0 && (!done_ids || !done_status))) return TT_EINVAL;
+  tt_ctx* c = e->c;
+  CallScope scope(c);
+  static const double one = 1.0;
+  hipError_t he;
+  tt_status s;
+  auto finish_req = [&](EngReq* q, tt_status st) {
+    e->done.emplace_back(q->id, st);
+    q->stage = -1;
+  };
+  // source sum of the current pass: w, or the rounded first-pass vector
+  auto src_sum = [&](EngReq* q) -> tt_sum {
+    if (q->stage >= 2) return tt_sum{1, &one, &q->p1};
+    return tt_sum{(int32_t)q->wcomp.size(), q->wcoef.data(), q->wcomp.data()};
+  };
+  std::vector<EngReq*> A, B, F;
+  for (EngReq* q : e->live) {
+    if (q->stage == 0 || q->stage == 2) A.push_back(q);
+    else if (q->stage == 1 || q->stage == 3) B.push_back(q);
+    else if (q->stage == 4) F.push_back(q);
+  }
+  for (int dt = 0; dt < 2; ++dt) {
+    // ---- inner products <src, q_j> and projection coefficients of the pass
+    std::vector<EngReq*> grp;
+    for (EngReq* q : A)
+      if (q->dtype == dt) grp.push_back(q);
+    if (!grp.empty()) {
+      std::vector<tt_sum> xs, ys;
+      std::vector<size_t> off;
+      for (EngReq* q : grp) {
+        off.push_back(xs.size());
+        const tt_sum src = src_sum(q);
+        for (int j = 0; j < q->r.b; ++j) {
+          xs.push_back(src);
+          ys.push_back(tt_sum{1, &one, &q->basis[j]});
+        }
+      }
+      const size_t np = xs.size();
+      if (np > 0) {
+        double* D = (double*)dev_scratch(c, np * 8);
+        double* Rd = (double*)dev_scratch(c, np * 8);
+        if (!D || !Rd) return fail(c, TT_ENOMEM, "engine: step buffers");
+        if ((s = dot_pairs(c, (int)np, xs.data(), ys.data(), D)) != TT_OK) return s;
+        std::vector<CoefTask> ct;
+        for (size_t g = 0; g < grp.size(); ++g) {
+          if (grp[g]->r.b == 0) continue;
+          CoefTask t;
+          t.dots = D + off[g];
+          t.gram = grp[g]->gram_dev;
+          t.r = Rd + off[g];
+          t.b = grp[g]->r.b;
+          t.modified = grp[g]->modified ? 1 : 0;
+          ct.push_back(t);
+        }
+        const CoefTask* dct = upload(c, ct);
+        if (!dct) return fail(c, TT_ENOMEM, "engine: task upload");
+        if ((he = launch_coef_batched(dct, (int)ct.size(), c->stream)) != hipSuccess) return hip_fail(c, he, "coef");
+        std::vector<double> hr(np);
+        if ((s = read_doubles(c, Rd, hr.data(), np)) != TT_OK) return s;
+        for (size_t g = 0; g < grp.size(); ++g) {
+          EngReq* q = grp[g];
+          q->rpass.assign(hr.begin() + off[g], hr.begin() + off[g] + q->r.b);
+        }
+      }
+      for (EngReq* q : grp) {
+        if (q->r.b == 0) q->rpass.clear();
+        for (int j = 0; j < q->r.b; ++j) q->rsum[j] += q->rpass[j];
+        q->stage += 1;
+      }
+    }
+  }
+  for (int dt = 0; dt < 2; ++dt) {
+    // ---- rounding of the pass: round(src - sum_j r_j q_j)
+    std::vector<EngReq*> grp;
+    for (EngReq* q : B)
+      if (q->dtype == dt) grp.push_back(q);
+    if (grp.empty()) continue;
+    std::vector<std::vector<double>> coefs(grp.size());
+    std::vector<std::vector<tt_vec>> comps(grp.size());
+    std::vector<tt_sum> sums(grp.size());
+    std::vector<RJob> jobs;
+    std::vector<EngReq*> jq;
+    for (size_t g = 0; g < grp.size(); ++g) {
+      EngReq* q = grp[g];
+      const tt_sum src = src_sum(q);
+      coefs[g].assign(src.coef, src.coef + src.ncomp);
+      comps[g].assign(src.comp, src.comp + src.ncomp);
+      for (int j = 0; j < q->r.b; ++j) {
+        coefs[g].push_back(-q->rpass[j]);
+        comps[g].push_back(q->basis[j]);
+      }
+      sums[g] = tt_sum{(int32_t)comps[g].size(), coefs[g].data(), comps[g].data()};
+      tt_vec* dest = (q->stage == 1 && q->passes == 2) ? &q->p1 : q->r.q_out;
+      RJob jb;
+      make_job(c, &sums[g], q->r.delta, 0, dest, jb);
+      std::vector<RJob> one_job(1, jb);
+      if (round_workspace_bytes(one_job) < 0) {   // a shape the tile kernels do not support
+        finish_req(q, TT_ENOTIMPL);
+        continue;
+      }
+      jobs.push_back(jb);
+      jq.push_back(q);
+    }
+    if (!jobs.empty()) {
+      if ((s = round_jobs(c, jobs)) != TT_OK) return s;
+      for (size_t i = 0; i < jobs.size(); ++i) {
+        EngReq* q = jq[i];
+        if (jobs[i].status != TT_OK) {
+          finish_req(q, jobs[i].status);
+          continue;
+        }
+        q->stage = (q->stage == 1 && q->passes == 2) ? 2 : 4;
+      }
+    }
+  }
+  if (!F.empty()) {
+    // ---- R(b, b) = ||p|| = ||last core|| (cores 0..d-2 left-orthonormal), q = p / ||p||
+    double* N = (double*)dev_scratch(c, F.size() * 8);
+    if (!N) return fail(c, TT_ENOMEM, "engine: norms");
+    std::vector<char*> lastp(F.size());
+    std::vector<int64_t> lastn(F.size());
+    for (size_t k = 0; k < F.size(); ++k) {
+      tt_vec& qo = *F[k]->r.q_out;
+      int64_t off = 0;
+      for (int i = 0; i + 1 < qo.d; ++i) off += qo.r[i] * qo.n[i] * qo.r[i + 1];
+      lastn[k] = qo.r[qo.d - 1] * qo.n[qo.d - 1];
+      lastp[k] = (char*)qo.data + (size_t)off * elt_size(qo.dtype);
+      if ((he = launch_sumsq(qo.dtype, lastp[k], lastn[k], N + k, c->stream)) != hipSuccess)
+        return hip_fail(c, he, "engine: norm");
+      if ((he = launch_scale(qo.dtype, lastp[k], lastn[k], N + k, c->stream)) != hipSuccess)
+        return hip_fail(c, he, "engine: scale");
+    }
+    std::vector<double> hn(F.size());
+    if ((s = read_doubles(c, N, hn.data(), F.size())) != TT_OK) return s;
+    for (int dt = 0; dt < 2; ++dt) {
+      std::vector<tt_sum> xs, ys;
+      std::vector<std::pair<size_t, size_t>> where;   // (request, offset)
+      for (size_t k = 0; k < F.size(); ++k) {
+        EngReq* q = F[k];
+        if (q->dtype != dt || !q->r.gram_out || !(hn[k] > 0.0)) continue;
+        where.emplace_back(k, xs.size());
+        for (int j = 0; j < q->r.b; ++j) {
+          xs.push_back(tt_sum{1, &one, q->r.q_out});
+          ys.push_back(tt_sum{1, &one, &q->basis[j]});
+        }
+      }
+      if (xs.empty()) continue;
+      double* G = (double*)dev_scratch(c, xs.size() * 8);
+      if (!G) return fail(c, TT_ENOMEM, "engine: gram row");
+      if ((s = dot_pairs(c, (int)xs.size(), xs.data(), ys.data(), G)) != TT_OK) return s;
+      std::vector<double> hg(xs.size());
+      if ((s = read_doubles(c, G, hg.data(), hg.size())) != TT_OK) return s;
+      for (auto& w : where) {
+        EngReq* q = F[w.first];
+        std::copy(hg.begin() + w.second, hg.begin() + w.second + q->r.b, q->r.gram_out);
+      }
+    }
+    for (size_t k = 0; k < F.size(); ++k) {
+      EngReq* q = F[k];
+      for (int j = 0; j < q->r.b; ++j) q->r.r_out[j] = q->rsum[j];
+      q->r.r_out[q->r.b] = hn[k];
+      if (hn[k] > 0.0) finish_req(q, TT_OK);
+      else finish_req(q, hn[k] == 0.0 ? TT_EBREAKDOWN : TT_ENONFINITE);
+    }
+  }
+  // retire finished requests, report up to max_done
+  std::vector<EngReq*> keep;
+  for (EngReq* q : e->live) {
+    if (q->stage < 0) delete q;
+    else keep.push_back(q);
+  }
+  e->live.swap(keep);
+  int32_t n = 0;
+  while (n < max_done && !e->done.empty()) {
+    done_ids[n] = e->done.front().first;
+    done_status[n] = e->done.front().second;
+    e->done.erase(e->done.begin());
+    ++n;
+  }
+  *ndone = n;
+  return TT_OK;
+}
+
+}  // extern "C"

@@ -153,6 +153,19 @@ hipError_t launch_axpy(int dtype, const AxpyTask* d_tasks, int ntasks, int64_t m
 // Small FP64 updates of the scheme drivers (single thread, sequential order):
 //   MGS correction   r[j] = dots[j] - sum_{l<j} r[l] * Gq[l*ldg + j]   (j < i)
 //   negated copy     coef[j] = -r[j]
+// Projection coefficients of one pass of a Gram-Schmidt step, for a batch of
+// requests (one thread per request, sequential in j):
+//   CGS: r[j] = dots[j];   MGS: r[j] = dots[j] - sum_{l<j} r[l] * gram[l*b + j]
+// (gram null: the identity).
+struct CoefTask {
+  const double* dots;
+  const double* gram;
+  double* r;
+  int32_t b;
+  int32_t modified;
+};
+hipError_t launch_coef_batched(const CoefTask* d_tasks, int ntasks, hipStream_t s);
+
 hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int i, double* r, double* neg,
                               hipStream_t s);
 // out[j] = a[j] + b[j]

@@ -206,6 +206,18 @@ __global__ void k_mgs_correct(const double* __restrict__ dots, const double* __r
   }
 }
 
+__global__ void k_coef_batched(const CoefTask* __restrict__ tasks, int ntasks) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntasks) return;
+  const CoefTask tk = tasks[t];
+  for (int j = 0; j < tk.b; ++j) {
+    double s = tk.dots[j];
+    if (tk.modified && tk.gram)
+      for (int l = 0; l < j; ++l) s -= tk.r[l] * tk.gram[(int64_t)l * tk.b + j];
+    tk.r[j] = s;
+  }
+}
+
 __global__ void k_add(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a[i] + b[i];
@@ -246,6 +258,12 @@ hipError_t launch_axpy(int dtype, const AxpyTask* d_tasks, int ntasks, int64_t m
 hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int i, double* r, double* neg,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_mgs_correct, dim3(1), dim3(64), 0, s, dots, Gq, ldg, i, r, neg);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_batched(const CoefTask* d_tasks, int ntasks, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_coef_batched, dim3((ntasks + 63) / 64), dim3(64), 0, s, d_tasks, ntasks);
   return hipGetLastError();
 }
 

@@ -97,3 +97,46 @@ def uneven_jobs(seed=30000, njobs=256, d_range=(4, 10), n_choices=(16, 32, 64),
         cores = random_tt(g, [n] * d, ranks, np.float64)
         jobs.append(([c.astype(dtype) for c in cores], (d, n, R)))
     return jobs
+
+
+def serving_solver(g: np.random.Generator, d_range=(5, 8), n_choices=(32, 64, 128), r_range=(4, 9),
+                   b0_range=(10, 39), bmax=40, dtype=np.float32):
+    """One simulated TT-GMRES solver of the serving workload.
+
+    Its vectors share one right part (cores 1..d-1, rank r, right-orthonormal)
+    and differ in the first core U (1 x n x r), so every vector of the solver
+    and every combination of them has TT-rank r: <U_a (x) P, U_b (x) P> is the
+    Frobenius product <U_a, U_b>.  `firsts` holds bmax first cores that are
+    orthonormal in that product; the initial basis uses the first b0.
+    """
+    d = int(g.integers(d_range[0], d_range[1] + 1))
+    n = int(g.choice(np.asarray(n_choices)))
+    r = int(g.integers(r_range[0], r_range[1] + 1))
+    b0 = int(g.integers(b0_range[0], b0_range[1] + 1))
+    right = []
+    for k in range(1, d):
+        r1 = 1 if k == d - 1 else r
+        m = g.standard_normal((r, n * r1))
+        q, _ = np.linalg.qr(m.T)                       # orthonormal columns: rows of the unfolding orthonormal
+        right.append(q.T.reshape(r, n, r1))
+    z = g.standard_normal((n * r, bmax))
+    u, _ = np.linalg.qr(z)
+    firsts = [u[:, j].reshape(1, n, r) for j in range(bmax)]
+    return {"d": d, "n": n, "r": r, "b0": b0, "bmax": bmax, "right": right, "firsts": firsts, "dtype": dtype}
+
+
+def serving_vector(g: np.random.Generator, solver, first):
+    """Cores of the solver's TT whose first core is `first`."""
+    return [first.astype(solver["dtype"])] + [c.astype(solver["dtype"]) for c in solver["right"]]
+
+
+def serving_request(g: np.random.Generator, solver, b):
+    """First core of w = sum_{j<b} c_j q_j + t (c_j ~ N(0, 1/b), t a unit random vector of the solver)."""
+    n, r = solver["n"], solver["r"]
+    t = g.standard_normal((1, n, r))
+    t /= np.linalg.norm(t)
+    c = g.standard_normal(b) / np.sqrt(max(b, 1))
+    w = t.copy()
+    for j in range(min(b, len(solver["firsts"]))):
+        w += c[j] * solver["firsts"][j]
+    return w

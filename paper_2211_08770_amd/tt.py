@@ -17,8 +17,8 @@ import threading
 import numpy as np
 import torch
 
-__all__ = ["TT", "dot", "dot_batched", "axpy", "round", "round_batched", "orthogonalize", "loo",
-           "TTError", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
+__all__ = ["TT", "dot", "dot_batched", "axpy", "norm", "round", "round_batched", "orthogonalize", "loo",
+           "Engine", "TTError", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
 
 TT_MAXD = 64
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -48,6 +48,13 @@ class _Sum(C.Structure):
 class _Stats(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("m_reached", C.c_int32), ("max_pre_rank", C.c_int32),
                 ("max_post_rank", C.c_int32)]
+
+
+class _Request(C.Structure):
+    _fields_ = [("scheme", C.c_int32), ("b", C.c_int32), ("basis", C.POINTER(_Vec)),
+                ("basis_gram", C.POINTER(C.c_double)), ("w", _Sum), ("delta", C.c_double),
+                ("q_out", C.POINTER(_Vec)), ("r_out", C.POINTER(C.c_double)), ("gram_out", C.POINTER(C.c_double)),
+                ("scratch", C.c_void_p), ("scratch_bytes", C.c_int64)]
 
 
 _lib = None
@@ -102,6 +109,19 @@ def _load():
         lib.tt_orthogonalize.restype = C.c_int
         lib.tt_loo.argtypes = [P, C.c_int32, C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.tt_loo.restype = C.c_int
+        lib.tt_request_out_capacity.argtypes = [C.POINTER(_Request)]
+        lib.tt_request_out_capacity.restype = C.c_int64
+        lib.tt_request_scratch_bytes.argtypes = [C.POINTER(_Request)]
+        lib.tt_request_scratch_bytes.restype = C.c_int64
+        lib.tt_engine_create.argtypes = [P, C.POINTER(P)]
+        lib.tt_engine_create.restype = C.c_int
+        lib.tt_engine_destroy.argtypes = [P]
+        lib.tt_engine_submit.argtypes = [P, C.POINTER(_Request), C.POINTER(C.c_int64)]
+        lib.tt_engine_submit.restype = C.c_int
+        lib.tt_engine_step.argtypes = [P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int32)]
+        lib.tt_engine_step.restype = C.c_int
+        lib.tt_engine_pending.argtypes = [P]
+        lib.tt_engine_pending.restype = C.c_int32
         _lib = lib
         return lib
 
@@ -388,3 +408,95 @@ def loo(Q):
     ctx.ensure_ws(64 << 20)
     ctx.call_with_ws(lambda: ctx.lib.tt_loo(ctx.h, m, vq, out, G))
     return np.array(out[:]), np.array(G[:]).reshape(m, m)
+
+
+class Engine:
+    """Continuous-batching engine of Gram-Schmidt steps (tt_engine_* of the C ABI).
+
+    submit() hands one request -- orthogonalise the lazy sum ``w`` against an
+    orthonormal resident ``basis`` with ``scheme`` -- and returns its id; each
+    step() advances every request in flight by one stage and returns the
+    requests that completed, as ``{id: (status, q, r, gram_row)}``.
+    """
+
+    def __init__(self, device=None):
+        self.ctx = _ctx(device)
+        h = C.c_void_p()
+        self.ctx.check(self.ctx.lib.tt_engine_create(self.ctx.h, C.byref(h)))
+        self.h = h
+        self.inflight = {}
+
+    def __del__(self):
+        try:
+            self.ctx.lib.tt_engine_destroy(self.h)
+        except Exception:
+            pass
+
+    @staticmethod
+    def _request(scheme, basis, basis_gram, w, delta):
+        hb = [t._vec() for t in basis]
+        hw = _SumHolder(w)
+        req = _Request()
+        req.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        req.b = len(basis)
+        keep = {"w": hw}
+        if basis:
+            arr = (_Vec * len(hb))(*hb)
+            keep["basis"] = arr
+            req.basis = C.cast(arr, C.POINTER(_Vec))
+        if basis_gram is not None and basis:
+            g = np.ascontiguousarray(np.asarray(basis_gram, dtype=np.float64).reshape(len(basis), len(basis)))
+            keep["gram"] = g
+            req.basis_gram = g.ctypes.data_as(C.POINTER(C.c_double))
+        req.w = hw.s
+        req.delta = float(delta)
+        return req, keep
+
+    def footprint(self, scheme, basis, w, delta=0.0):
+        """Device bytes a request holds while in flight: output TT and scratch."""
+        req, keep = self._request(scheme, basis, None, w, delta)
+        first = _as_terms(w)[0][1]
+        elt = first.data.element_size()
+        return int(self.ctx.lib.tt_request_out_capacity(C.byref(req))) * elt + \
+            int(self.ctx.lib.tt_request_scratch_bytes(C.byref(req)))
+
+    def submit(self, scheme, basis, w, delta, basis_gram=None, want_gram=True):
+        req, keep = self._request(scheme, basis, basis_gram, w, delta)
+        first = _as_terms(w)[0][1]
+        cap = int(self.ctx.lib.tt_request_out_capacity(C.byref(req)))
+        nbytes = int(self.ctx.lib.tt_request_scratch_bytes(C.byref(req)))
+        if cap < 0 or nbytes < 0:
+            raise TTError(-1, "bad request")
+        q = TT(torch.empty(max(cap, 1), dtype=first.dtype, device=first.data.device), first.n, [1] * (first.d + 1))
+        qv = q._vec()
+        scratch = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=first.data.device)
+        r = (C.c_double * (len(basis) + 1))()
+        g = (C.c_double * max(len(basis), 1))()
+        req.q_out = C.pointer(qv)
+        req.r_out = r
+        req.gram_out = g if want_gram else None
+        req.scratch = scratch.data_ptr()
+        req.scratch_bytes = scratch.numel()
+        rid = C.c_int64(0)
+        self.ctx.check(self.ctx.lib.tt_engine_submit(self.h, C.byref(req), C.byref(rid)))
+        self.inflight[rid.value] = (q, qv, scratch, r, g, len(basis), want_gram, keep, req)
+        return rid.value
+
+    def step(self):
+        n = max(len(self.inflight), 1)
+        ids = (C.c_int64 * n)()
+        sts = (C.c_int * n)()
+        nd = C.c_int32(0)
+        self.ctx.call_with_ws(lambda: self.ctx.lib.tt_engine_step(self.h, n, ids, sts, C.byref(nd)))
+        out = {}
+        for k in range(nd.value):
+            q, qv, scratch, r, g, b, want_gram, keep, req = self.inflight.pop(ids[k])
+            if sts[k] == 0:
+                q.r = [int(qv.r[i]) for i in range(q.d + 1)]
+                q.data = q.data[: q.size()]
+            out[ids[k]] = (_STATUS.get(sts[k], sts[k]), q, np.array(r[: b + 1]),
+                           np.array(g[:b]) if want_gram else None)
+        return out
+
+    def pending(self):
+        return int(self.ctx.lib.tt_engine_pending(self.h))

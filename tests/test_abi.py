@@ -23,7 +23,7 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for required in ("tt_round", "tt_round_batched", "tt_norm", "tt_axpy", "tt_dot", "tt_dot_batched",
+    for required in ("tt_round", "tt_round_batched", "tt_norm", "tt_engine_step", "tt_axpy", "tt_dot", "tt_dot_batched",
                      "tt_orthogonalize", "tt_loo", "tt_ctx_create", "tt_ctx_destroy"):
         assert required in names
 
