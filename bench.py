@@ -107,6 +107,38 @@ def run_config(tt, torch, dtype, delta, steps, warmup, profile):
     return {"rate": steps / dt, "ms": 1e3 * dt / steps, "ranks": out.r, "rel_err": nd / nx, "prof": prof}
 
 
+def run_batched(tt, torch, reps=3):
+    """256 independent uneven roundings (orders 4-10, modes 16/32/64, ranks 8-128, FP32, delta 1e-5)
+    in shared batched launches; value in roundings/s; validity: output ranks equal the caps and a
+    sample of errors ||x - x~|| / ||x|| <= delta."""
+    from paper_2211_08770_amd import synth
+    jobs = synth.uneven_jobs()
+    xs = [tt.TT.from_cores(c, device="cuda", dtype=torch.float32) for c, _ in jobs]
+    outs = tt.round_batched(xs, 1e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        outs = tt.round_batched(xs, 1e-5)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    caps_ok = all(o.r == [1] + [min(R, n ** k, n ** (d - k)) for k in range(1, d)] + [1]
+                  for o, (_, (d, n, R)) in zip(outs, jobs))
+    errs = [tt.norm([(1.0, xs[i]), (-1.0, outs[i])]) / tt.norm(xs[i]) for i in range(0, len(xs), 16)]
+    return {"value": round(len(xs) / dt, 2), "unit": "TT-roundings/s", "jobs": len(xs), "ms_per_batch": round(1e3 * dt, 3),
+            "ranks_equal_caps": caps_ok, "max_sampled_rel_err": max(errs),
+            "workload": "256 uneven jobs: d~U{4..10}, n~U{16,32,64}, rank~U{8..128}, N(0,1) FP32 cores, delta=1e-5"}
+
+
+def run_serving(torch, qps=100.0, nreq=150):
+    """Poisson serving trace: MGS2 steps of 64 simulated TT-GMRES solvers against resident bases."""
+    from paper_2211_08770_amd import serve
+    solvers, g = serve.make_solvers(64, seed=40000, dtype=torch.float32)
+    rep = serve.run_trace(solvers, g, qps=qps, nreq=nreq, delta=1e-6)
+    rep["workload"] = ("64 solvers, d~U{5..8}, n~U{32,64,128}, solver rank~U{4..9}, basis b0~U{10..39} (restart at 40), "
+                       "MGS2 FP32-bulk, delta=1e-6, 8 GiB admission budget")
+    return rep
+
+
 def cpu_baseline(seconds):
     import numpy as np
     import oracle
@@ -190,6 +222,9 @@ def main():
         "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
         "roofline": roof,
     }
+    if not args.headline_only:
+        line["batched_uneven"] = run_batched(tt, torch)
+        line["serving"] = run_serving(torch)
     if not args.no_cpu and not args.headline_only:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line))
