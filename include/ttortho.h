@@ -166,7 +166,8 @@ int64_t tt_round_workspace_bytes(const tt_sum* x);
  * m*m column-major, upper triangular, A ~ Q R: column i holds the
  * projections of a_i), loo (HOST [m], nullable: ||I_k - Q_k^T Q_k||_2 for
  * k = 1..m), stats (nullable).  rank_guard > 0 stops with TT_EGUARD when a
- * vector to be rounded would exceed that bond rank.  Errors:
+ * vector to be rounded would exceed that bond rank; q and the columns of R of
+ * the stats->m_reached completed vectors are then valid.  Errors:
  * TT_ENOTSPD (Gram: Cholesky fails), TT_EBREAKDOWN (||p|| = 0). */
 tt_status tt_orthogonalize(tt_ctx* ctx, tt_scheme scheme, int32_t m, const tt_sum* a, double delta,
                            int64_t rank_guard, tt_vec* q, double* R, double* loo,

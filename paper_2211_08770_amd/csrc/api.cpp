@@ -890,6 +890,10 @@ tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum*
       st.max_pre_rank = (int32_t)std::max<int64_t>(st.max_pre_rank, pre);
       if (rank_guard > 0 && pre > rank_guard) {
         st.m_reached = i;
+        // R of the completed prefix (columns < i) is still returned
+        if (passes == 2 && (e = launch_add(R1, R2, R1, m * m, c->stream)) != hipSuccess)
+          return finish(hip_fail(c, e, "R1+R2"));
+        if ((s = read_doubles(c, R1, R, (size_t)m * m)) != TT_OK) return finish(s);
         return finish(fail(c, TT_EGUARD, "pre-round rank " + std::to_string(pre) + " exceeds the guard at vector " +
                                              std::to_string(i)));
       }

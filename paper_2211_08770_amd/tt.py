@@ -359,38 +359,66 @@ def round_batched(xs, deltas, max_ranks=None):
     return [_finish_out(o, vos[i]) for i, o in enumerate(outs)]
 
 
-def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: bool = True, q_capacity=None):
-    """Q, R (and the LOO curve) of the TT vectors / lazy sums A (Algorithms 1-5)."""
+def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: bool = True, q_capacity=None,
+                  partial_on_guard: bool = False):
+    """Q, R (and the LOO curve) of the TT vectors / lazy sums A (Algorithms 1-5).
+
+    With partial_on_guard, a stop at the rank guard returns the completed
+    prefix (Q[:m_reached], R, None, stats with "guard": True) instead of raising.
+    """
     m = len(A)
     hs = [_SumHolder(a) for a in A]
     first = hs[0].tts[0]
     ctx = _ctx(first.data.device.index)
     sums = (_Sum * m)(*[h.s for h in hs])
-    # output capacity: rank caps of the order/mode sizes, bounded by the pre-round ranks
-    if q_capacity is None:
-        caps = [1]
-        for k in range(1, first.d):
-            caps.append(min(int(np.prod(first.n[:k], dtype=object)), int(np.prod(first.n[k:], dtype=object))))
-        caps.append(1)
-        q_capacity = sum(caps[k] * first.n[k] * caps[k + 1] for k in range(first.d))
-        # the pre-round rank of any rounded vector bounds its output ranks
-        tot = [1] + [0] * (first.d - 1) + [1]
-        for h in hs:
-            for t in h.tts:
-                for k in range(1, first.d):
-                    tot[k] += t.r[k]
-        # q ranks never exceed min(caps, sum of all input ranks + previous q's) -> use caps
-        q_capacity = int(min(q_capacity, 1 << 31))
-    Q = [TT(torch.empty(q_capacity, dtype=first.dtype, device=first.data.device), first.n, [1] * (first.d + 1))
-         for _ in range(m)]
+    # output capacity of q_i: bond ranks bounded by the rank caps of the mode sizes, by the pre-round
+    # ranks (Gram: sum_{k<=i} rank(a_k); the Gram-Schmidt schemes: rank(a_i) + sum_{j<i} bound(q_j),
+    # which also bounds their second pass) and by the rank guard
+    d = first.d
+    caps = [1]
+    for k in range(1, d):
+        caps.append(min(int(np.prod(first.n[:k], dtype=object)), int(np.prod(first.n[k:], dtype=object))))
+    caps.append(1)
+    ra = [[sum(t.r[k] for t in h.tts) for k in range(d + 1)] for h in hs]
+    bounds, acc = [], [0] * (d + 1)
+    for i in range(m):
+        if scheme == "gram":
+            acc = [acc[k] + ra[i][k] for k in range(d + 1)]
+            b = list(acc)
+        else:
+            b = [ra[i][k] + sum(bb[k] for bb in bounds) for k in range(d + 1)]
+        b = [1 if k in (0, d) else min(b[k], caps[k], rank_guard if rank_guard > 0 else b[k]) for k in range(d + 1)]
+        bounds.append(b)
+    sizes = [sum(b[k] * first.n[k] * b[k + 1] for k in range(d)) for b in bounds]
+    if q_capacity is not None:
+        sizes = [min(sz, int(q_capacity)) for sz in sizes]
+    Q = [TT(torch.empty(max(sz, 1), dtype=first.dtype, device=first.data.device), first.n, [1] * (d + 1))
+         for sz in sizes]
     vq = (_Vec * m)(*[q._vec() for q in Q])
     R = (C.c_double * (m * m))()
     L = (C.c_double * m)()
     stats = _Stats()
     ctx.ensure_ws(256 << 20)
-    ctx.call_with_ws(lambda: ctx.lib.tt_orthogonalize(ctx.h, SCHEMES[scheme], m, sums, float(delta),
-                                                      int(rank_guard), vq, R, L if with_loo else None,
-                                                      C.byref(stats)))
+    call = lambda: ctx.lib.tt_orthogonalize(ctx.h, SCHEMES[scheme], m, sums, float(delta), int(rank_guard), vq, R,
+                                            L if with_loo else None, C.byref(stats))
+    if partial_on_guard:
+        guarded = []
+
+        def call_guard():
+            st = call()
+            if st == -8:
+                guarded.append(True)
+                return 0
+            return st
+        ctx.call_with_ws(call_guard)
+        if guarded:
+            k = stats.m_reached
+            Qp = [_finish_out(Q[i], vq[i]) for i in range(k)]
+            Rm = np.array(R[:], dtype=np.float64).reshape(m, m).T.copy()
+            return Qp, Rm, None, {"rounds": stats.rounds, "m_reached": k, "max_pre_rank": stats.max_pre_rank,
+                                  "max_post_rank": stats.max_post_rank, "guard": True}
+    else:
+        ctx.call_with_ws(call)
     Q = [_finish_out(q, vq[i]) for i, q in enumerate(Q)]
     Rm = np.array(R[:], dtype=np.float64).reshape(m, m).T.copy()   # column-major -> R[j, i]
     st = {"rounds": stats.rounds, "m_reached": stats.m_reached, "max_pre_rank": stats.max_pre_rank,

@@ -108,3 +108,39 @@ def test_loo_entry_point_matches_oracle():
     loo, G = tt.loo(Q)
     assert np.allclose(G, oracle.gram_of(ref.Q), atol=1e-13)
     assert np.allclose(loo, oracle.loo_curve(ref.Q), rtol=1e-8, atol=1e-14)
+
+
+def _config2_inputs():
+    # m = 50 TT-vectors of order 6, n = 64, generating ranks 8, cond(Gram) = 1e10
+    return conditioned_inputs(20000, 50, 6, 64, 8, 1e10)
+
+
+def test_gram_fp32_dots_report_singular_gram_at_condition_1e10():
+    """With FP32 dots the Gram matrix at cond 1e10 is numerically singular: reported, never hidden."""
+    tt = need_gpu()
+    X, C, M = _config2_inputs()
+    A = [dev_sum([(a, [c.astype(np.float32) for c in x]) for a, x in s], torch.float32) for s in X]
+    with pytest.raises(tt.TTError) as ei:
+        tt.orthogonalize("gram", A, 1e-5, rank_guard=384)
+    assert ei.value.status == "TT_ENOTSPD"
+
+
+@pytest.mark.parametrize("scheme,delta", [("gram", 1e-3), ("gram", 1e-7), ("cgs2", 1e-5)])
+def test_config2_fp64_prefix_under_rank_guard(scheme, delta):
+    """FP64 CGS2 / Gram on 50 vectors: the run stops at the rank guard with TT_EGUARD and
+    the completed prefix equals the oracle run on that prefix (step i only uses vectors <= i)."""
+    tt = need_gpu()
+    X, C, M = _config2_inputs()
+    A = [dev_sum(s) for s in X]
+    guard = 384
+    Q, R, _, st = tt.orthogonalize(scheme, A, delta, rank_guard=guard, with_loo=False, partial_on_guard=True)
+    assert st.get("guard") and 1 <= st["m_reached"] < 50
+    assert st["max_pre_rank"] > guard
+    k = min(st["m_reached"], 4)
+    ref = oracle.orthogonalize(scheme, X[:k], delta)
+    for i in range(k):
+        kap = math.sqrt(np.linalg.cond(M[: i + 1, : i + 1]))
+        tol = 1e-11 * max(1.0, kap ** POW[scheme])
+        assert np.allclose(R[: i + 1, i], ref.R[: i + 1, i], rtol=0, atol=tol * max(1.0, np.abs(ref.R[:, i]).max()))
+        qd = diff_norm(host_cores(Q[i]), ref.Q[i]) / oracle.tt_norm(ref.Q[i])
+        assert qd <= max(tol, 2 * delta), (scheme, i, qd)
