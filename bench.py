@@ -88,8 +88,10 @@ def run_config(tt, torch, dtype, delta, steps, warmup, profile):
     x = [(a, tt.TT.from_cores(c, device="cuda", dtype=dtype)) for a, c in terms]
     ctx = tt._ctx()
     ctx.lib.tt_ctx_set_profiling.argtypes = [C.c_void_p, C.c_int]
-    for _ in range(warmup):
+    tt.set_autotune(True)   # the first (warm-up) call times candidate TSQR tree shapes once
+    for _ in range(max(warmup, 1)):
         out = tt.round(x, delta)
+        tt.set_autotune(False)
     torch.cuda.synchronize()
     if profile:
         ctx.lib.tt_ctx_set_profiling(ctx.h, 1)
@@ -114,7 +116,9 @@ def run_batched(tt, torch, reps=3):
     from paper_2211_08770_amd import synth
     jobs = synth.uneven_jobs()
     xs = [tt.TT.from_cores(c, device="cuda", dtype=torch.float32) for c, _ in jobs]
+    tt.set_autotune(True)
     outs = tt.round_batched(xs, 1e-5)
+    tt.set_autotune(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
@@ -220,6 +224,8 @@ def main():
             "value": round(res64b["rate"], 3), "ms_per_step": round(res64b["ms"], 4),
             "rel_err": res64b["rel_err"], "out_ranks": res64b["ranks"]},
         "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
+        "tsqr_tree_shapes": {"6400x200": tt.tune_tsqr(6400, 200, torch.float32),
+                             "640x200": tt.tune_tsqr(640, 200, torch.float32)},
         "roofline": roof,
     }
     if not args.headline_only:

@@ -110,6 +110,16 @@ tt_status tt_ctx_profile(const tt_ctx* ctx, int kind, double* ms, int64_t* launc
                          double* bytes);
 const char* tt_profile_kind_name(int kind);
 
+/* Autotuning of the TSQR tree shapes (rows of a leaf tile, children per tree
+ * node).  When on, a TT-round call first times a few candidate shapes on
+ * synthetic data for every QR shape class it has not met before (dtype,
+ * columns, ceil(log2 rows)) and keeps the fastest for the rest of the
+ * process; results do not depend on the shape, only the time does. */
+tt_status tt_ctx_set_autotune(tt_ctx* ctx, int on);
+/* Tune one shape class now; leaf_rows and fanin (nullable) receive the choice.
+ * Needs workspace for a rows x cols matrix and its tree (TT_ECAPACITY otherwise). */
+tt_status tt_tune_tsqr(tt_ctx* ctx, int64_t rows, int64_t cols, int32_t dtype, int32_t* leaf_rows, int32_t* fanin);
+
 /* Human-readable status and last error message of this context. */
 const char* tt_status_str(tt_status s);
 const char* tt_last_error(const tt_ctx* ctx);

@@ -447,6 +447,30 @@ size_t tt_ctx_required_bytes(const tt_ctx* c) { return c ? c->required : 0; }
 
 const char* tt_last_error(const tt_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+tt_status tt_ctx_set_autotune(tt_ctx* c, int on) {
+  if (!c) return TT_EINVAL;
+  c->autotune = on != 0;
+  return TT_OK;
+}
+
+tt_status tt_tune_tsqr(tt_ctx* c, int64_t rows, int64_t cols, int32_t dtype, int32_t* leaf_rows, int32_t* fanin) {
+  if (!c || rows < 1 || cols < 1 || (dtype != TT_F64 && dtype != TT_F32)) return fail(c, TT_EINVAL, "tune: bad shape");
+  CallScope scope(c);
+  const size_t mark = c->ws_off;
+  c->ws_overflow = false;
+  TreeShape best;
+  tt_status s = tune_tree(c, rows, cols, dtype, &best);
+  c->ws_off = mark;
+  if (s != TT_OK) return s;
+  if (!tuned_shape(rows, cols, dtype, nullptr)) {
+    c->required = std::max(c->required, (size_t)(rows * cols * (int64_t)elt_size(dtype)) * 3 + (1 << 20));
+    return fail(c, TT_ECAPACITY, "tune: workspace too small for the synthetic matrix and its tree");
+  }
+  if (leaf_rows) *leaf_rows = best.leaf_rows;
+  if (fanin) *fanin = best.fanin;
+  return TT_OK;
+}
+
 tt_status tt_ctx_set_profiling(tt_ctx* c, int on) {
   if (!c) return TT_EINVAL;
   c->prof = on != 0;

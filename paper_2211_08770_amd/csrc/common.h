@@ -164,6 +164,7 @@ struct CoefTask {
   int32_t b;
   int32_t modified;
 };
+hipError_t launch_fill_pattern(int dtype, void* x, int64_t n, hipStream_t s);
 hipError_t launch_coef_batched(const CoefTask* d_tasks, int ntasks, hipStream_t s);
 
 hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int i, double* r, double* neg,

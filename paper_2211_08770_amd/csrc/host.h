@@ -48,6 +48,7 @@ struct tt_ctx {
   std::string err;
   // profiler: HIP events around each launch on this context's stream
   bool prof = false;
+  bool autotune = false;       // time candidate TSQR tree shapes for unseen shapes
   std::vector<tto::ProfRec> prof_open;
   std::vector<hipEvent_t> prof_pool;
   double prof_ms[tto::PK_COUNT] = {0};
@@ -113,6 +114,19 @@ struct Carver {
 };
 bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs, int64_t cs,
                std::string* why);
+
+// TSQR tree shape: rows of a leaf tile and children per tree node.  The
+// autotuner times candidate shapes on synthetic data once per (dtype, N,
+// ceil(log2 M)) and records the fastest; plan_tree uses a recorded shape when
+// there is one, else default_shape.
+struct TreeShape {
+  int32_t leaf_rows;
+  int32_t fanin;
+};
+TreeShape default_shape(int64_t M, int64_t N);
+bool tuned_shape(int64_t M, int64_t N, int dtype, TreeShape* out);
+void set_tuned_shape(int64_t M, int64_t N, int dtype, TreeShape sh);
+tt_status tune_tree(tt_ctx* c, int64_t M, int64_t N, int dtype, TreeShape* best);
 
 // ---- rounding jobs ---------------------------------------------------------
 struct Comp {

@@ -2,6 +2,8 @@
 // component pairs), norms and scaling, block copies of TT sums, the FP64
 // Cholesky + triangular inverse of the Gram scheme, and the matrices whose
 // 2-norms give the loss of orthogonality.
+#include <algorithm>
+
 #include "common.h"
 
 namespace tto {
@@ -218,6 +220,19 @@ __global__ void k_coef_batched(const CoefTask* __restrict__ tasks, int ntasks) {
   }
 }
 
+// Deterministic values in [-1, 1) from an integer hash of the index (synthetic
+// matrices for timing tile shapes; the values do not matter to the timing).
+template <typename T>
+__global__ void k_fill_pattern(T* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 32;
+    x[i] = (T)((double)(h >> 11) * (1.0 / 4503599627370496.0) - 1.0);
+  }
+}
+
 __global__ void k_add(const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = a[i] + b[i];
@@ -264,6 +279,14 @@ hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int
 hipError_t launch_coef_batched(const CoefTask* d_tasks, int ntasks, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_coef_batched, dim3((ntasks + 63) / 64), dim3(64), 0, s, d_tasks, ntasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_pattern(int dtype, void* x, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  if (dtype == 0) hipLaunchKernelGGL(k_fill_pattern<double>, dim3(blocks), dim3(256), 0, s, (double*)x, n);
+  else hipLaunchKernelGGL(k_fill_pattern<float>, dim3(blocks), dim3(256), 0, s, (float*)x, n);
   return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "host.h"
 
@@ -28,6 +30,40 @@ namespace {
 int npanels(int64_t k) { return (int)((k + QR_NB - 1) / QR_NB); }
 
 }  // namespace
+
+// ---- tree shapes picked by the autotuner (process-wide: a property of the
+// device and the shape, shared by every context so that workspace sizing and
+// planning always agree)
+namespace {
+std::mutex g_tune_mu;
+std::map<uint64_t, TreeShape> g_tune;
+}  // namespace
+
+uint64_t tune_key(int64_t M, int64_t N, int dtype) {
+  int lb = 0;
+  while (lb < 62 && (int64_t(1) << lb) < M) ++lb;
+  return (uint64_t)(dtype & 1) | ((uint64_t)N << 1) | ((uint64_t)lb << 40);
+}
+
+bool tuned_shape(int64_t M, int64_t N, int dtype, TreeShape* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(M, N, dtype));
+  if (it == g_tune.end()) return false;
+  if (out) *out = it->second;
+  return true;
+}
+
+void set_tuned_shape(int64_t M, int64_t N, int dtype, TreeShape sh) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[tune_key(M, N, dtype)] = sh;
+}
+
+TreeShape default_shape(int64_t M, int64_t N) {
+  TreeShape sh;
+  sh.leaf_rows = (int32_t)(M <= QR_MAXROWS ? M : std::min<int64_t>(QR_MAXROWS, std::max<int64_t>(2 * N, 64)));
+  sh.fanin = (int32_t)std::max<int64_t>(2, QR_MAXROWS / std::max<int64_t>(N, 1));
+  return sh;
+}
 
 void* Carver::take(size_t bytes) {
   bytes = (bytes + 255) & ~(size_t)255;
@@ -45,8 +81,19 @@ int Tree::kr() const {
 
 const void* Tree::root_R() const { return lvl.back()[0].tile; }
 
+bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs, int64_t cs,
+                     TreeShape sh, std::string* why);
+
 bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs, int64_t cs,
                std::string* why) {
+  TreeShape sh = default_shape(M, N);
+  TreeShape tuned;
+  if (tuned_shape(M, N, dtype, &tuned)) sh = tuned;
+  return plan_tree_shape(cv, t, M, N, dtype, src, rs, cs, sh, why);
+}
+
+bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs, int64_t cs,
+                     TreeShape req, std::string* why) {
   t.M = M;
   t.N = N;
   t.leaf_dtype = dtype;
@@ -57,8 +104,14 @@ bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void*
     return false;
   }
   const size_t elt = elt_size(dtype);
+  // a requested shape must keep every tile within the LDS panel: leaves of
+  // at least min(N, M) rows, nodes of at most QR_MAXROWS stacked rows
+  TreeShape sh = default_shape(M, N);
+  if (req.leaf_rows >= std::min<int64_t>(N, M) && req.leaf_rows <= QR_MAXROWS && req.fanin >= 2 &&
+      (int64_t)req.fanin * std::min<int64_t>(req.leaf_rows, N) <= QR_MAXROWS)
+    sh = req;
   int64_t b;
-  if (M <= QR_MAXROWS) {
+  if (M <= QR_MAXROWS && sh.leaf_rows >= M) {
     b = M;
   } else {
     if (N > QR_MAXROWS / 2) {
@@ -68,7 +121,7 @@ bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void*
                " needs columns <= " + std::to_string(QR_MAXROWS / 2) + ")";
       return false;
     }
-    b = std::min<int64_t>(QR_MAXROWS, std::max<int64_t>(2 * N, 64));
+    b = sh.leaf_rows;
   }
   const int64_t nleaves = (M + b - 1) / b;
   std::vector<QrTask> leaves;
@@ -91,7 +144,7 @@ bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void*
     t.leaf_row0.push_back(r0);
   }
   t.lvl.push_back(std::move(leaves));
-  const int64_t g = std::max<int64_t>(2, QR_MAXROWS / N);
+  const int64_t g = sh.fanin;
   while (t.lvl.back().size() > 1) {
     const std::vector<QrTask>& prev = t.lvl.back();
     std::vector<QrTask> nodes;
@@ -250,21 +303,44 @@ struct JobState {
   bool alive = true;
 };
 
-// measure the bytes a tree plan needs
+// Bytes a tree plan of any M' x N matrix with M' <= M needs, whatever shape the
+// autotuner picks for it: the most storage goes to the shape with the
+// shortest leaves (N rows) and fan-in 2 (most stacked triangles), so that
+// shape is measured.  (Used where the row count is known only as a bound.)
+TreeShape worst_shape(int64_t M, int64_t N) {
+  TreeShape sh;
+  sh.leaf_rows = (int32_t)std::min<int64_t>(std::max<int64_t>(N, 1), QR_MAXROWS);
+  sh.fanin = 2;
+  if (M <= QR_MAXROWS && N >= M) sh.leaf_rows = (int32_t)M;
+  return sh;
+}
+
 size_t tree_bytes(int64_t M, int64_t N, int dtype) {
-  Carver cv;
-  cv.measure = true;
-  Tree t;
-  if (!plan_tree(cv, t, M, N, dtype, nullptr, 1, 1, nullptr)) return 0;
-  return cv.off;
+  size_t best = 0;
+  for (int pass = 0; pass < 2; ++pass) {   // the default/tuned plan and the worst legal shape
+    Carver cv;
+    cv.measure = true;
+    Tree t;
+    const bool ok = pass == 0 ? plan_tree(cv, t, M, N, dtype, nullptr, 1, 1, nullptr)
+                              : plan_tree_shape(cv, t, M, N, dtype, nullptr, 1, 1, worst_shape(M, N), nullptr);
+    if (!ok) return 0;
+    best = std::max(best, cv.off);
+  }
+  return best;
 }
 
 size_t tree_apply_bytes(int64_t M, int64_t N, int dtype, int64_t tcols) {
-  Carver cv;
-  cv.measure = true;
-  Tree t;
-  if (!plan_tree(cv, t, M, N, dtype, nullptr, 1, 1, nullptr)) return 0;
-  return apply_work_bytes(t, tcols);
+  size_t best = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    Carver cv;
+    cv.measure = true;
+    Tree t;
+    const bool ok = pass == 0 ? plan_tree(cv, t, M, N, dtype, nullptr, 1, 1, nullptr)
+                              : plan_tree_shape(cv, t, M, N, dtype, nullptr, 1, 1, worst_shape(M, N), nullptr);
+    if (!ok) return 0;
+    best = std::max(best, apply_work_bytes(t, tcols));
+  }
+  return best;
 }
 
 // plan buffers of one job (workspace carving); returns false on unsupported shape
@@ -404,6 +480,120 @@ tt_status launch_apply_plans(tt_ctx* c, std::vector<std::vector<ApplyLevel>>& pl
 
 }  // namespace
 
+tt_status tune_tree(tt_ctx* c, int64_t M, int64_t N, int dtype, TreeShape* best_out) {
+  const TreeShape def = default_shape(M, N);
+  if (best_out) *best_out = def;
+  if (M < 1 || N < 1) return TT_OK;
+  // candidate leaf heights: the whole matrix when it fits one tile, and multiples of N
+  std::vector<int64_t> bs;
+  if (M <= QR_MAXROWS) bs.push_back(M);
+  for (double f : {1.0, 1.5, 2.0, 3.0, 4.0, 6.0}) {
+    int64_t b = ((int64_t)std::ceil(f * (double)std::max<int64_t>(N, 16)) + 15) / 16 * 16;
+    if (b >= N && b <= QR_MAXROWS && b < M) bs.push_back(b);
+  }
+  for (int64_t b : {256, 512, 768})
+    if (b >= N && b < M) bs.push_back(b);
+  std::sort(bs.begin(), bs.end());
+  bs.erase(std::unique(bs.begin(), bs.end()), bs.end());
+  std::vector<TreeShape> cand;
+  for (int64_t b : bs) {
+    const int64_t kc = std::min<int64_t>(b, N);
+    if (b >= M) {
+      cand.push_back(TreeShape{(int32_t)b, def.fanin});
+      continue;
+    }
+    for (int64_t g : {2, 3, 4, 6, 8, 12, 16})
+      if (g * kc <= QR_MAXROWS) cand.push_back(TreeShape{(int32_t)b, (int32_t)g});
+  }
+  if (cand.empty()) return TT_OK;
+  const size_t elt = elt_size(dtype);
+  const size_t mark = c->ws_off;
+  struct Reset {
+    tt_ctx* c;
+    size_t off;
+    ~Reset() { c->ws_off = off; }
+  } reset{c, mark};
+  const bool overflow0 = c->ws_overflow;
+  void* src = ws_alloc(c, (size_t)M * N * elt);
+  if (!src) {
+    c->ws_overflow = overflow0;
+    return TT_OK;   // no room to tune here: the default shape stays in use
+  }
+  hipError_t e = launch_fill_pattern(dtype, src, M * N, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "tune fill");
+  hipEvent_t e0, e1;
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(c, e, "tune event");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(c, e, "tune event");
+  }
+  const bool prof = c->prof;
+  c->prof = false;
+  TreeShape best = def;
+  float best_ms = 1e30f, def_ms = 1e30f;
+  tt_status st = TT_OK;
+  for (const TreeShape& sh : cand) {
+    const size_t m2 = c->ws_off;
+    Carver cv;
+    cv.ctx = c;
+    Tree t;
+    if (!plan_tree_shape(cv, t, M, N, dtype, src, 1, M, sh, nullptr) || c->ws_overflow) {
+      c->ws_overflow = overflow0;
+      c->ws_off = m2;
+      continue;
+    }
+    std::vector<Tree*> tv(1, &t);
+    // the tree is timed as TT-round uses it: factorisation, then the application of
+    // its Q to a block of min(N, 32) columns (the left-to-right sweep)
+    const int64_t tcols = std::min<int64_t>(N, 32);
+    Carver acv;
+    acv.ctx = c;
+    std::vector<std::vector<ApplyLevel>> plans(1);
+    double* X = (double*)ws_alloc(c, (size_t)N * tcols * 8);
+    void* out = ws_alloc(c, (size_t)M * tcols * elt);
+    if (!X || !out || c->ws_overflow) {
+      c->ws_overflow = overflow0;
+      c->ws_off = m2;
+      continue;
+    }
+    plan_apply(acv, t, X, tcols, tcols, out, dtype, tcols, 1, plans[0]);
+    if (c->ws_overflow) {
+      c->ws_overflow = overflow0;
+      c->ws_off = m2;
+      continue;
+    }
+    if ((e = launch_fill_pattern(TT_F64, X, N * tcols, c->stream)) != hipSuccess) { st = hip_fail(c, e, "tune"); break; }
+    float ms = 1e30f;
+    for (int rep = 0; rep < 5 && st == TT_OK; ++rep) {
+      if ((e = hipEventRecord(e0, c->stream)) != hipSuccess) { st = hip_fail(c, e, "tune"); break; }
+      if ((st = launch_levels_factor(c, tv)) != TT_OK) break;
+      if ((st = launch_apply_plans(c, plans, dtype)) != TT_OK) break;
+      if ((e = hipEventRecord(e1, c->stream)) != hipSuccess) { st = hip_fail(c, e, "tune"); break; }
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = hip_fail(c, e, "tune"); break; }
+      float x = 0.f;
+      if (rep > 0 && hipEventElapsedTime(&x, e0, e1) == hipSuccess) ms = std::min(ms, x);
+    }
+    c->ws_off = m2;
+    if (st != TT_OK) break;
+    const bool is_def = sh.leaf_rows == def.leaf_rows && (sh.fanin == def.fanin || sh.leaf_rows >= M);
+    if (is_def) def_ms = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = sh;
+    }
+  }
+  // keep the default shape unless another one is clearly (5%) faster: timing noise
+  // must not move the choice
+  if (def_ms < 1e29f && best_ms > 0.95f * def_ms) best = def;
+  c->prof = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != TT_OK) return st;
+  set_tuned_shape(M, N, dtype, best);
+  if (best_out) *best_out = best;
+  return TT_OK;
+}
+
 int64_t round_workspace_bytes(const std::vector<RJob>& jobs) {
   tt_ctx tmp;
   tmp.ws = nullptr;
@@ -438,6 +628,22 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     ~WsMark() { c->ws_off = off; }
   } mark{c, c->ws_off};
   c->ws_overflow = false;
+  if (c->autotune) {
+    // shapes of the right-to-left trees (the left-to-right ones are tuned when their rank is known)
+    for (int j = 0; j < nj; ++j) {
+      const RJob& jb = jobs[j];
+      if (jb.d < 2) continue;
+      int64_t s1 = 1;
+      for (int k = jb.d - 1; k >= 1; --k) {
+        const int64_t M = jb.n[k] * s1, N = jb.R[k];
+        if (!tuned_shape(M, N, jb.dtype, nullptr)) {
+          tt_status ts = tune_tree(c, M, N, jb.dtype, nullptr);
+          if (ts != TT_OK) return ts;
+        }
+        s1 = std::min<int64_t>(jb.R[k], jb.n[k] * s1);
+      }
+    }
+  }
   for (int j = 0; j < nj; ++j) {
     RJob& jb = jobs[j];
     int64_t need = 0;
@@ -657,6 +863,10 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       cv.cap = js.lr_cap;
       std::string why;
       const int64_t M = js.t[k] * jb.n[k], N = js.s[k + 1];
+      if (c->autotune && !tuned_shape(M, N, jb.dtype, nullptr)) {
+        tt_status ts = tune_tree(c, M, N, jb.dtype, nullptr);
+        if (ts != TT_OK) return ts;
+      }
       if (!plan_tree(cv, js.lr, M, N, jb.dtype, js.C, N, 1, &why)) return fail(c, TT_ENOTIMPL, why);
       if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "left-to-right tree block");
       trees.push_back(&js.lr);

@@ -109,6 +109,10 @@ def _load():
         lib.tt_orthogonalize.restype = C.c_int
         lib.tt_loo.argtypes = [P, C.c_int32, C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.tt_loo.restype = C.c_int
+        lib.tt_ctx_set_autotune.argtypes = [P, C.c_int]
+        lib.tt_ctx_set_autotune.restype = C.c_int
+        lib.tt_tune_tsqr.argtypes = [P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        lib.tt_tune_tsqr.restype = C.c_int
         lib.tt_request_out_capacity.argtypes = [C.POINTER(_Request)]
         lib.tt_request_out_capacity.restype = C.c_int64
         lib.tt_request_scratch_bytes.argtypes = [C.POINTER(_Request)]
@@ -308,6 +312,22 @@ def _finish_out(out: TT, v: _Vec):
     out.r = [int(v.r[k]) for k in range(out.d + 1)]
     out.data = out.data[: out.size()]
     return out
+
+
+def set_autotune(on: bool = True, device=None):
+    """Let TT-round time candidate TSQR tree shapes for unseen QR shapes (kept for the process)."""
+    ctx = _ctx(device)
+    ctx.check(ctx.lib.tt_ctx_set_autotune(ctx.h, 1 if on else 0))
+
+
+def tune_tsqr(rows: int, cols: int, dtype=torch.float64, device=None):
+    """Tune the TSQR tree shape of one QR shape class now; returns (leaf_rows, fanin)."""
+    ctx = _ctx(device)
+    lr, fi = C.c_int32(0), C.c_int32(0)
+    ctx.ensure_ws(3 * rows * cols * (8 if dtype == torch.float64 else 4) + (1 << 20))
+    ctx.call_with_ws(lambda: ctx.lib.tt_tune_tsqr(ctx.h, int(rows), int(cols), _F64 if dtype == torch.float64 else _F32,
+                                                  C.byref(lr), C.byref(fi)))
+    return lr.value, fi.value
 
 
 def norm(x) -> float:
