@@ -83,7 +83,9 @@ void* upload_bytes(tt_ctx* c, const void* src, size_t bytes) {
   char* h = c->pin.alloc(bytes);
   if (!d || !h) return nullptr;
   std::memcpy(h, src, bytes);
-  if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->stream) != hipSuccess) return nullptr;
+  if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->upload_stream ? c->upload_stream : c->stream) !=
+      hipSuccess)
+    return nullptr;
   return d;
 }
 
@@ -100,8 +102,23 @@ static hipEvent_t prof_event(tt_ctx* c) {
   return e;
 }
 
-int prof_begin(tt_ctx* c, int kind, double flops, double bytes) {
+hipStream_t side_stream(tt_ctx* c) {
+  if (!c->side && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
+  return c->side;
+}
+
+hipEvent_t dep_event(tt_ctx* c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+int prof_begin(tt_ctx* c, int kind, double flops, double bytes, hipStream_t s) {
   if (!c->prof) return -1;
+  if (!s) s = c->stream;
   ProfRec r;
   r.kind = kind;
   r.flops = flops;
@@ -109,14 +126,14 @@ int prof_begin(tt_ctx* c, int kind, double flops, double bytes) {
   r.start = prof_event(c);
   r.stop = prof_event(c);
   if (!r.start || !r.stop) return -1;
-  if (hipEventRecord(r.start, c->stream) != hipSuccess) return -1;
+  if (hipEventRecord(r.start, s) != hipSuccess) return -1;
   c->prof_open.push_back(r);
   return (int)c->prof_open.size() - 1;
 }
 
-void prof_end(tt_ctx* c, int rec) {
+void prof_end(tt_ctx* c, int rec, hipStream_t s) {
   if (rec < 0 || !c->prof) return;
-  (void)hipEventRecord(c->prof_open[rec].stop, c->stream);
+  (void)hipEventRecord(c->prof_open[rec].stop, s ? s : c->stream);
 }
 
 void prof_collect(tt_ctx* c) {
@@ -147,7 +164,9 @@ struct CallScope {
     (void)hipSetDevice(c->device);
   }
   ~CallScope() {
+    if (c->side) (void)hipStreamSynchronize(c->side);
     (void)hipStreamSynchronize(c->stream);
+    c->ev_used = 0;
     prof_collect(c);
     c->dev.reset();
     c->pin.reset();
@@ -427,8 +446,13 @@ void tt_ctx_destroy(tt_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
   prof_collect(c);
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   c->dev.release();
   c->pin.release();
   delete c;

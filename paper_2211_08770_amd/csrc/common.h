@@ -92,6 +92,22 @@ struct GemmTask {
   int64_t c_ld;
 };
 
+// Strided GEMM C = A B (A, C in the tile dtype, B double) for the left-to-right
+// contraction with an explicitly formed orthogonal factor:
+//   C[r*c_rs + c*c_cs] = sum_k A[r*a_rs + k*a_cs] * B[k*b_rs + c*b_cs]
+struct GemmSTask {
+  const void* A;
+  int64_t a_rs, a_cs;
+  const double* B;
+  int64_t b_rs, b_cs;
+  void* C;
+  int64_t c_rs, c_cs;
+  int32_t M, N, K;
+};
+hipError_t launch_gemm_strided(int dtype, const GemmSTask* d_tasks, int ntasks, int max_m, int max_n, hipStream_t s);
+// X = identity (n x n, row-major, ld = n)
+hipError_t launch_eye(double* X, int n, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // TT inner product of one pair of components (left-to-right contraction).
 // ---------------------------------------------------------------------------

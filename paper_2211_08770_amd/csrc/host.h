@@ -38,6 +38,10 @@ struct ProfRec {
 struct tt_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;  // second stream (default priority) for work off the critical path
+  hipStream_t upload_stream = nullptr;   // stream of task-descriptor uploads (null: stream)
+  std::vector<hipEvent_t> ev_pool;   // timing-free events for stream dependencies
+  size_t ev_used = 0;
   char* ws = nullptr;          // caller workspace
   size_t ws_bytes = 0;
   size_t ws_off = 0;
@@ -86,8 +90,13 @@ inline size_t elt_size(int dtype) { return dtype == TT_F64 ? 8 : 4; }
 
 // Profiler: prof_begin before a launch, prof_end after it (no-ops when off);
 // prof_collect after the stream has drained accumulates the elapsed times.
-int prof_begin(tt_ctx* c, int kind, double flops, double bytes);
-void prof_end(tt_ctx* c, int rec);
+int prof_begin(tt_ctx* c, int kind, double flops, double bytes, hipStream_t s = nullptr);
+void prof_end(tt_ctx* c, int rec, hipStream_t s = nullptr);
+
+// Side stream of the context (created on first use) and a dependency event
+// (recycled when the call ends).  Both streams are drained by every entry point.
+hipStream_t side_stream(tt_ctx* c);
+hipEvent_t dep_event(tt_ctx* c);
 void prof_collect(tt_ctx* c);
 
 // ---- TSQR tree -------------------------------------------------------------

@@ -301,6 +301,13 @@ struct JobState {
   double* d_norm = nullptr;
   int64_t out_off = 0;
   bool alive = true;
+  // explicit orthogonal factors Q_k (row-major (n_k s_{k+1}) x R_k) of the right-to-left
+  // trees, formed on the side stream while the sweep goes on; the left-to-right sweep then
+  // contracts W_k with Q_k by a GEMM instead of applying the tree
+  void* Qx[TT_MAXD] = {nullptr};
+  double* eye = nullptr;
+  char* qx_block = nullptr;
+  size_t qx_cap = 0;
 };
 
 // Bytes a tree plan of any M' x N matrix with M' <= M needs, whatever shape the
@@ -400,6 +407,21 @@ bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why) {
   st.wt = (double*)ws.take((size_t)smax * tmax * 8);
   st.ur = (double*)ws.take((size_t)smax * tmax * 8);
   st.d_norm = (double*)ws.take(64);
+  // explicit Q for the right-to-left cores 2..d-1 (core 1's is needed right after the sweep,
+  // so it keeps the tree application); one identity and one apply scratch shared by them
+  int64_t nmax = 0;
+  size_t qx_work = 0;
+  for (int k = 2; k < d; ++k) {
+    const int64_t M = jb.n[k] * st.s[k + 1], N = jb.R[k];
+    st.Qx[k] = ws.take((size_t)M * st.s[k] * elt);
+    nmax = std::max(nmax, N);
+    qx_work = std::max(qx_work, apply_work_bytes(st.rl[k], N));
+  }
+  if (nmax > 0) {
+    st.eye = (double*)ws.take((size_t)nmax * nmax * 8);
+    st.qx_cap = qx_work;
+    st.qx_block = (char*)ws.take(std::max<size_t>(qx_work, 256));
+  }
   return true;
 }
 
@@ -447,7 +469,9 @@ tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
   return TT_OK;
 }
 
-tt_status launch_apply_plans(tt_ctx* c, std::vector<std::vector<ApplyLevel>>& plans, int out_dtype) {
+tt_status launch_apply_plans(tt_ctx* c, std::vector<std::vector<ApplyLevel>>& plans, int out_dtype,
+                             hipStream_t stream = nullptr) {
+  if (!stream) stream = c->stream;
   int maxL = 0;
   for (auto& p : plans) maxL = std::max(maxL, (int)p.size());
   for (int depth = 0; depth < maxL; ++depth) {
@@ -467,11 +491,11 @@ tt_status launch_apply_plans(tt_ctx* c, std::vector<std::vector<ApplyLevel>>& pl
           fl += apply_flops(a);
           by += (double)a.m * a.ncol * (tdt == 0 ? 8.0 : 4.0) + 2.0 * (double)a.m * a.t * 8.0;
         }
-      const int pr = prof_begin(c, PK_QR_APPLY, fl, by);
+      const int pr = prof_begin(c, PK_QR_APPLY, fl, by, stream);
       int max_rows = 1;
       for (const ApplyTask& a : tasks) max_rows = std::max(max_rows, (int)a.m);
-      hipError_t e = launch_qr_apply(tdt, out_dtype, dt, (int)tasks.size(), max_rows, c->stream);
-      prof_end(c, pr);
+      hipError_t e = launch_qr_apply(tdt, out_dtype, dt, (int)tasks.size(), max_rows, stream);
+      prof_end(c, pr, stream);
       if (e != hipSuccess) return hip_fail(c, e, "qr_apply");
     }
   }
@@ -729,6 +753,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
   }
   int maxd = 0;
   for (const RJob& jb : jobs) maxd = std::max(maxd, jb.d);
+  std::vector<hipEvent_t> qx_done(maxd, nullptr);   // side-stream completion of the explicit Q of a step
   for (int step = 0; step + 1 < maxd; ++step) {
     std::vector<Tree*> trees;
     std::vector<int> act;
@@ -742,6 +767,39 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     if (act.empty()) continue;
     tt_status rs = launch_levels_factor(c, trees);
     if (rs != TT_OK) return rs;
+    // explicit Q_k of cores 2..d-1 on the side stream: the tree applied to the identity
+    {
+      std::vector<std::vector<ApplyLevel>> xplans;
+      for (int j : act) {
+        const int k = jobs[j].d - 1 - step;
+        JobState& js = st[j];
+        if (k < 2 || !js.Qx[k]) continue;
+        const int64_t sk = js.s[k];   // columns of Q_k: min(R_k, n_k s_{k+1})
+        int64_t nmax = 0;
+        for (int kk = 2; kk < jobs[j].d; ++kk) nmax = std::max(nmax, jobs[j].R[kk]);
+        if (k == jobs[j].d - 1 && (e = launch_eye(js.eye, (int)nmax, s)) != hipSuccess) return hip_fail(c, e, "eye");
+        Carver cv;
+        cv.base = js.qx_block;
+        cv.cap = js.qx_cap;
+        std::vector<ApplyLevel> pl;
+        plan_apply(cv, js.rl[k], js.eye, nmax, sk, js.Qx[k], jobs[j].dtype, sk, 1, pl);
+        if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "explicit Q scratch");
+        xplans.push_back(std::move(pl));
+      }
+      if (!xplans.empty()) {
+        hipStream_t side = side_stream(c);
+        hipEvent_t ready = dep_event(c), done = dep_event(c);
+        if (!side || !ready || !done) return fail(c, TT_EDEVICE, "side stream");
+        if ((e = hipEventRecord(ready, s)) != hipSuccess) return hip_fail(c, e, "event");
+        if ((e = hipStreamWaitEvent(side, ready, 0)) != hipSuccess) return hip_fail(c, e, "event");
+        c->upload_stream = side;
+        rs = launch_apply_plans(c, xplans, dtype, side);
+        c->upload_stream = nullptr;
+        if (rs != TT_OK) return rs;
+        if ((e = hipEventRecord(done, side)) != hipSuccess) return hip_fail(c, e, "event");
+        qx_done[step] = done;
+      }
+    }
     // contraction into core k-1
     std::vector<GemmTask> gt;
     std::vector<GemmPart> gp;
@@ -836,12 +894,36 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     for (int j = 0; j < nj; ++j)
       if (st[j].alive && k + 1 < jobs[j].d) act.push_back(j);
     if (act.empty()) break;
-    // (1) C_k = Q_k [W_k^T; 0]
+    // (1) C_k = Q_k [W_k^T; 0]: a GEMM with the explicit Q_k where it was formed, else the tree
     if (k >= 1) {
       std::vector<std::vector<ApplyLevel>> plans;
+      std::vector<GemmSTask> xg;
+      int xm = 0, xn = 0;
       for (int j : act) {
         RJob& jb = jobs[j];
         JobState& js = st[j];
+        if (js.Qx[k]) {
+          hipEvent_t ev = qx_done[jb.d - 1 - k];
+          if (ev && (e = hipStreamWaitEvent(s, ev, 0)) != hipSuccess) return hip_fail(c, e, "event");
+          GemmSTask g;
+          const int64_t M = jb.n[k] * js.s[k + 1], sk = js.s[k];
+          g.A = js.Qx[k];   // M x s_k row-major
+          g.a_rs = sk;
+          g.a_cs = 1;
+          g.B = js.wt;
+          g.b_rs = js.t[k];
+          g.b_cs = 1;
+          g.C = js.C;
+          g.c_rs = 1;
+          g.c_cs = M;
+          g.M = (int32_t)M;
+          g.N = (int32_t)js.t[k];
+          g.K = (int32_t)sk;
+          xg.push_back(g);
+          xm = std::max(xm, g.M);
+          xn = std::max(xn, g.N);
+          continue;
+        }
         Carver cv;
         cv.base = js.ap_block;
         cv.cap = js.ap_cap;
@@ -852,6 +934,19 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       }
       tt_status rs = launch_apply_plans(c, plans, dtype);
       if (rs != TT_OK) return rs;
+      if (!xg.empty()) {
+        const GemmSTask* dxg = upload(c, xg);
+        if (!dxg) return fail(c, TT_ENOMEM, "task upload");
+        double fl = 0.0, by = 0.0;
+        for (const GemmSTask& g : xg) {
+          fl += 2.0 * g.M * g.N * (double)g.K;
+          by += (double)elt * ((double)g.M * g.K + (double)g.M * g.N) + 8.0 * g.K * g.N;
+        }
+        const int pr = prof_begin(c, PK_GEMM, fl, by);
+        e = launch_gemm_strided(dtype, dxg, (int)xg.size(), xm, xn, s);
+        prof_end(c, pr);
+        if (e != hipSuccess) return hip_fail(c, e, "explicit-Q contraction");
+      }
     }
     // (2) TSQR of L(C_k)
     std::vector<Tree*> trees;
