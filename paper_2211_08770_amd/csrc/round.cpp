@@ -291,12 +291,16 @@ struct JobState {
   void* Y[TT_MAXD];
   Tree rl[TT_MAXD];
   void* C = nullptr;
-  char* lr_block = nullptr;
   size_t lr_cap = 0;
   char* ap_block = nullptr;
   size_t ap_cap = 0;
-  Tree lr;
-  double *A = nullptr, *acc = nullptr, *sig = nullptr, *wt = nullptr, *ur = nullptr;
+  // left-to-right trees and U factors, double-buffered by step parity: the output core of
+  // step k is formed on the side stream while step k+1 runs
+  Tree lr[2];
+  char* lr_blk[2] = {nullptr, nullptr};
+  double* urb[2] = {nullptr, nullptr};
+  char* ap_side = nullptr;
+  double *A = nullptr, *acc = nullptr, *sig = nullptr, *wt = nullptr;
   int32_t* perm = nullptr;
   double* d_norm = nullptr;
   int64_t out_off = 0;
@@ -397,15 +401,18 @@ bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why) {
   for (int k = 1; k < d; ++k) apmax = std::max(apmax, apply_work_bytes(st.rl[k], st.tb[k]));
   st.C = ws.take(std::max<size_t>(cmax, 1) * elt);
   st.lr_cap = lrmax;
-  st.lr_block = (char*)ws.take(std::max<size_t>(lrmax, 256));
+  st.lr_blk[0] = (char*)ws.take(std::max<size_t>(lrmax, 256));
+  st.lr_blk[1] = (char*)ws.take(std::max<size_t>(lrmax, 256));
   st.ap_cap = apmax;
   st.ap_block = (char*)ws.take(std::max<size_t>(apmax, 256));
+  st.ap_side = (char*)ws.take(std::max<size_t>(apmax, 256));
   st.A = (double*)ws.take((size_t)smax * smax * 8);
   st.acc = (double*)ws.take((size_t)smax * smax * 8);
   st.sig = (double*)ws.take((size_t)smax * 8);
   st.perm = (int32_t*)ws.take((size_t)smax * 4);
   st.wt = (double*)ws.take((size_t)smax * tmax * 8);
-  st.ur = (double*)ws.take((size_t)smax * tmax * 8);
+  st.urb[0] = (double*)ws.take((size_t)smax * tmax * 8);
+  st.urb[1] = (double*)ws.take((size_t)smax * tmax * 8);
   st.d_norm = (double*)ws.take(64);
   // explicit Q for the right-to-left cores 2..d-1 (core 1's is needed right after the sweep,
   // so it keeps the tree application); one identity and one apply scratch shared by them
@@ -889,6 +896,8 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     st[j].out_off = 0;
     st[j].alive = jobs[j].d >= 2 && jobs[j].status == TT_OK && !jobs[j].orth_only;
   }
+  std::vector<hipEvent_t> out_done(maxd, nullptr);
+  hipEvent_t last_side = nullptr;
   for (int k = 0; k + 1 < maxd; ++k) {
     std::vector<int> act;
     for (int j = 0; j < nj; ++j)
@@ -948,13 +957,16 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
         if (e != hipSuccess) return hip_fail(c, e, "explicit-Q contraction");
       }
     }
-    // (2) TSQR of L(C_k)
+    // (2) TSQR of L(C_k), into the tree block of this step's parity once the output
+    // core of step k-2 (side stream) no longer reads it
+    if (k >= 2 && out_done[k - 2] && (e = hipStreamWaitEvent(s, out_done[k - 2], 0)) != hipSuccess)
+      return hip_fail(c, e, "event");
     std::vector<Tree*> trees;
     for (int j : act) {
       RJob& jb = jobs[j];
       JobState& js = st[j];
       Carver cv;
-      cv.base = js.lr_block;
+      cv.base = js.lr_blk[k & 1];
       cv.cap = js.lr_cap;
       std::string why;
       const int64_t M = js.t[k] * jb.n[k], N = js.s[k + 1];
@@ -962,9 +974,9 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
         tt_status ts = tune_tree(c, M, N, jb.dtype, nullptr);
         if (ts != TT_OK) return ts;
       }
-      if (!plan_tree(cv, js.lr, M, N, jb.dtype, js.C, N, 1, &why)) return fail(c, TT_ENOTIMPL, why);
+      if (!plan_tree(cv, js.lr[k & 1], M, N, jb.dtype, js.C, N, 1, &why)) return fail(c, TT_ENOTIMPL, why);
       if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "left-to-right tree block");
-      trees.push_back(&js.lr);
+      trees.push_back(&js.lr[k & 1]);
     }
     tt_status rs = launch_levels_factor(c, trees);
     if (rs != TT_OK) return rs;
@@ -975,11 +987,12 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       JobState& js = st[j];
       SvdTask t;
       std::memset(&t, 0, sizeof(t));
-      t.R = js.lr.root_R();
-      t.r_ld = js.lr.N;
-      t.r_f32 = js.lr.root_f32();
-      t.kr = js.lr.kr();
-      t.ncol = (int32_t)js.lr.N;
+      const Tree& LR = js.lr[k & 1];
+      t.R = LR.root_R();
+      t.r_ld = LR.N;
+      t.r_f32 = LR.root_f32();
+      t.kr = LR.kr();
+      t.ncol = (int32_t)LR.N;
       t.upper = 1;
       t.bulk_u = (jb.dtype == TT_F64) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
       t.A = js.A;
@@ -991,7 +1004,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       t.max_rank = jb.max_rank;
       t.rank_out = d_ranks + (size_t)j * (TT_MAXD + 1) + (k + 1);
       t.wt = js.wt;
-      t.ur = js.ur;
+      t.ur = js.urb[k & 1];
       t.info = nullptr;
       sv.push_back(t);
     }
@@ -1025,17 +1038,33 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
         continue;
       }
       Carver cv;
-      cv.base = js.ap_block;
+      cv.base = js.ap_side;
       cv.cap = js.ap_cap;
       std::vector<ApplyLevel> pl;
-      plan_apply(cv, js.lr, js.ur, tk1, tk1, (char*)jb.out->data + (size_t)js.out_off * elt, jb.dtype, tk1, 1, pl);
+      plan_apply(cv, js.lr[k & 1], js.urb[k & 1], tk1, tk1, (char*)jb.out->data + (size_t)js.out_off * elt, jb.dtype,
+                 tk1, 1, pl);
       if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "apply scratch");
       plans.push_back(std::move(pl));
       js.out_off += sz;
     }
-    rs = launch_apply_plans(c, plans, dtype);
-    if (rs != TT_OK) return rs;
+    // on the side stream: the next step only needs W (already final), not this core
+    if (!plans.empty()) {
+      hipStream_t side = side_stream(c);
+      hipEvent_t ready = dep_event(c), done = dep_event(c);
+      if (!side || !ready || !done) return fail(c, TT_EDEVICE, "side stream");
+      if ((e = hipEventRecord(ready, s)) != hipSuccess) return hip_fail(c, e, "event");
+      if ((e = hipStreamWaitEvent(side, ready, 0)) != hipSuccess) return hip_fail(c, e, "event");
+      c->upload_stream = side;
+      rs = launch_apply_plans(c, plans, dtype, side);
+      c->upload_stream = nullptr;
+      if (rs != TT_OK) return rs;
+      if ((e = hipEventRecord(done, side)) != hipSuccess) return hip_fail(c, e, "event");
+      out_done[k] = done;
+      last_side = done;
+    }
   }
+  // the output cores written on the side stream are complete before anything reads them
+  if (last_side && (e = hipStreamWaitEvent(s, last_side, 0)) != hipSuccess) return hip_fail(c, e, "event");
   // ---------------- last core
   {
     std::vector<std::vector<ApplyLevel>> plans;
