@@ -88,10 +88,8 @@ def run_config(tt, torch, dtype, delta, steps, warmup, profile):
     x = [(a, tt.TT.from_cores(c, device="cuda", dtype=dtype)) for a, c in terms]
     ctx = tt._ctx()
     ctx.lib.tt_ctx_set_profiling.argtypes = [C.c_void_p, C.c_int]
-    tt.set_autotune(True)   # the first (warm-up) call times candidate TSQR tree shapes once
-    for _ in range(max(warmup, 1)):
+    for _ in range(warmup):
         out = tt.round(x, delta)
-        tt.set_autotune(False)
     torch.cuda.synchronize()
     if profile:
         ctx.lib.tt_ctx_set_profiling(ctx.h, 1)
@@ -224,8 +222,6 @@ def main():
             "value": round(res64b["rate"], 3), "ms_per_step": round(res64b["ms"], 4),
             "rel_err": res64b["rel_err"], "out_ranks": res64b["ranks"]},
         "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in prof.items()},
-        "tsqr_tree_shapes": {"6400x200": tt.tune_tsqr(6400, 200, torch.float32),
-                             "640x200": tt.tune_tsqr(640, 200, torch.float32)},
         "roofline": roof,
     }
     if not args.headline_only:

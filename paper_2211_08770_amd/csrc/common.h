@@ -15,7 +15,7 @@ namespace tto {
 // ---------------------------------------------------------------------------
 constexpr int QR_NB = 16;          // panel width
 constexpr int QR_THREADS = 1024;   // 16 waves per tile
-constexpr int QR_MAXROWS = 768;    // LDS panel: QR_MAXROWS x QR_NB doubles = 96 KiB
+constexpr int QR_MAXROWS = 800;    // LDS panel: QR_MAXROWS x QR_NB doubles = 100 KiB (fan-in 4 at 200 columns)
 
 struct QrTask {
   const void* src;        // leaf: element (r, c) at src[r * src_rs + c * src_cs]

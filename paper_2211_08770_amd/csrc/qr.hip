@@ -36,9 +36,10 @@ constexpr int NT = QR_THREADS;  // 1024 = 16 waves
 constexpr int NWV = NT / 64;
 static_assert(NWV >= QR_NB, "the panel factorisation gives every panel column its own wave");
 constexpr int MAXR = QR_MAXROWS;
+constexpr int XSTRIDE = ((MAXR + 63) / 64) * 64;   // a published column: every row slot of every lane
 // LDS scratch after the panel: two column buffers during the panel
 // factorisation, partial V^T A of row-split tiles during the update.
-constexpr int SCR_DOUBLES = (2 * MAXR > NWV * NB * NB) ? 2 * MAXR : NWV * NB * NB;
+constexpr int SCR_DOUBLES = (2 * XSTRIDE > NWV * NB * NB) ? 2 * XSTRIDE : NWV * NB * NB;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
     for (int jj = 0; jj < nb; ++jj) {
       if (mine && wave >= jj) {
         // column jj below its diagonal (zero elsewhere) and its reflector
-        const double* xs = scr + (jj & 1) * MAXR;
+        const double* xs = scr + (jj & 1) * XSTRIDE;
         const double* pp = prm + (jj & 1) * 4;
         // all loads first (no wait between them), then the products
         double x[RT];
@@ -421,9 +422,9 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
         for (int t = 0; t < RT; ++t) x[t] = (t < rt) ? xs[lane + 64 * t] : 0.0;
         double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-        for (int t = 0; t < RT; t += 2) {
-          d0 += x[t] * y[t];
-          d1 += x[t + 1] * y[t + 1];
+        for (int t = 0; t < RT; ++t) {
+          if (t & 1) d1 += x[t] * y[t];
+          else d0 += x[t] * y[t];
         }
         const double tau = pp[0], scal = pp[1];
         if (wave > jj) {
@@ -436,7 +437,7 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
             for (int t = 0; t < RT; ++t) y[t] -= f * x[t];
             if (lane == jj) y[0] -= tw;
           }
-          if (wave == jj + 1) publish(y, jj + 1, rows, rt, scr + ((jj + 1) & 1) * MAXR, prm + ((jj + 1) & 1) * 4);
+          if (wave == jj + 1) publish(y, jj + 1, rows, rt, scr + ((jj + 1) & 1) * XSTRIDE, prm + ((jj + 1) & 1) * 4);
         } else if (wave == jj) {
           // the own column becomes beta on the diagonal and the reflector below
           // (rounded to the tile precision: the MFMA updates use that V)
