@@ -485,51 +485,143 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   }
 }
 
-// out = Q [X; 0] for one factored tile; Q = Q_0 Q_1 ... (panels applied last to first)
+// out = Q [X; 0] for one factored tile; Q = Q_0 Q_1 ... (panels applied last to first).
+// Workgroup (task, y) owns the 16 output columns [16y, 16y + 16): its slice of
+// W = [X; 0] stays in registers through every panel (row block b of 16 rows
+// belongs to wave b mod 16; lane l holds rows 4s + l/16 of the block, column
+// l%16, in the B-operand layout of K-step s), so the only memory traffic per
+// panel is the panel's V, staged in LDS by tile row with zeros on the rows the
+// panel does not touch.  Per panel: W_p = V^T W (per-wave MFMA partials summed
+// in LDS in wave order), Y = T W_p, W -= V Y.
 template <typename TT, typename TO>
 __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ tasks, int ldv) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int rowl[MAXR];
   __shared__ int bstart[MAXR + 1];
   __shared__ double Tm[NB * NB];
+  __shared__ double wsum[NB * NB];
+  typedef Mma<TT> M;
   const ApplyTask tk = tasks[blockIdx.x];
-  const int m = tk.m, N = tk.ncol, t = tk.t, tid = threadIdx.x;
+  const int m = tk.m, N = tk.ncol, t = tk.t, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int cb = blockIdx.y * NB;
+  if (cb >= t) return;   // the whole workgroup: no barrier is reached
+  const int col = cb + (lane & 15);
+  const bool colok = col < t;
   const TT* tile = (const TT*)tk.tile;
-  double* W = tk.work;
-  const int64_t total = (int64_t)m * t;
-  for (int64_t idx = tid; idx < total; idx += NT) {
-    const int r = (int)(idx / t), c = (int)(idx - (int64_t)r * t);
-    W[idx] = (r < tk.k_in) ? tk.x[r * tk.x_ld + c] : 0.0;
-  }
-  __syncthreads();
-  TT* V = (TT*)smem;
-  double* scr = (double*)(smem + panel_bytes((int)sizeof(TT), ldv));
+  TT* V = (TT*)smem;   // [NB][ldv], ldv > m: row index = tile row
+  double* wpart = (double*)(smem + panel_bytes((int)sizeof(TT), ldv));
+  constexpr int RB = (MAXR / NB + NWV - 1) / NWV;
+  const int nrb = (m + NB - 1) / NB;
+  double Wr[RB][4];
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int row = (wave + NWV * b) * NB + 4 * s + (lane >> 4);
+      Wr[b][s] = (colok && row < tk.k_in) ? tk.x[(int64_t)row * tk.x_ld + col] : 0.0;
+    }
   const int np = (tk.kq + NB - 1) / NB;
   for (int pi = np - 1; pi >= 0; --pi) {
     const int p0 = pi * NB;
     const int nb = (tk.kq - p0) < NB ? (tk.kq - p0) : NB;
-    const int rows = panel_rows(rowl, bstart, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
-    for (int idx = tid; idx < rows * NB; idx += NT) {
-      const int r = idx / NB, jj = idx - r * NB;
-      TT v = (TT)0;
-      if (jj < nb) {
-        if (r == jj) v = (TT)1;
-        else if (r > jj) v = tile[(int64_t)rowl[r] * N + p0 + jj];
+    // node: first compacted row index of each child block's active rows
+    if (tk.nchild > 0 && tid == 0) {
+      int c = 0;
+      for (int b = 0; b < tk.nchild; ++b) {
+        const int off = b * tk.kc0;
+        const int kcb = (b == tk.nchild - 1) ? tk.kc_last : tk.kc0;
+        const int lo = (p0 - off) > 0 ? (p0 - off) : 0;
+        const int hi = kcb < (p0 + nb) ? kcb : (p0 + nb);
+        bstart[b] = c;
+        c += (hi > lo) ? (hi - lo) : 0;
       }
-      V[jj * ldv + r] = v;
     }
+    __syncthreads();   // also: every wave is done with the previous panel's V, T and partials
     if (tid < NB * NB) Tm[tid] = ((const double*)tk.tmat)[(size_t)pi * NB * NB + tid];
+    // V by tile row: compacted index r of an active row (reflector jj has its unit
+    // entry at r == jj and its stored entries at r > jj), zero elsewhere
+    for (int idx = tid; idx < m * NB; idx += NT) {
+      const int row = idx / NB, jj = idx - row * NB;
+      int r = -1;
+      if (tk.nchild == 0) {
+        r = row - p0;
+      } else {
+        int b = row / tk.kc0;
+        if (b > tk.nchild - 1) b = tk.nchild - 1;
+        const int off = b * tk.kc0;
+        const int kcb = (b == tk.nchild - 1) ? tk.kc_last : tk.kc0;
+        const int i = row - off;
+        const int lo = (p0 - off) > 0 ? (p0 - off) : 0;
+        const int hi = kcb < (p0 + nb) ? kcb : (p0 + nb);
+        if (i >= lo && i < hi) r = bstart[b] + (i - lo);
+      }
+      TT v = (TT)0;
+      if (jj < nb && r >= jj) v = (r == jj) ? (TT)1 : tile[(int64_t)row * N + p0 + jj];
+      V[jj * ldv + row] = v;
+    }
     __syncthreads();
-    block_update<false, double, TT>(W, t, rowl, 0, t, rows, V, ldv, Tm, scr);
+    // W_p partial over this wave's row blocks
+    typename M::acc_t w = M::zero();
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int rb = wave + NWV * b;
+      if (rb < nrb) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int row = rb * NB + 4 * s + (lane >> 4);
+          const TT a = row < m ? V[(lane & 15) * ldv + row] : (TT)0;
+          w = M::mma(a, (TT)Wr[b][s], w);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) wpart[wave * 256 + v * 64 + lane] = (double)w[v];
     __syncthreads();
-  }
-  if (tk.to_out) {
-    TO* out = (TO*)tk.out;
-    for (int64_t idx = tid; idx < total; idx += NT) {
-      const int r = (int)(idx / t), c = (int)(idx - (int64_t)r * t);
-      out[r * tk.out_rs + c * tk.out_cs] = (TO)W[idx];
+    // W_p: thread e < 256 sums element e of the partials in wave order
+    if (tid < 256) {
+      double a = 0.0;
+      for (int p = 0; p < NWV; ++p) a += wpart[p * 256 + tid];
+      wsum[tid] = a;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) w[v] = (TT)wsum[v * 64 + lane];
+    // Y = T W_p
+    typename M::acc_t y = M::zero();
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = lane & 15, k = 4 * s + (lane >> 4);
+      y = M::mma((TT)Tm[i * NB + k], bop(w, s), y);
+    }
+    TT yb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) yb[s] = bop(y, s);
+    // W -= V Y on this wave's row blocks
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const int rb = wave + NWV * b;
+      if (rb < nrb) {
+        const int ra = rb * NB + (lane & 15);
+        typename M::acc_t d = M::zero();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const TT a = ra < m ? V[(4 * s + (lane >> 4)) * ldv + ra] : (TT)0;
+          d = M::mma(a, yb[s], d);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) Wr[b][s] -= (double)bop(d, s);
+      }
     }
   }
+#pragma unroll
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int row = (wave + NWV * b) * NB + 4 * s + (lane >> 4);
+      if (colok && row < m) {
+        if (tk.to_out) ((TO*)tk.out)[row * tk.out_rs + col * tk.out_cs] = (TO)Wr[b][s];
+        else tk.work[(int64_t)row * t + col] = Wr[b][s];
+      }
+    }
 }
 
 size_t panel_smem(int elt, int ldv) { return panel_bytes(elt, ldv) + (size_t)SCR_DOUBLES * 8; }
@@ -560,10 +652,11 @@ hipError_t launch_qr_factor(int dtype_src, int dtype_tile, const QrTask* d_tasks
 }
 
 hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tasks, int ntasks, int max_rows,
-                           hipStream_t s) {
-  if (ntasks <= 0) return hipSuccess;
+                           int max_t, hipStream_t s) {
+  if (ntasks <= 0 || max_t <= 0) return hipSuccess;
+  if (max_rows > MAXR) return hipErrorInvalidValue;
   const int ldv = max_rows + 1;
-  dim3 grid(ntasks), block(NT);
+  dim3 grid(ntasks, (max_t + NB - 1) / NB), block(NT);
   if (dtype_tile == 0) {
     const size_t sm = panel_smem(8, ldv);
     if (dtype_out == 0) hipLaunchKernelGGL((k_qr_apply<double, double>), grid, block, sm, s, d_tasks, ldv);

@@ -499,9 +499,12 @@ tt_status launch_apply_plans(tt_ctx* c, std::vector<std::vector<ApplyLevel>>& pl
           by += (double)a.m * a.ncol * (tdt == 0 ? 8.0 : 4.0) + 2.0 * (double)a.m * a.t * 8.0;
         }
       const int pr = prof_begin(c, PK_QR_APPLY, fl, by, stream);
-      int max_rows = 1;
-      for (const ApplyTask& a : tasks) max_rows = std::max(max_rows, (int)a.m);
-      hipError_t e = launch_qr_apply(tdt, out_dtype, dt, (int)tasks.size(), max_rows, stream);
+      int max_rows = 1, max_t = 0;
+      for (const ApplyTask& a : tasks) {
+        max_rows = std::max(max_rows, (int)a.m);
+        max_t = std::max(max_t, (int)a.t);
+      }
+      hipError_t e = launch_qr_apply(tdt, out_dtype, dt, (int)tasks.size(), max_rows, max_t, stream);
       prof_end(c, pr, stream);
       if (e != hipSuccess) return hip_fail(c, e, "qr_apply");
     }

@@ -30,7 +30,10 @@ namespace {
 constexpr int NT = 1024;
 constexpr int NW = NT / 64;
 constexpr int MAXC = 1024;
-constexpr int LDS_DOUBLES = 18000;   // 140.6 KiB for A and J (plus ~16 KiB static)
+constexpr int LDS_DOUBLES = 18000;
+#ifndef JGL
+#define JGL 16
+#endif   // 140.6 KiB for A and J (plus ~16 KiB static)
 
 __device__ inline double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -63,19 +66,77 @@ __device__ inline void rr_pair(int round, int pair, int kp, int& p, int& q) {
 
 extern __shared__ __align__(16) double svd_lds[];
 
-// One-sided Jacobi on A (len x k, column-major, lda = len); when J is
-// requested the rotations are accumulated into J (k x k, column-major).
+// Sum over each GL-lane group of a wave (GL = 8 or 16; every lane gets its group's sum).
+template <int GL>
+__device__ inline double group_sum(double v) {
+  v += dpp_d<0xB1>(v);    // quad_perm(1,0,3,2)
+  v += dpp_d<0x4E>(v);    // quad_perm(2,3,0,1)
+  if (GL == 8) {
+    v += dpp_d<0x141>(v);   // row_half_mirror: the other quad of the 8-lane half
+  } else {
+    v += dpp_d<0x124>(v);   // row_ror:4
+    v += dpp_d<0x128>(v);   // row_ror:8
+  }
+  return v;
+}
+
+// One Newton step towards 1/x from r, and towards 1/sqrt(x) from y (each
+// step doubles the number of correct bits of the hardware estimate).
+__device__ inline double rcp_step(double x, double r) {
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ inline double rsq_step(double x, double y) {
+  return fma(0.5 * y, fma(-x * y, y, 1.0), y);
+}
+
+// Rotation (c, s) that makes columns p and q orthogonal, from their squared
+// norms al, be and their dot product ga != 0: t = tan(theta) is the root of
+// smaller magnitude of t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga),
+// written as t = sign(be - al) 2ga / (|be - al| + sqrt((be - al)^2 + 4ga^2))
+// so that it takes one square root and one reciprocal (hardware estimates
+// refined by two Newton steps); c = 1/sqrt(1 + t^2), s = c t.  Outside the
+// range where the squares are safe, the quotient form is used.
+__device__ inline void rotation(double al, double be, double ga, double& c, double& s) {
+  const double d = be - al, g = 2.0 * ga;
+  const double m = fmax(fabs(d), fabs(g));
+  double t;
+  if (m > 1e-150 && m < 1e150) {
+    const double w = fma(d, d, g * g);
+    double y = __builtin_amdgcn_rsq(w);
+    y = rsq_step(w, rsq_step(w, y));
+    const double den = fma(w, y, fabs(d));
+    double r = __builtin_amdgcn_rcp(den);
+    r = rcp_step(den, rcp_step(den, r));
+    t = (d >= 0.0 ? g : -g) * r;
+  } else {
+    const double zeta = d / g;
+    if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+    else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  }
+  const double u = fma(t, t, 1.0);
+  double cc = __builtin_amdgcn_rsq(u);
+  cc = rsq_step(u, rsq_step(u, cc));
+  c = cc;
+  s = cc * t;
+}
+
+// One-sided Jacobi on A (len x k, column-major, leading dimension lda >= len,
+// rows len..lda-1 zero); when J is requested the rotations are accumulated
+// into J (k x k, column-major).
 // SH: A (and J right after it) live in the dynamic LDS block, so the
 // accesses compile to LDS instructions; otherwise Ag / Jg in global memory.
+// A group of GL lanes handles one pair; EPL > 0 (lda == GL * EPL) keeps the
+// pair's two columns in registers between the dot products and the rotation.
 // Returns the number of sweeps used.
-template <bool SH>
-__device__ __attribute__((always_inline)) int jacobi(double* Ag, double* Jg, bool with_j, int len, int k,
-                                                     int* rots) {
+template <bool SH, int GL, int EPL>
+__device__ __attribute__((always_inline)) int jacobi(double* Ag, double* Jg, bool with_j, int len, int lda,
+                                                     int k, int* rots) {
   double* A = SH ? svd_lds : Ag;
-  double* J = with_j ? (SH ? svd_lds + (int64_t)len * k : Jg) : nullptr;
-  // a 16-lane row of a wave handles one pair: reductions stay inside the row
-  const int tid = threadIdx.x, gl = tid & 15, grp = tid >> 4;
-  constexpr int NG = NT / 16;
+  double* J = with_j ? (SH ? svd_lds + (int64_t)lda * k : Jg) : nullptr;
+  // a GL-lane group of a wave handles one pair: reductions stay inside the group
+  const int tid = threadIdx.x, gl = tid % GL, grp = tid / GL;
+  constexpr int NG = NT / GL;
+  constexpr int NE = EPL > 0 ? EPL : 1;
   const int kp = k + (k & 1);
   const double tol = (double)len * 1.1102230246251565e-16;
   const double tol2 = tol * tol;
@@ -84,44 +145,64 @@ __device__ __attribute__((always_inline)) int jacobi(double* Ag, double* Jg, boo
     if (tid == 0) *rots = 0;
     __syncthreads();
     for (int round = 0; round < kp - 1; ++round) {
-      for (int pb = 0; pb < kp / 2; pb += NG) {   // uniform trip count: every row takes part in the sums
+      for (int pb = 0; pb < kp / 2; pb += NG) {   // uniform trip count: every group takes part in the sums
         const int pair = pb + grp;
         int p = 0, q = 0;
         if (pair < kp / 2) rr_pair(round, pair, kp, p, q);
         const bool live = pair < kp / 2 && q < k;
-        double* ap = A + (int64_t)p * len;
-        double* aq = A + (int64_t)q * len;
+        if (!live) p = q = 0;
+        double* ap = A + (int64_t)p * lda;
+        double* aq = A + (int64_t)q * lda;
         double al = 0.0, be = 0.0, ga = 0.0;
-        if (live) {
-          for (int i = gl; i < len; i += 16) {
-            const double x = ap[i], y = aq[i];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
+        double x[NE], y[NE];
+        if (EPL > 0) {
+          // every group loads (idle groups read column 0 and drop the result)
+#pragma unroll
+          for (int t = 0; t < NE; ++t) {
+            x[t] = ap[gl + GL * t];
+            y[t] = aq[gl + GL * t];
+          }
+#pragma unroll
+          for (int t = 0; t < NE; ++t) {
+            al += x[t] * x[t];
+            be += y[t] * y[t];
+            ga += x[t] * y[t];
+          }
+        } else if (live) {
+          for (int i = gl; i < len; i += GL) {
+            const double u = ap[i], v = aq[i];
+            al += u * u;
+            be += v * v;
+            ga += u * v;
           }
         }
-        al = row16_sum(al);
-        be = row16_sum(be);
-        ga = row16_sum(ga);
+        al = group_sum<GL>(al);
+        be = group_sum<GL>(be);
+        ga = group_sum<GL>(ga);
         // rotate unless the pair is orthogonal to relative precision tol
         if (live && ga != 0.0 && ga * ga > tol2 * al * be) {
-          const double zeta = (be - al) / (2.0 * ga);
-          double t;
-          if (fabs(zeta) > 1e150) t = 0.5 / zeta;
-          else t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-          for (int i = gl; i < len; i += 16) {
-            const double x = ap[i], y = aq[i];
-            ap[i] = c * x - s * y;
-            aq[i] = s * x + c * y;
+          double c, s;
+          rotation(al, be, ga, c, s);
+          if (EPL > 0) {
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+              ap[gl + GL * e] = c * x[e] - s * y[e];
+              aq[gl + GL * e] = s * x[e] + c * y[e];
+            }
+          } else {
+            for (int i = gl; i < len; i += GL) {
+              const double u = ap[i], v = aq[i];
+              ap[i] = c * u - s * v;
+              aq[i] = s * u + c * v;
+            }
           }
           if (J) {
             double* jp = J + (int64_t)p * k;
             double* jq = J + (int64_t)q * k;
-            for (int i = gl; i < k; i += 16) {
-              const double x = jp[i], y = jq[i];
-              jp[i] = c * x - s * y;
-              jq[i] = s * x + c * y;
+            for (int i = gl; i < k; i += GL) {
+              const double u = jp[i], v = jq[i];
+              jp[i] = c * u - s * v;
+              jq[i] = s * u + c * v;
             }
           }
           if (gl == 0) *rots = 1;
@@ -203,16 +284,26 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   __syncthreads();
   const int k = kact, len = lenact > 0 ? lenact : 1;
 
-  // ---- A_active (len x k) and, for a wide R, J (k x k): LDS when they fit, else global scratch
+  // ---- A_active (len x k, leading dimension lda, zero rows below len) and,
+  // for a wide R, J (k x k): LDS when they fit, else global scratch.  In LDS
+  // the columns are padded to a register-tile length when that fits.
   const int64_t jsz = tall ? 0 : (int64_t)k * k;
-  const bool in_lds = (int64_t)len * k + jsz <= LDS_DOUBLES;
+  const int epl = len <= 4 * JGL ? 4 : len <= 8 * JGL ? 8 : len <= 16 * JGL ? 16 : 0;
+  int mode = -1, lda = len;   // -1: global scratch; 0: LDS, plain loops; > 0: LDS, registers
+  if (epl > 0 && (int64_t)epl * JGL * k + jsz <= LDS_DOUBLES) {
+    mode = epl;
+    lda = epl * JGL;
+  } else if ((int64_t)len * k + jsz <= LDS_DOUBLES) {
+    mode = 0;
+  }
+  const bool in_lds = mode >= 0;
   double* A = in_lds ? svd_lds : tk.A;
-  double* J = tall ? nullptr : (in_lds ? svd_lds + (int64_t)len * k : tk.acc);
+  double* J = tall ? nullptr : (in_lds ? svd_lds + (int64_t)lda * k : tk.acc);
   // (the Jacobi sweeps are called with the LDS or the global pointer written
   // out, so that each copy uses LDS or global instructions, not flat ones)
-  for (int64_t idx = tid; idx < (int64_t)k * len; idx += NT) {
-    const int a = (int)(idx / len), i = (int)(idx - (int64_t)a * len);
-    A[idx] = aval(i, act[a]);
+  for (int64_t idx = tid; idx < (int64_t)k * lda; idx += NT) {
+    const int a = (int)(idx / lda), i = (int)(idx - (int64_t)a * lda);
+    A[idx] = i < len ? aval(i, act[a]) : 0.0;
   }
   for (int64_t idx = tid; idx < jsz; idx += NT) {
     const int j = (int)(idx / k), i = (int)(idx - (int64_t)j * k);
@@ -221,13 +312,16 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   __syncthreads();
   int sweeps = 0;
   if (k > 0) {
-    if (in_lds) sweeps = jacobi<true>(nullptr, nullptr, !tall, len, k, &rots);
-    else sweeps = jacobi<false>(tk.A, tk.acc, !tall, len, k, &rots);
+    if (mode < 0) sweeps = jacobi<false, JGL, 0>(tk.A, tk.acc, !tall, len, lda, k, &rots);
+    else if (mode == 4) sweeps = jacobi<true, JGL, 4>(nullptr, nullptr, !tall, len, lda, k, &rots);
+    else if (mode == 8) sweeps = jacobi<true, JGL, 8>(nullptr, nullptr, !tall, len, lda, k, &rots);
+    else if (mode == 16) sweeps = jacobi<true, JGL, 16>(nullptr, nullptr, !tall, len, lda, k, &rots);
+    else sweeps = jacobi<true, JGL, 0>(nullptr, nullptr, !tall, len, lda, k, &rots);
   }
 
   // ---- singular values, order, rank
   for (int j = wave; j < k; j += NW) {
-    const double* aj = A + (int64_t)j * len;
+    const double* aj = A + (int64_t)j * lda;
     double s = 0.0;
     for (int i = lane; i < len; i += 64) s += aj[i] * aj[i];
     s = wave_sum(s);
@@ -281,14 +375,14 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
         // row i of W = Sigma_t V_t^T = U_t^T R, with U_t = (final column)/sigma
         const double s = tk.sigma[i];
         if (s > 0.0) {
-          const double* aj = A + (int64_t)j * len;
+          const double* aj = A + (int64_t)j * lda;
           const int rmax = (tk.upper && col + 1 < len) ? col + 1 : len;   // R(row, col) = 0 below the diagonal
           double acc = 0.0;
           for (int row = 0; row < rmax; ++row) acc += aj[row] * aval(row, col);
           v = acc / s;
         }
       } else {
-        v = (col < len) ? A[(int64_t)j * len + col] : 0.0;
+        v = (col < len) ? A[(int64_t)j * lda + col] : 0.0;
       }
     }
     tk.wt[idx] = v;
@@ -303,7 +397,7 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
       const int j = perm[i];
       if (tall) {
         const double s = tk.sigma[i];
-        if (s > 0.0) v = (row < len) ? A[(int64_t)j * len + row] / s : 0.0;
+        if (s > 0.0) v = (row < len) ? A[(int64_t)j * lda + row] / s : 0.0;
         else v = (row == i) ? 1.0 : 0.0;
       } else {
         const int a = (int)nrm2[row];
