@@ -111,30 +111,45 @@ __device__ inline float bop(const v4f& d, int s) {                 // f32: lane 
 // 16-column tile at column `col`; four accumulators keep four MFMAs in flight.
 template <typename TA, typename TV>
 __device__ __attribute__((always_inline)) typename Mma<TV>::acc_t wpartial(
-    const TA* __restrict__ A, int64_t lda, const int* __restrict__ rowl, int col, bool colok, int rlo, int rhi,
+    gptr<const TA> __restrict__ A, int64_t lda, const int* __restrict__ rowl, int col, bool colok, int rlo, int rhi,
     const TV* __restrict__ V, int ldv) {
   typedef Mma<TV> M;
   const int lane = threadIdx.x & 63;
   typename M::acc_t w0 = M::zero(), w1 = M::zero(), w2 = M::zero(), w3 = M::zero();
   constexpr int U = 12;   // K-steps whose global loads are issued together
+  // every load is issued unconditionally from a valid address (rows past rhi and
+  // columns past the tile read row rlo / column 0) and masked afterwards, so the
+  // row-list reads and then the global loads go out back to back
+  const int colc = colok ? col : 0;
   for (int r0 = rlo; r0 < rhi; r0 += 4 * U) {
+    int ri[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = r0 + 4 * u + (lane >> 4);
+      ri[u] = rowl[r < rhi ? r : rlo];
+    }
+    TA g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) g[u] = A[(int64_t)ri[u] * lda + colc];
     TV b[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int r = r0 + 4 * u + (lane >> 4);
-      b[u] = (r < rhi && colok) ? (TV)A[(int64_t)rowl[r] * lda + col] : (TV)0;
+      b[u] = (r < rhi && colok) ? (TV)g[u] : (TV)0;
     }
 #pragma unroll
     for (int u = 0; u < U; u += 4) {
-      const int r = r0 + 4 * u + (lane >> 4);
-      const TV a0 = (r < rhi) ? V[(lane & 15) * ldv + r] : (TV)0;
-      const TV a1 = (r + 4 < rhi) ? V[(lane & 15) * ldv + r + 4] : (TV)0;
-      const TV a2 = (r + 8 < rhi) ? V[(lane & 15) * ldv + r + 8] : (TV)0;
-      const TV a3 = (r + 12 < rhi) ? V[(lane & 15) * ldv + r + 12] : (TV)0;
-      w0 = M::mma(a0, b[u], w0);
-      w1 = M::mma(a1, b[u + 1], w1);
-      w2 = M::mma(a2, b[u + 2], w2);
-      w3 = M::mma(a3, b[u + 3], w3);
+      TV a[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = r0 + 4 * u + (lane >> 4) + 4 * k;
+        const TV vv = V[(lane & 15) * ldv + (r < rhi ? r : rlo)];
+        a[k] = (r < rhi) ? vv : (TV)0;
+      }
+      w0 = M::mma(a[0], b[u], w0);
+      w1 = M::mma(a[1], b[u + 1], w1);
+      w2 = M::mma(a[2], b[u + 2], w2);
+      w3 = M::mma(a[3], b[u + 3], w3);
     }
   }
   return (w0 + w1) + (w2 + w3);
@@ -143,38 +158,43 @@ __device__ __attribute__((always_inline)) typename Mma<TV>::acc_t wpartial(
 // A -= V Y on the rows [rlo, rhi) (rlo a multiple of 16) of the tile's column;
 // yb holds Y in B-operand layout.  The A values of UB row blocks are loaded together.
 template <typename TA, typename TV>
-__device__ __attribute__((always_inline)) void update_rows(TA* __restrict__ A, int64_t lda,
+__device__ __attribute__((always_inline)) void update_rows(gptr<TA> __restrict__ A, int64_t lda,
                                                            const int* __restrict__ rowl, int col, bool colok, int rlo,
                                                            int rhi, const TV* __restrict__ V, int ldv,
                                                            const TV (&yb)[4]) {
   typedef Mma<TV> M;
   const int lane = threadIdx.x & 63;
   constexpr int UB = 2;
+  const int colc = colok ? col : 0;
   for (int rb0 = rlo; rb0 < rhi; rb0 += NB * UB) {
-    double old[UB][4];
+    // row-list reads, then the loads of the old values (valid addresses, masked later)
     int idx[UB][4];   // tile element offsets (a tile holds < 2^31 elements)
 #pragma unroll
-    for (int ub = 0; ub < UB; ++ub) {
+    for (int ub = 0; ub < UB; ++ub)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = rb0 + NB * ub + M::row(lane, v);
-        const bool ok = colok && r < rhi;
-        idx[ub][v] = ok ? (int)((int64_t)rowl[r] * lda + col) : -1;
-        old[ub][v] = ok ? (double)A[idx[ub][v]] : 0.0;
+        idx[ub][v] = (int)((int64_t)rowl[r < rhi ? r : rlo] * lda + colc);
       }
-    }
+    TA old[UB][4];
+#pragma unroll
+    for (int ub = 0; ub < UB; ++ub)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) old[ub][v] = A[idx[ub][v]];
 #pragma unroll
     for (int ub = 0; ub < UB; ++ub) {
       const int ra = rb0 + NB * ub + (lane & 15);
       typename M::acc_t d = M::zero();
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const TV a = (ra < rhi) ? V[(4 * s + (lane >> 4)) * ldv + ra] : (TV)0;
-        d = M::mma(a, yb[s], d);
+        const TV vv = V[(4 * s + (lane >> 4)) * ldv + (ra < rhi ? ra : rlo)];
+        d = M::mma((ra < rhi) ? vv : (TV)0, yb[s], d);
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        if (idx[ub][v] >= 0) A[idx[ub][v]] = (TA)(old[ub][v] - (double)d[v]);
+      for (int v = 0; v < 4; ++v) {
+        const int r = rb0 + NB * ub + M::row(lane, v);
+        if (colok && r < rhi) A[idx[ub][v]] = (TA)((double)old[ub][v] - (double)d[v]);
+      }
     }
   }
 }
@@ -186,7 +206,7 @@ __device__ __attribute__((always_inline)) void update_rows(TA* __restrict__ A, i
 // Tm: LDS NB x NB row-major upper-triangular T (zero beyond the panel width);
 // wpart: LDS scratch of NWV x 256 doubles.  Called by the whole workgroup.
 template <bool FORWARD, typename TA, typename TV>
-__device__ __attribute__((always_inline)) void block_update(TA* __restrict__ A, int64_t lda, const int* __restrict__ rowl, int c0, int ncol,
+__device__ __attribute__((always_inline)) void block_update(gptr<TA> __restrict__ A, int64_t lda, const int* __restrict__ rowl, int c0, int ncol,
                              int rows, const TV* __restrict__ V, int ldv, const double* __restrict__ Tm,
                              double* __restrict__ wpart) {
   typedef Mma<TV> M;
@@ -361,11 +381,11 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   __shared__ double prm[8];
   const QrTask tk = tasks[blockIdx.x];
   const int m = tk.m, N = tk.ncol, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  TT* A = (TT*)tk.tile;
+  const gptr<TT> A = glb((TT*)tk.tile);
 
   // ---- fill the tile
   if (tk.nchild == 0) {
-    const TS* src = (const TS*)tk.src;
+    const gptr<const TS> src = glb((const TS*)tk.src);
     const int64_t total = (int64_t)m * N;
     for (int64_t idx = tid; idx < total; idx += NT) {
       const int r = (int)(idx / N), c = (int)(idx - (int64_t)r * N);
@@ -375,7 +395,7 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
     int row0 = 0;
     for (int ci = 0; ci < tk.nchild; ++ci) {
       const QrTask ch = children[tk.child0 + ci];
-      const TS* ct = (const TS*)ch.tile;
+      const gptr<const TS> ct = glb((const TS*)ch.tile);
       const int kc = ch.m < N ? ch.m : N;
       const int64_t total = (int64_t)kc * N;
       for (int64_t idx = tid; idx < total; idx += NT) {
@@ -465,7 +485,7 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
       const int r = idx >> 4, jj = idx & (NB - 1);
       if (jj < nb) A[(int64_t)rowl[r] * N + p0 + jj] = P[jj * ldv + r];
     }
-    if (tid < nb) tk.tau[p0 + tid] = taus[tid];
+    if (tid < nb) glb(tk.tau)[p0 + tid] = taus[tid];
     __syncthreads();
     // ---- explicit V (unit diagonal, zeros above; padded columns zero)
     if (tid < NB * NB) {
@@ -477,7 +497,7 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
     gram_v<TT>(P, ldv, rows, nb, scr, S);
     form_t(S, taus, Tm);
     __syncthreads();
-    if (tid < NB * NB) ((double*)tk.tmat)[(size_t)pi * NB * NB + tid] = Tm[tid];
+    if (tid < NB * NB) glb((double*)tk.tmat)[(size_t)pi * NB * NB + tid] = Tm[tid];
     // ---- trailing update  A <- Q_p^T A  on the panel's rows
     const int c0 = p0 + nb;
     if (c0 < N) block_update<true, TT, TT>(A, N, rowl, c0, N, rows, P, ldv, Tm, scr);
@@ -506,7 +526,8 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
   if (cb >= t) return;   // the whole workgroup: no barrier is reached
   const int col = cb + (lane & 15);
   const bool colok = col < t;
-  const TT* tile = (const TT*)tk.tile;
+  const gptr<const TT> tile = glb((const TT*)tk.tile);
+  const gptr<const double> X = glb(tk.x);
   TT* V = (TT*)smem;   // [NB][ldv], ldv > m: row index = tile row
   double* wpart = (double*)(smem + panel_bytes((int)sizeof(TT), ldv));
   constexpr int RB = (MAXR / NB + NWV - 1) / NWV;
@@ -517,7 +538,7 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int row = (wave + NWV * b) * NB + 4 * s + (lane >> 4);
-      Wr[b][s] = (colok && row < tk.k_in) ? tk.x[(int64_t)row * tk.x_ld + col] : 0.0;
+      Wr[b][s] = (colok && row < tk.k_in) ? X[(int64_t)row * tk.x_ld + col] : 0.0;
     }
   const int np = (tk.kq + NB - 1) / NB;
   for (int pi = np - 1; pi >= 0; --pi) {
@@ -536,7 +557,7 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
       }
     }
     __syncthreads();   // also: every wave is done with the previous panel's V, T and partials
-    if (tid < NB * NB) Tm[tid] = ((const double*)tk.tmat)[(size_t)pi * NB * NB + tid];
+    if (tid < NB * NB) Tm[tid] = glb((const double*)tk.tmat)[(size_t)pi * NB * NB + tid];
     // V by tile row: compacted index r of an active row (reflector jj has its unit
     // entry at r == jj and its stored entries at r > jj), zero elsewhere
     for (int idx = tid; idx < m * NB; idx += NT) {
@@ -618,8 +639,8 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
     for (int s = 0; s < 4; ++s) {
       const int row = (wave + NWV * b) * NB + 4 * s + (lane >> 4);
       if (colok && row < m) {
-        if (tk.to_out) ((TO*)tk.out)[row * tk.out_rs + col * tk.out_cs] = (TO)Wr[b][s];
-        else tk.work[(int64_t)row * t + col] = Wr[b][s];
+        if (tk.to_out) glb((TO*)tk.out)[row * tk.out_rs + col * tk.out_cs] = (TO)Wr[b][s];
+        else glb(tk.work)[(int64_t)row * t + col] = Wr[b][s];
       }
     }
 }

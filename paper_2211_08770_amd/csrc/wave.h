@@ -4,6 +4,17 @@
 
 namespace tto {
 
+// Pointers into device memory that reach a kernel inside a task descriptor are
+// generic to the compiler, which then emits FLAT instructions; those count
+// against the LDS wait counter too, so every LDS wait also waits for the
+// global loads in flight.  glb() marks such a pointer as global memory.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __attribute__((always_inline)) inline gptr<T> glb(T* p) {
+  return (gptr<T>)p;
+}
+
 // DPP move of a double within 16-lane rows (GFX9 DPP controls).
 template <int CTRL>
 __device__ inline double dpp_d(double v) {
