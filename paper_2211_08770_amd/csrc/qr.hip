@@ -383,13 +383,23 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   const int m = tk.m, N = tk.ncol, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const gptr<TT> A = glb((TT*)tk.tile);
 
-  // ---- fill the tile
+  // ---- fill the tile (UF loads in flight per thread: clamped addresses, masked stores;
+  // a tile holds fewer than 2^31 elements)
+  constexpr int UF = 4;
   if (tk.nchild == 0) {
     const gptr<const TS> src = glb((const TS*)tk.src);
-    const int64_t total = (int64_t)m * N;
-    for (int64_t idx = tid; idx < total; idx += NT) {
-      const int r = (int)(idx / N), c = (int)(idx - (int64_t)r * N);
-      A[idx] = (TT)src[r * tk.src_rs + c * tk.src_cs];
+    const int total = m * N;
+    for (int base = tid; base < total; base += UF * NT) {
+      TS v[UF];
+#pragma unroll
+      for (int k = 0; k < UF; ++k) {
+        const int idx = (base + k * NT < total) ? base + k * NT : total - 1;
+        const int r = idx / N, c = idx - r * N;
+        v[k] = src[r * tk.src_rs + c * tk.src_cs];
+      }
+#pragma unroll
+      for (int k = 0; k < UF; ++k)
+        if (base + k * NT < total) A[base + k * NT] = (TT)v[k];
     }
   } else {
     int row0 = 0;
@@ -397,10 +407,19 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
       const QrTask ch = children[tk.child0 + ci];
       const gptr<const TS> ct = glb((const TS*)ch.tile);
       const int kc = ch.m < N ? ch.m : N;
-      const int64_t total = (int64_t)kc * N;
-      for (int64_t idx = tid; idx < total; idx += NT) {
-        const int r = (int)(idx / N), c = (int)(idx - (int64_t)r * N);
-        A[(int64_t)(row0 + r) * N + c] = (c >= r) ? (TT)ct[idx] : (TT)0;
+      const int total = kc * N;
+      for (int base = tid; base < total; base += UF * NT) {
+        TS v[UF];
+#pragma unroll
+        for (int k = 0; k < UF; ++k) v[k] = ct[(base + k * NT < total) ? base + k * NT : total - 1];
+#pragma unroll
+        for (int k = 0; k < UF; ++k) {
+          const int idx = base + k * NT;
+          if (idx < total) {
+            const int r = idx / N, c = idx - r * N;
+            A[(int64_t)(row0 + r) * N + c] = (c >= r) ? (TT)v[k] : (TT)0;
+          }
+        }
       }
       row0 += kc;
     }
@@ -414,9 +433,24 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   for (int p0 = 0, pi = 0; p0 < kmax; p0 += NB, ++pi) {
     const int nb = (kmax - p0) < NB ? (kmax - p0) : NB;
     const int rows = panel_rows(rowl, bstart, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
-    for (int idx = tid; idx < rows * NB; idx += NT) {
-      const int r = idx / NB, jj = idx - r * NB;
-      P[jj * ldv + r] = (jj < nb) ? A[(int64_t)rowl[r] * N + p0 + jj] : (TT)0;
+    for (int base = tid; base < rows * NB; base += UF * NT) {
+      int ri[UF];
+      TT v[UF];
+#pragma unroll
+      for (int k = 0; k < UF; ++k) ri[k] = rowl[((base + k * NT < rows * NB) ? base + k * NT : rows * NB - 1) >> 4];
+#pragma unroll
+      for (int k = 0; k < UF; ++k) {
+        const int jj = (base + k * NT) & (NB - 1);
+        v[k] = A[(int64_t)ri[k] * N + p0 + (jj < nb ? jj : nb - 1)];
+      }
+#pragma unroll
+      for (int k = 0; k < UF; ++k) {
+        const int idx = base + k * NT;
+        if (idx < rows * NB) {
+          const int r = idx >> 4, jj = idx & (NB - 1);
+          P[jj * ldv + r] = (jj < nb) ? v[k] : (TT)0;
+        }
+      }
     }
     if (tid < NB) taus[tid] = 0.0;
     __syncthreads();
@@ -560,24 +594,40 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
     if (tid < NB * NB) Tm[tid] = glb((const double*)tk.tmat)[(size_t)pi * NB * NB + tid];
     // V by tile row: compacted index r of an active row (reflector jj has its unit
     // entry at r == jj and its stored entries at r > jj), zero elsewhere
-    for (int idx = tid; idx < m * NB; idx += NT) {
-      const int row = idx / NB, jj = idx - row * NB;
-      int r = -1;
-      if (tk.nchild == 0) {
-        r = row - p0;
-      } else {
-        int b = row / tk.kc0;
-        if (b > tk.nchild - 1) b = tk.nchild - 1;
-        const int off = b * tk.kc0;
-        const int kcb = (b == tk.nchild - 1) ? tk.kc_last : tk.kc0;
-        const int i = row - off;
-        const int lo = (p0 - off) > 0 ? (p0 - off) : 0;
-        const int hi = kcb < (p0 + nb) ? kcb : (p0 + nb);
-        if (i >= lo && i < hi) r = bstart[b] + (i - lo);
+    constexpr int UF = 4;   // loads in flight per thread (clamped addresses, masked values)
+    for (int base = tid; base < m * NB; base += UF * NT) {
+      int rr[UF];
+      TT v[UF];
+#pragma unroll
+      for (int k = 0; k < UF; ++k) {
+        const int idx = (base + k * NT < m * NB) ? base + k * NT : m * NB - 1;
+        const int row = idx >> 4;
+        int r = -1;
+        if (tk.nchild == 0) {
+          r = row - p0;
+        } else {
+          int b = row / tk.kc0;
+          if (b > tk.nchild - 1) b = tk.nchild - 1;
+          const int off = b * tk.kc0;
+          const int kcb = (b == tk.nchild - 1) ? tk.kc_last : tk.kc0;
+          const int i = row - off;
+          const int lo = (p0 - off) > 0 ? (p0 - off) : 0;
+          const int hi = kcb < (p0 + nb) ? kcb : (p0 + nb);
+          if (i >= lo && i < hi) r = bstart[b] + (i - lo);
+        }
+        rr[k] = r;
+        const int jj = idx & (NB - 1);
+        v[k] = tile[(int64_t)row * N + p0 + (jj < nb ? jj : nb - 1)];
       }
-      TT v = (TT)0;
-      if (jj < nb && r >= jj) v = (r == jj) ? (TT)1 : tile[(int64_t)row * N + p0 + jj];
-      V[jj * ldv + row] = v;
+#pragma unroll
+      for (int k = 0; k < UF; ++k) {
+        const int idx = base + k * NT;
+        if (idx < m * NB) {
+          const int row = idx >> 4, jj = idx & (NB - 1);
+          const int r = rr[k];
+          V[jj * ldv + row] = (jj < nb && r >= jj) ? ((r == jj) ? (TT)1 : v[k]) : (TT)0;
+        }
+      }
     }
     __syncthreads();
     // W_p partial over this wave's row blocks
