@@ -389,17 +389,26 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   if (tk.nchild == 0) {
     const gptr<const TS> src = glb((const TS*)tk.src);
     const int total = m * N;
+    // walk the source along its unit stride (rows of a transposed source)
+    const bool by_col = tk.src_rs == 1 && tk.src_cs != 1;
+    const int inner = by_col ? m : N;
     for (int base = tid; base < total; base += UF * NT) {
       TS v[UF];
 #pragma unroll
       for (int k = 0; k < UF; ++k) {
         const int idx = (base + k * NT < total) ? base + k * NT : total - 1;
-        const int r = idx / N, c = idx - r * N;
+        const int o = idx / inner, i = idx - o * inner;
+        const int r = by_col ? i : o, c = by_col ? o : i;
         v[k] = src[r * tk.src_rs + c * tk.src_cs];
       }
 #pragma unroll
-      for (int k = 0; k < UF; ++k)
-        if (base + k * NT < total) A[base + k * NT] = (TT)v[k];
+      for (int k = 0; k < UF; ++k) {
+        const int idx = base + k * NT;
+        if (idx < total) {
+          const int o = idx / inner, i = idx - o * inner;
+          A[by_col ? i * N + o : idx] = (TT)v[k];
+        }
+      }
     }
   } else {
     int row0 = 0;
