@@ -146,6 +146,13 @@ hipError_t launch_gemm(int dtype, const GemmTask* d_tasks, const GemmPart* d_par
                        int max_m, int max_n, hipStream_t s);
 hipError_t launch_dot(int dtype, const DotTask* d_tasks, int ntasks, hipStream_t s);
 hipError_t launch_sumsq(int dtype, const void* x, int64_t n, double* out_norm, hipStream_t s);
+// Frobenius norms of several buffers in one launch (one workgroup per buffer).
+struct SumsqTask {
+  const void* x;
+  int64_t n;
+  double* out;
+};
+hipError_t launch_sumsq_batched(int dtype, const SumsqTask* d_tasks, int ntasks, hipStream_t s);
 hipError_t launch_scale(int dtype, void* x, int64_t n, const double* d_norm, hipStream_t s);
 hipError_t launch_copy_segs(int dtype, const CopySeg* d_segs, int nsegs, hipStream_t s);
 // out[idx ? idx[o] : o] = sum of slots[seg[o] .. seg[o+1])

@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "wave.h"
 
 namespace tto {
 
@@ -82,6 +83,20 @@ __global__ __launch_bounds__(1024) void k_sumsq(const T* __restrict__ x, int64_t
   }
   s = block_sum256(s, red);
   if (threadIdx.x == 0) *out = sqrt(s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_sumsq_batched(const SumsqTask* __restrict__ tasks) {
+  __shared__ double red[16];
+  const SumsqTask tk = tasks[blockIdx.x];
+  const gptr<const T> x = glb((const T*)tk.x);
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < tk.n; i += 1024) {
+    const double v = (double)x[i];
+    s += v * v;
+  }
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) *glb(tk.out) = sqrt(s);
 }
 
 template <typename T>
@@ -324,6 +339,15 @@ hipError_t launch_dot(int dtype, const DotTask* d_tasks, int ntasks, hipStream_t
 hipError_t launch_sumsq(int dtype, const void* x, int64_t n, double* out, hipStream_t s) {
   if (dtype == 0) hipLaunchKernelGGL(k_sumsq<double>, dim3(1), dim3(1024), 0, s, (const double*)x, n, out);
   else hipLaunchKernelGGL(k_sumsq<float>, dim3(1), dim3(1024), 0, s, (const float*)x, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq_batched(int dtype, const SumsqTask* d_tasks, int ntasks, hipStream_t s) {
+  for (int first = 0; first < ntasks; first += 65535) {
+    const int cnt = (ntasks - first) < 65535 ? (ntasks - first) : 65535;
+    if (dtype == 0) hipLaunchKernelGGL(k_sumsq_batched<double>, dim3(cnt), dim3(1024), 0, s, d_tasks + first);
+    else hipLaunchKernelGGL(k_sumsq_batched<float>, dim3(cnt), dim3(1024), 0, s, d_tasks + first);
+  }
   return hipGetLastError();
 }
 

@@ -701,7 +701,9 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
   int32_t* d_ranks = (int32_t*)dev_scratch(c, (size_t)nj * (TT_MAXD + 1) * 4);
   int32_t* h_ranks = (int32_t*)c->pin.alloc((size_t)nj * (TT_MAXD + 1) * 4);
   double* h_norms = (double*)c->pin.alloc((size_t)nj * 8);
-  if (!d_ranks || !h_ranks || !h_norms) return fail(c, TT_ENOMEM, "small buffers");
+  double* d_norms = (double*)dev_scratch(c, (size_t)nj * 8);   // ||x|| of every job, read back at once
+  if (!d_ranks || !h_ranks || !h_norms || !d_norms) return fail(c, TT_ENOMEM, "small buffers");
+  for (int j = 0; j < nj; ++j) st[j].d_norm = d_norms + j;
 
   // ---------------- order-1 jobs: the sum itself (components accumulated in order)
   {
@@ -709,7 +711,6 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     for (int j = 0; j < nj; ++j) {
       RJob& jb = jobs[j];
       if (jb.d != 1) continue;
-      st[j].d_norm = (double*)dev_scratch(c, 8);
       if (!jb.orth_only && jb.out->capacity < jb.n[0]) jb.status = TT_ECAPACITY;
       else maxc = std::max(maxc, jb.comps.size());
     }
@@ -730,11 +731,16 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       const CopySeg* dg = upload(c, g);
       if ((e = launch_copy_segs(dtype, dg, (int)g.size(), s)) != hipSuccess) return hip_fail(c, e, "copy");
     }
+    std::vector<SumsqTask> nt;
     for (int j = 0; j < nj; ++j) {
       RJob& jb = jobs[j];
       if (jb.d != 1 || jb.status != TT_OK) continue;
-      if ((e = launch_sumsq(dtype, jb.orth_only ? st[j].C : jb.out->data, jb.n[0], st[j].d_norm, s)) != hipSuccess)
-        return hip_fail(c, e, "sumsq");
+      nt.push_back(SumsqTask{jb.orth_only ? st[j].C : jb.out->data, jb.n[0], st[j].d_norm});
+    }
+    if (!nt.empty()) {
+      const SumsqTask* dn = upload(c, nt);
+      if (!dn) return fail(c, TT_ENOMEM, "task upload");
+      if ((e = launch_sumsq_batched(dtype, dn, (int)nt.size(), s)) != hipSuccess) return hip_fail(c, e, "sumsq");
     }
   }
 
@@ -764,6 +770,18 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
   int maxd = 0;
   for (const RJob& jb : jobs) maxd = std::max(maxd, jb.d);
   std::vector<hipEvent_t> qx_done(maxd, nullptr);   // side-stream completion of the explicit Q of a step
+  // one identity for every job's explicit Q: the largest of the jobs' identity buffers
+  double* eye = nullptr;
+  int64_t eye_n = 0;
+  for (int j = 0; j < nj; ++j) {
+    int64_t nmax = 0;
+    for (int kk = 2; kk < jobs[j].d; ++kk) nmax = std::max(nmax, jobs[j].R[kk]);
+    if (st[j].eye && nmax > eye_n) {
+      eye_n = nmax;
+      eye = st[j].eye;
+    }
+  }
+  if (eye && (e = launch_eye(eye, (int)eye_n, s)) != hipSuccess) return hip_fail(c, e, "eye");
   for (int step = 0; step + 1 < maxd; ++step) {
     std::vector<Tree*> trees;
     std::vector<int> act;
@@ -785,14 +803,11 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
         JobState& js = st[j];
         if (k < 2 || !js.Qx[k]) continue;
         const int64_t sk = js.s[k];   // columns of Q_k: min(R_k, n_k s_{k+1})
-        int64_t nmax = 0;
-        for (int kk = 2; kk < jobs[j].d; ++kk) nmax = std::max(nmax, jobs[j].R[kk]);
-        if (k == jobs[j].d - 1 && (e = launch_eye(js.eye, (int)nmax, s)) != hipSuccess) return hip_fail(c, e, "eye");
         Carver cv;
         cv.base = js.qx_block;
         cv.cap = js.qx_cap;
         std::vector<ApplyLevel> pl;
-        plan_apply(cv, js.rl[k], js.eye, nmax, sk, js.Qx[k], jobs[j].dtype, sk, 1, pl);
+        plan_apply(cv, js.rl[k], eye, eye_n, sk, js.Qx[k], jobs[j].dtype, sk, 1, pl);
         if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "explicit Q scratch");
         xplans.push_back(std::move(pl));
       }
@@ -886,11 +901,18 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
   }
 
   // ---------------- norms
-  for (int j = 0; j < nj; ++j) {
-    RJob& jb = jobs[j];
-    if (jb.d < 2) continue;
-    if ((e = launch_sumsq(dtype, st[j].C, jb.n[0] * st[j].s[1], st[j].d_norm, s)) != hipSuccess)
-      return hip_fail(c, e, "norm");
+  {
+    std::vector<SumsqTask> nt;
+    for (int j = 0; j < nj; ++j) {
+      RJob& jb = jobs[j];
+      if (jb.d < 2) continue;
+      nt.push_back(SumsqTask{st[j].C, jb.n[0] * st[j].s[1], st[j].d_norm});
+    }
+    if (!nt.empty()) {
+      const SumsqTask* dn = upload(c, nt);
+      if (!dn) return fail(c, TT_ENOMEM, "task upload");
+      if ((e = launch_sumsq_batched(dtype, dn, (int)nt.size(), s)) != hipSuccess) return hip_fail(c, e, "norm");
+    }
   }
 
   // ---------------- left-to-right sweep
@@ -911,12 +933,16 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       std::vector<std::vector<ApplyLevel>> plans;
       std::vector<GemmSTask> xg;
       int xm = 0, xn = 0;
+      std::vector<hipEvent_t> waited;
       for (int j : act) {
         RJob& jb = jobs[j];
         JobState& js = st[j];
         if (js.Qx[k]) {
           hipEvent_t ev = qx_done[jb.d - 1 - k];
-          if (ev && (e = hipStreamWaitEvent(s, ev, 0)) != hipSuccess) return hip_fail(c, e, "event");
+          if (ev && std::find(waited.begin(), waited.end(), ev) == waited.end()) {
+            if ((e = hipStreamWaitEvent(s, ev, 0)) != hipSuccess) return hip_fail(c, e, "event");
+            waited.push_back(ev);
+          }
           GemmSTask g;
           const int64_t M = jb.n[k] * js.s[k + 1], sk = js.s[k];
           g.A = js.Qx[k];   // M x s_k row-major
@@ -1096,11 +1122,8 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     if (rs != TT_OK) return rs;
   }
   // ---------------- norms back, ranks out
-  for (int j = 0; j < nj; ++j) {
-    if (jobs[j].status != TT_OK || !st[j].d_norm) continue;
-    if ((e = hipMemcpyAsync(h_norms + j, st[j].d_norm, 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
-      return hip_fail(c, e, "norm readback");
-  }
+  if ((e = hipMemcpyAsync(h_norms, d_norms, (size_t)nj * 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+    return hip_fail(c, e, "norm readback");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "sync");
   for (int j = 0; j < nj; ++j) {
     RJob& jb = jobs[j];
