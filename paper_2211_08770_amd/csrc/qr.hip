@@ -482,7 +482,11 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
         // all loads first (no wait between them), then the products
         double x[RT];
 #pragma unroll
-        for (int t = 0; t < RT; ++t) x[t] = (t < rt) ? xs[lane + 64 * t] : 0.0;
+        for (int t = 0; t < RT; ++t) {
+          // unconditional load (the buffer holds every row slot), masked value: no branch per slot
+          const double v = xs[lane + 64 * t];
+          x[t] = (t < rt) ? v : 0.0;
+        }
         double d0 = 0.0, d1 = 0.0;
 #pragma unroll
         for (int t = 0; t < RT; ++t) {
