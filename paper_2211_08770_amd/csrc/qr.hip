@@ -348,24 +348,39 @@ __device__ __attribute__((always_inline)) void gram_v(const TV* __restrict__ V, 
   __syncthreads();
 }
 
-// T of the compact WY form H_0 ... H_15 = I - V T V^T (forward, column-wise):
-// T_ii = tau_i, T_{a,i} = -tau_i sum_{b=a}^{i-1} T_ab S_bi.  Lane a of wave 0
-// builds row a; S (LDS, strictly upper V^T V) and tau (LDS) are inputs.
-__device__ __attribute__((always_inline)) void form_t(const double* __restrict__ S, const double* __restrict__ tau, double* __restrict__ Tm) {
+// T of the compact WY form H_0 ... H_15 = I - V T V^T (forward): T_ii = tau_i,
+// and two adjacent blocks of reflectors with factors T1, T2 combine into
+// [[T1, -T1 S12 T2], [0, T2]] with S12 = V1^T V2 (a block of S).  Blocks of
+// 1, 2, 4 and 8 columns are combined in four levels, every element of a
+// level's products by its own thread (two barrier-separated steps, at most 8
+// terms each).  S (LDS, strictly upper V^T V) and tau (LDS) are inputs; a zero
+// tau gives a zero row and column.  Called by the whole workgroup.
+__device__ __attribute__((always_inline)) void form_t(const double* __restrict__ S, const double* __restrict__ tau,
+                                                      double* __restrict__ Tm) {
+  __shared__ double Mt[NB * NB];
   const int tid = threadIdx.x;
-  if (tid < NB) {
-    const int a = tid;
-    double row[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      double acc = 0.0;
-#pragma unroll
-      for (int b = 0; b < i; ++b) acc += row[b] * S[b * NB + i];
-      row[i] = (a < i) ? -tau[i] * acc : (a == i ? tau[i] : 0.0);
-      __builtin_amdgcn_sched_barrier(0);
+  const int r = (tid >> 4) & (NB - 1), c = tid & (NB - 1);
+  const bool mine = tid < NB * NB;
+  if (mine) Tm[tid] = (r == c) ? tau[r] : 0.0;
+  __syncthreads();
+#pragma unroll 1
+  for (int h = 1; h < NB; h <<= 1) {
+    const int p = (r / (2 * h)) * (2 * h);
+    const bool in12 = mine && (c / (2 * h)) == (r / (2 * h)) && (r - p) < h && (c - p) >= h;
+    if (in12) {   // M = S12 T2 (T2 upper triangular)
+      double m = 0.0;
+#pragma unroll 1
+      for (int k = p + h; k <= c; ++k) m += S[r * NB + k] * Tm[k * NB + c];
+      Mt[tid] = m;
     }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) Tm[a * NB + i] = row[i];
+    __syncthreads();
+    if (in12) {   // T12 = -T1 M (T1 upper triangular)
+      double t = 0.0;
+#pragma unroll 1
+      for (int k = r; k < p + h; ++k) t += Tm[r * NB + k] * Mt[k * NB + c];
+      Tm[tid] = -t;
+    }
+    __syncthreads();
   }
 }
 
