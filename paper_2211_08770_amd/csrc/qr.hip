@@ -404,26 +404,32 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   if (tk.nchild == 0) {
     const gptr<const TS> src = glb((const TS*)tk.src);
     const int total = m * N;
-    // walk the source along its unit stride (rows of a transposed source)
+    // walk the source along its unit stride (rows of a transposed source); the (outer, inner)
+    // position of element tid + j NT advances by (NT / inner, NT % inner) with a carry
     const bool by_col = tk.src_rs == 1 && tk.src_cs != 1;
     const int inner = by_col ? m : N;
+    const int d_o = NT / inner, d_i = NT - d_o * inner;
+    int o = tid / inner, i = tid - o * inner;
     for (int base = tid; base < total; base += UF * NT) {
       TS v[UF];
+      int oo[UF], ii[UF];
 #pragma unroll
       for (int k = 0; k < UF; ++k) {
-        const int idx = (base + k * NT < total) ? base + k * NT : total - 1;
-        const int o = idx / inner, i = idx - o * inner;
+        oo[k] = o;
+        ii[k] = i;
+        const bool in = base + k * NT < total;
         const int r = by_col ? i : o, c = by_col ? o : i;
-        v[k] = src[r * tk.src_rs + c * tk.src_cs];
-      }
-#pragma unroll
-      for (int k = 0; k < UF; ++k) {
-        const int idx = base + k * NT;
-        if (idx < total) {
-          const int o = idx / inner, i = idx - o * inner;
-          A[by_col ? i * N + o : idx] = (TT)v[k];
+        v[k] = src[in ? r * tk.src_rs + c * tk.src_cs : 0];
+        o += d_o;
+        i += d_i;
+        if (i >= inner) {
+          i -= inner;
+          ++o;
         }
       }
+#pragma unroll
+      for (int k = 0; k < UF; ++k)
+        if (base + k * NT < total) A[by_col ? ii[k] * N + oo[k] : oo[k] * N + ii[k]] = (TT)v[k];
     }
   } else {
     int row0 = 0;

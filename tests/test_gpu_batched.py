@@ -34,3 +34,21 @@ def test_batched_uneven_matches_oracle_and_singles(dtype):
         assert diff_norm(host_cores(o), ref) <= tol * nx
         single = tt.round(x, delta)
         assert single.r == o.r and torch.equal(single.data, o.data)
+
+
+def test_batched_mixed_orders_including_order_one():
+    """Jobs of order 1 to 4 in one batch (the norms of every job come back in one array): each
+    equals its oracle result and the same job rounded alone."""
+    tt = need_gpu()
+    delta = 1e-6
+    jobs = synth.uneven_jobs(seed=30011, njobs=10, d_range=(1, 4), n_choices=(3, 5), r_range=(1, 6),
+                             dtype=np.float64)
+    assert any(d == 1 for _, (d, _, _) in jobs) and any(d >= 3 for _, (d, _, _) in jobs)
+    xs = [dev_tt(c, torch.float64) for c, _ in jobs]
+    outs = tt.round_batched(xs, delta)
+    for (c, _), o, x in zip(jobs, outs, xs):
+        ref = oracle.tt_round(c, delta)
+        assert o.r == oracle.tt_ranks(ref)
+        assert diff_norm(host_cores(o), ref) <= 1e-12 * oracle.tt_norm(c)
+        single = tt.round(x, delta)
+        assert single.r == o.r and torch.equal(single.data, o.data)
