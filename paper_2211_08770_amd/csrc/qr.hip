@@ -294,10 +294,28 @@ __device__ __attribute__((always_inline)) void publish(const double (&y)[(MAXR +
   const double alpha = readlane_d(y[0], j);
   double tau = 0.0, beta = alpha, scal = 0.0;
   if (sigma != 0.0) {
-    const double nrm = sqrt(alpha * alpha + sigma);
-    beta = (alpha >= 0.0) ? -nrm : nrm;
-    tau = (beta - alpha) / beta;
-    scal = 1.0 / (alpha - beta);
+    const double w = fma(alpha, alpha, sigma);
+    if (w > 1e-280 && w < 1e280) {
+      // hardware estimates of 1/sqrt and 1/x, each refined by two Newton steps
+      double ys = __builtin_amdgcn_rsq(w);
+      ys = fma(0.5 * ys, fma(-w * ys, ys, 1.0), ys);
+      ys = fma(0.5 * ys, fma(-w * ys, ys, 1.0), ys);
+      const double nrm = w * ys;
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      double rb = __builtin_amdgcn_rcp(beta);
+      rb = fma(rb, fma(-beta, rb, 1.0), rb);
+      rb = fma(rb, fma(-beta, rb, 1.0), rb);
+      tau = (beta - alpha) * rb;
+      const double den = alpha - beta;
+      double rs = __builtin_amdgcn_rcp(den);
+      rs = fma(rs, fma(-den, rs, 1.0), rs);
+      scal = fma(rs, fma(-den, rs, 1.0), rs);
+    } else {
+      const double nrm = sqrt(alpha * alpha + sigma);
+      beta = (alpha >= 0.0) ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
   }
   if (lane == 0) {
     prm[0] = tau;
