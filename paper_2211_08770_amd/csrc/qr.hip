@@ -275,9 +275,9 @@ __device__ __attribute__((always_inline)) void block_update(gptr<TA> __restrict_
 // (zeros elsewhere, up to the last used row slot) to xs, and its Householder
 // reflector parameters to prm = {tau, scal, beta}: H = I - tau v v^T with
 // v = [1; scal * x], beta the new diagonal.  Called by the owning wave.
-__device__ __attribute__((always_inline)) void publish(const double (&y)[(MAXR + 63) / 64], int j, int rows, int rt, double* __restrict__ xs,
+template <int RT>
+__device__ __attribute__((always_inline)) void publish(const double (&y)[RT], int j, int rows, int rt, double* __restrict__ xs,
                                double* __restrict__ prm) {
-  constexpr int RT = (MAXR + 63) / 64;
   const int lane = threadIdx.x & 63;
   double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -402,7 +402,8 @@ __device__ __attribute__((always_inline)) void form_t(const double* __restrict__
   }
 }
 
-template <typename TS, typename TT>
+// RT: row slots per lane of the panel columns (tiles of at most 64 RT rows).
+template <typename TS, typename TT, int RT>
 __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tasks,
                                                   const QrTask* __restrict__ children, int ldv) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -477,7 +478,6 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   const int kmax = m < N ? m : N;
   TT* P = (TT*)smem;                                       // NB columns x ldv rows
   double* scr = (double*)(smem + panel_bytes((int)sizeof(TT), ldv));
-  constexpr int RT = (MAXR + 63) / 64;                     // row slots per lane
   for (int p0 = 0, pi = 0; p0 < kmax; p0 += NB, ++pi) {
     const int nb = (kmax - p0) < NB ? (kmax - p0) : NB;
     const int rows = panel_rows(rowl, bstart, m, tk.nchild, tk.kc0, tk.kc_last, p0, nb);
@@ -756,20 +756,33 @@ hipError_t raise_lds(K kernel, size_t bytes) {
 
 }  // namespace
 
+// smallest instantiated row-slot count that holds max_rows (unconditional
+// loads of the published column then read no slot past the tile)
+constexpr int RT_MAX = (MAXR + 63) / 64;
+static_assert(RT_MAX == 13, "row-slot buckets below assume 800-row tiles");
+template <typename TS, typename TT>
+void launch_factor_rt(int max_rows, dim3 grid, dim3 block, size_t sm, hipStream_t s, const QrTask* t,
+                      const QrTask* c, int ldv) {
+  const int rt = (max_rows + 63) / 64;
+  if (rt <= 4) hipLaunchKernelGGL((k_qr_factor<TS, TT, 4>), grid, block, sm, s, t, c, ldv);
+  else if (rt <= 7) hipLaunchKernelGGL((k_qr_factor<TS, TT, 7>), grid, block, sm, s, t, c, ldv);
+  else if (rt <= 10) hipLaunchKernelGGL((k_qr_factor<TS, TT, 10>), grid, block, sm, s, t, c, ldv);
+  else hipLaunchKernelGGL((k_qr_factor<TS, TT, RT_MAX>), grid, block, sm, s, t, c, ldv);
+}
+
 hipError_t launch_qr_factor(int dtype_src, int dtype_tile, const QrTask* d_tasks, const QrTask* d_children,
                             int ntasks, int max_rows, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;
+  if (max_rows > MAXR) return hipErrorInvalidValue;
   const int ldv = max_rows + 1;
   dim3 grid(ntasks), block(NT);
   if (dtype_tile == 0) {
     const size_t sm = panel_smem(8, ldv);
-    if (dtype_src == 0)
-      hipLaunchKernelGGL((k_qr_factor<double, double>), grid, block, sm, s, d_tasks, d_children, ldv);
-    else
-      hipLaunchKernelGGL((k_qr_factor<float, double>), grid, block, sm, s, d_tasks, d_children, ldv);
+    if (dtype_src == 0) launch_factor_rt<double, double>(max_rows, grid, block, sm, s, d_tasks, d_children, ldv);
+    else launch_factor_rt<float, double>(max_rows, grid, block, sm, s, d_tasks, d_children, ldv);
   } else {
     const size_t sm = panel_smem(4, ldv);
-    hipLaunchKernelGGL((k_qr_factor<float, float>), grid, block, sm, s, d_tasks, d_children, ldv);
+    launch_factor_rt<float, float>(max_rows, grid, block, sm, s, d_tasks, d_children, ldv);
   }
   return hipGetLastError();
 }
@@ -792,12 +805,21 @@ hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tas
   return hipGetLastError();
 }
 
+template <typename TS, typename TT>
+hipError_t raise_factor(size_t bytes) {
+  hipError_t e;
+  if ((e = raise_lds(k_qr_factor<TS, TT, 4>, bytes)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_factor<TS, TT, 7>, bytes)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_factor<TS, TT, 10>, bytes)) != hipSuccess) return e;
+  return raise_lds(k_qr_factor<TS, TT, RT_MAX>, bytes);
+}
+
 hipError_t qr_kernels_init() {
   hipError_t e;
   const size_t s8 = panel_smem(8, MAXR + 1), s4 = panel_smem(4, MAXR + 1);
-  if ((e = raise_lds(k_qr_factor<double, double>, s8)) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_factor<float, double>, s8)) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_factor<float, float>, s4)) != hipSuccess) return e;
+  if ((e = raise_factor<double, double>(s8)) != hipSuccess) return e;
+  if ((e = raise_factor<float, double>(s8)) != hipSuccess) return e;
+  if ((e = raise_factor<float, float>(s4)) != hipSuccess) return e;
   if ((e = raise_lds(k_qr_apply<double, double>, s8)) != hipSuccess) return e;
   if ((e = raise_lds(k_qr_apply<double, float>, s8)) != hipSuccess) return e;
   if ((e = raise_lds(k_qr_apply<float, double>, s4)) != hipSuccess) return e;
