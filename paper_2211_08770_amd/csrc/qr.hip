@@ -402,6 +402,82 @@ __device__ __attribute__((always_inline)) void form_t(const double* __restrict__
   }
 }
 
+// Householder factorisation of the nb columns of one panel held in P (LDS,
+// column-major [NB][ldv], rows [0, rows)): column c in the registers of wave c
+// (RS row slots per lane, rows <= 64 RS); per column the owner publishes it
+// (xs, prm in scr), every later column's wave takes one dot product and
+// updates itself: one workgroup barrier per column.  On return P holds the
+// factored panel (R on and above the diagonal, V below) and taus the tau.
+template <typename TT, int RS>
+__device__ __attribute__((always_inline)) void panel_columns(TT* __restrict__ P, int ldv, int rows, int nb,
+                                                             double* __restrict__ scr, double* __restrict__ prm,
+                                                             double* __restrict__ taus) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rt = (rows + 63) >> 6;
+  const bool mine = wave < nb;
+  double y[RS];
+#pragma unroll
+  for (int t = 0; t < RS; ++t) {
+    const int r = lane + 64 * t;
+    y[t] = (mine && t < rt && r < rows) ? (double)P[wave * ldv + r] : 0.0;
+  }
+  if (wave == 0) publish(y, 0, rows, rt, scr, prm);
+  __syncthreads();
+  for (int jj = 0; jj < nb; ++jj) {
+    if (mine && wave >= jj) {
+      // column jj below its diagonal (zero elsewhere) and its reflector
+      const double* xs = scr + (jj & 1) * XSTRIDE;
+      const double* pp = prm + (jj & 1) * 4;
+      // all loads first (no wait between them), then the products
+      double x[RS];
+#pragma unroll
+      for (int t = 0; t < RS; ++t) {
+        // unconditional load (the buffer holds every row slot), masked value: no branch per slot
+        const double v = xs[lane + 64 * t];
+        x[t] = (t < rt) ? v : 0.0;
+      }
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < RS; ++t) {
+        if (t & 1) d1 += x[t] * y[t];
+        else d0 += x[t] * y[t];
+      }
+      const double tau = pp[0], scal = pp[1];
+      if (wave > jj) {
+        // apply H_jj to the own column
+        const double dot = wave_sum(d0 + d1);
+        if (tau != 0.0) {
+          const double tw = tau * (scal * dot + readlane_d(y[0], jj));
+          const double f = tw * scal;
+#pragma unroll
+          for (int t = 0; t < RS; ++t) y[t] -= f * x[t];
+          if (lane == jj) y[0] -= tw;
+        }
+        if (wave == jj + 1) publish(y, jj + 1, rows, rt, scr + ((jj + 1) & 1) * XSTRIDE, prm + ((jj + 1) & 1) * 4);
+      } else if (wave == jj) {
+        // the own column becomes beta on the diagonal and the reflector below
+        // (rounded to the tile precision: the MFMA updates use that V)
+        if (tau != 0.0) {
+#pragma unroll
+          for (int t = 0; t < RS; ++t)
+            if (t < rt && lane + 64 * t > jj) y[t] = (double)(TT)(y[t] * scal);
+        }
+        if (lane == jj) y[0] = pp[2];
+        if (lane == 0) taus[jj] = tau;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- factored panel back to LDS
+  if (mine) {
+#pragma unroll
+    for (int t = 0; t < RS; ++t) {
+      const int r = lane + 64 * t;
+      if (t < rt && r < rows) P[wave * ldv + r] = (TT)y[t];
+    }
+  }
+}
+
 // RT: row slots per lane of the panel columns (tiles of at most 64 RT rows).
 template <typename TS, typename TT, int RT>
 __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tasks,
@@ -414,7 +490,7 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   __shared__ double taus[NB];
   __shared__ double prm[8];
   const QrTask tk = tasks[blockIdx.x];
-  const int m = tk.m, N = tk.ncol, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m = tk.m, N = tk.ncol, tid = threadIdx.x;
   const gptr<TT> A = glb((TT*)tk.tile);
 
   // ---- fill the tile (UF loads in flight per thread: clamped addresses, masked stores;
@@ -502,69 +578,14 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
     }
     if (tid < NB) taus[tid] = 0.0;
     __syncthreads();
-    // ---- panel column `wave` into registers (double); wave 0 publishes column 0
-    const int rt = (rows + 63) >> 6;
-    const bool mine = wave < nb;
-    double y[RT];
-#pragma unroll
-    for (int t = 0; t < RT; ++t) {
-      const int r = lane + 64 * t;
-      y[t] = (mine && t < rt && r < rows) ? (double)P[wave * ldv + r] : 0.0;
-    }
-    if (wave == 0) publish(y, 0, rows, rt, scr, prm);
-    __syncthreads();
-    for (int jj = 0; jj < nb; ++jj) {
-      if (mine && wave >= jj) {
-        // column jj below its diagonal (zero elsewhere) and its reflector
-        const double* xs = scr + (jj & 1) * XSTRIDE;
-        const double* pp = prm + (jj & 1) * 4;
-        // all loads first (no wait between them), then the products
-        double x[RT];
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          // unconditional load (the buffer holds every row slot), masked value: no branch per slot
-          const double v = xs[lane + 64 * t];
-          x[t] = (t < rt) ? v : 0.0;
-        }
-        double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          if (t & 1) d1 += x[t] * y[t];
-          else d0 += x[t] * y[t];
-        }
-        const double tau = pp[0], scal = pp[1];
-        if (wave > jj) {
-          // apply H_jj to the own column
-          const double dot = wave_sum(d0 + d1);
-          if (tau != 0.0) {
-            const double tw = tau * (scal * dot + readlane_d(y[0], jj));
-            const double f = tw * scal;
-#pragma unroll
-            for (int t = 0; t < RT; ++t) y[t] -= f * x[t];
-            if (lane == jj) y[0] -= tw;
-          }
-          if (wave == jj + 1) publish(y, jj + 1, rows, rt, scr + ((jj + 1) & 1) * XSTRIDE, prm + ((jj + 1) & 1) * 4);
-        } else if (wave == jj) {
-          // the own column becomes beta on the diagonal and the reflector below
-          // (rounded to the tile precision: the MFMA updates use that V)
-          if (tau != 0.0) {
-#pragma unroll
-            for (int t = 0; t < RT; ++t)
-              if (t < rt && lane + 64 * t > jj) y[t] = (double)(TT)(y[t] * scal);
-          }
-          if (lane == jj) y[0] = pp[2];
-          if (lane == 0) taus[jj] = tau;
-        }
-      }
-      __syncthreads();
-    }
-    // ---- factored panel to LDS, then to the tile (coalesced); tau out
-    if (mine) {
-#pragma unroll
-      for (int t = 0; t < RT; ++t) {
-        const int r = lane + 64 * t;
-        if (t < rt && r < rows) P[wave * ldv + r] = (TT)y[t];
-      }
+    // ---- panel columns: the smallest row-slot count that holds this panel's rows
+    {
+      const int rt = (rows + 63) >> 6;
+      if (RT > 4 && rt <= 2) panel_columns<TT, 2>(P, ldv, rows, nb, scr, prm, taus);
+      else if (RT > 4 && rt <= 4) panel_columns<TT, 4>(P, ldv, rows, nb, scr, prm, taus);
+      else if (RT > 7 && rt <= 7) panel_columns<TT, 7>(P, ldv, rows, nb, scr, prm, taus);
+      else if (RT > 10 && rt <= 10) panel_columns<TT, 10>(P, ldv, rows, nb, scr, prm, taus);
+      else panel_columns<TT, RT>(P, ldv, rows, nb, scr, prm, taus);
     }
     __syncthreads();
     for (int idx = tid; idx < rows * NB; idx += NT) {
