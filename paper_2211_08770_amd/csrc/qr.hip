@@ -368,10 +368,11 @@ __device__ __attribute__((always_inline)) void gram_v(const TV* __restrict__ V, 
 
 // T of the compact WY form H_0 ... H_15 = I - V T V^T (forward): T_ii = tau_i,
 // and two adjacent blocks of reflectors with factors T1, T2 combine into
-// [[T1, -T1 S12 T2], [0, T2]] with S12 = V1^T V2 (a block of S).  Blocks of
-// 1, 2, 4 and 8 columns are combined in four levels, every element of a
-// level's products by its own thread (two barrier-separated steps, at most 8
-// terms each).  S (LDS, strictly upper V^T V) and tau (LDS) are inputs; a zero
+// [[T1, -T1 S12 T2], [0, T2]] with S12 = V1^T V2 (a block of S).  The 4 x 4
+// diagonal blocks come from the recurrence T_rc = -tau_c sum_b T_rb S_bc directly; blocks of 4 and
+// 8 columns are then combined in two levels, every element of a level's
+// products by its own thread (two barrier-separated steps, at most 8 terms
+// each).  S (LDS, strictly upper V^T V) and tau (LDS) are inputs; a zero
 // tau gives a zero row and column.  Called by the whole workgroup.
 __device__ __attribute__((always_inline)) void form_t(const double* __restrict__ S, const double* __restrict__ tau,
                                                       double* __restrict__ Tm) {
@@ -379,10 +380,30 @@ __device__ __attribute__((always_inline)) void form_t(const double* __restrict__
   const int tid = threadIdx.x;
   const int r = (tid >> 4) & (NB - 1), c = tid & (NB - 1);
   const bool mine = tid < NB * NB;
-  if (mine) Tm[tid] = (r == c) ? tau[r] : 0.0;
+  // 4 x 4 diagonal blocks directly: row r of a block by the recurrence
+  // T_rc = -tau_c sum_{r <= b < c} T_rb S_bc (at most three terms), each element by its own thread
+  if (mine) {
+    double v = 0.0;
+    const int d = c - r;
+    if ((c & ~3) == (r & ~3) && d >= 0) {
+      const double t0 = tau[r];
+      v = t0;
+      if (d >= 1) {
+        const double t1 = -tau[r + 1] * (t0 * S[r * NB + r + 1]);
+        v = t1;
+        if (d >= 2) {
+          const double t2 = -tau[r + 2] * (t0 * S[r * NB + r + 2] + t1 * S[(r + 1) * NB + r + 2]);
+          v = t2;
+          if (d >= 3)
+            v = -tau[r + 3] * (t0 * S[r * NB + r + 3] + t1 * S[(r + 1) * NB + r + 3] + t2 * S[(r + 2) * NB + r + 3]);
+        }
+      }
+    }
+    Tm[tid] = v;
+  }
   __syncthreads();
 #pragma unroll 1
-  for (int h = 1; h < NB; h <<= 1) {
+  for (int h = 4; h < NB; h <<= 1) {
     const int p = (r / (2 * h)) * (2 * h);
     const bool in12 = mine && (c / (2 * h)) == (r / (2 * h)) && (r - p) < h && (c - p) >= h;
     if (in12) {   // M = S12 T2 (T2 upper triangular)

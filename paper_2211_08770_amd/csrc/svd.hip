@@ -54,8 +54,11 @@ __device__ inline void rr_pair(int round, int pair, int kp, int& p, int& q) {
     p = m;
     q = round;
   } else {
-    p = (round + pair) % m;
-    q = (round - pair + m) % m;
+    // round, pair < m: one conditional subtraction each instead of a remainder
+    p = round + pair;
+    if (p >= m) p -= m;
+    q = round - pair;
+    if (q < 0) q += m;
   }
   if (p > q) {
     const int t = p;
