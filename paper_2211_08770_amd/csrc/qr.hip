@@ -181,6 +181,12 @@ __device__ __attribute__((always_inline)) void update_rows(gptr<TA> __restrict__
     for (int ub = 0; ub < UB; ++ub)
 #pragma unroll
       for (int v = 0; v < 4; ++v) old[ub][v] = A[idx[ub][v]];
+    // every loaded value is needed in a register here: the compiler may not sink a load
+    // into its conditional store below (a full round trip inside the store sequence)
+#pragma unroll
+    for (int ub = 0; ub < UB; ++ub)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) asm volatile("" ::"v"(old[ub][v]));
 #pragma unroll
     for (int ub = 0; ub < UB; ++ub) {
       const int ra = rb0 + NB * ub + (lane & 15);
