@@ -560,18 +560,27 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
       const gptr<const TS> ct = glb((const TS*)ch.tile);
       const int kc = ch.m < N ? ch.m : N;
       const int total = kc * N;
+      const int d_r = NT / N, d_c = NT - d_r * N;   // (row, column) step of NT elements
+      int r = tid / N, c = tid - r * N;
       for (int base = tid; base < total; base += UF * NT) {
         TS v[UF];
-#pragma unroll
-        for (int k = 0; k < UF; ++k) v[k] = ct[(base + k * NT < total) ? base + k * NT : total - 1];
+        int rr[UF], cc[UF];
 #pragma unroll
         for (int k = 0; k < UF; ++k) {
-          const int idx = base + k * NT;
-          if (idx < total) {
-            const int r = idx / N, c = idx - r * N;
-            A[(int64_t)(row0 + r) * N + c] = (c >= r) ? (TT)v[k] : (TT)0;
+          v[k] = ct[(base + k * NT < total) ? base + k * NT : total - 1];
+          rr[k] = r;
+          cc[k] = c;
+          r += d_r;
+          c += d_c;
+          if (c >= N) {
+            c -= N;
+            ++r;
           }
         }
+#pragma unroll
+        for (int k = 0; k < UF; ++k)
+          if (base + k * NT < total)
+            A[(int64_t)(row0 + rr[k]) * N + cc[k]] = (cc[k] >= rr[k]) ? (TT)v[k] : (TT)0;
       }
       row0 += kc;
     }
