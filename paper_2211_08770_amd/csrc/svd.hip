@@ -226,6 +226,7 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   __shared__ double nrm2[MAXC];
   __shared__ double red[NW];
   __shared__ int rots, kact, lenact, tsel;
+  __shared__ int wcount[NW], wmax[NW];
   __shared__ double edrop;
 
   const SvdTask tk = tasks[blockIdx.x];
@@ -243,16 +244,43 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   };
 
   // ---- column norms and deflation
-  for (int j = wave; j < nc; j += NW) {
-    double s = 0.0;
-    for (int i = lane; i < N; i += 64) {
-      const double v = aval(i, j);
-      s += v * v;
+  if (tall) {
+    // A = R (row-major): one thread per column and RG row groups, so that the reads of a
+    // row are coalesced; partial sums in the LDS block (free until A is filled)
+    constexpr int RG = NT / 256;
+    double* part = svd_lds;
+    for (int j0 = 0; j0 < nc; j0 += 256) {
+      const int j = j0 + (tid & 255), g = tid >> 8;
+      double s = 0.0;
+      if (j < nc) {
+        const int imax = (tk.upper && j + 1 < N) ? j + 1 : N;   // R(i, j) = 0 below the diagonal
+        for (int i = g; i < imax; i += RG) {
+          const double v = aval(i, j);
+          s += v * v;
+        }
+      }
+      part[g * 256 + (tid & 255)] = s;
+      __syncthreads();
+      if (g == 0 && j < nc) {
+        double a = 0.0;
+        for (int q = 0; q < RG; ++q) a += part[q * 256 + tid];
+        nrm2[j] = a;
+      }
+      __syncthreads();
     }
-    s = wave_sum(s);
-    if (lane == 0) nrm2[j] = s;
+  } else {
+    // A = R^T: column j of A is row j of R (contiguous), one wave per column
+    for (int j = wave; j < nc; j += NW) {
+      double s = 0.0;
+      for (int i = lane; i < N; i += 64) {
+        const double v = aval(i, j);
+        s += v * v;
+      }
+      s = wave_sum(s);
+      if (lane == 0) nrm2[j] = s;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   double tot = 0.0;
   for (int j = tid; j < nc; j += NT) tot += nrm2[j];
   tot = block_sum(tot, red);
@@ -261,28 +289,43 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   // a column is set aside when it and every smaller column (ties by index) fit in tau^2 together
   for (int j = tid; j < nc; j += NT) {
     const double v = nrm2[j];
-    double below = 0.0;
-    for (int i = 0; i < nc; ++i) {
-      const double w = nrm2[i];
-      if (w < v || (w == v && i <= j)) below += w;
+    double b[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // eight independent partial sums
+    for (int i0 = 0; i0 < nc; i0 += 8) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q;
+        const double w = nrm2[i < nc ? i : 0];
+        if (i < nc && (w < v || (w == v && i <= j))) b[q] += w;
+      }
     }
+    const double below = ((b[0] + b[1]) + (b[2] + b[3])) + ((b[4] + b[5]) + (b[6] + b[7]));
     perm[j] = ((below <= tau2 && tau2 > 0.0) || v == 0.0) ? 0 : 1;
   }
   __syncthreads();
-  if (tid == 0) {
-    int k = 0, mx = -1;
-    double e = 0.0;
-    for (int j = 0; j < nc; ++j) {
-      if (perm[j]) {
-        act[k++] = j;
-        mx = j;
-      } else {
-        e += nrm2[j];
-      }
+  // active columns in increasing order (ballot prefix counts), the largest active index and
+  // the energy set aside (nc <= MAXC = NT: one column per thread)
+  {
+    const bool on = tid < nc && perm[tid] != 0;
+    const unsigned long long bal = __ballot(on);
+    const int below_in_wave = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) {
+      wcount[wave] = __popcll(bal);
+      wmax[wave] = bal ? 64 * wave + 63 - __clzll(bal) : -1;   // largest active column of the wave
     }
-    kact = k;
-    edrop = e;
-    lenact = (tall && tk.upper) ? (mx + 1) : N;
+    const double dropped = block_sum((tid < nc && !on) ? nrm2[tid] : 0.0, red);   // (contains barriers)
+    int off = 0;
+    for (int w = 0; w < wave; ++w) off += wcount[w];
+    if (on) act[off + below_in_wave] = tid;
+    if (tid == 0) {
+      int k = 0, mx = -1;
+      for (int w = 0; w < NW; ++w) {
+        k += wcount[w];
+        mx = wmax[w] > mx ? wmax[w] : mx;
+      }
+      kact = k;
+      edrop = dropped;
+      lenact = (tall && tk.upper) ? (mx + 1) : N;
+    }
   }
   __syncthreads();
   const int k = kact, len = lenact > 0 ? lenact : 1;
@@ -342,8 +385,8 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
     tk.sigma[rk] = sj;
   }
   __syncthreads();
+  for (int i = k + tid; i < nc; i += NT) tk.sigma[i] = 0.0;
   if (tid == 0) {
-    for (int i = k; i < nc; ++i) tk.sigma[i] = 0.0;
     const double eps = tk.delta_scaled * (*tk.norm);
     const double eps2 = eps * eps;
     int t = k > 0 ? k : 1;
@@ -368,6 +411,16 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   for (int a = tid; a < k; a += NT) nrm2[act[a]] = (double)a;
   __syncthreads();
   const bool degenerate = (k == 0);
+  // rows [0, len) of a square R staged in LDS beside A when they fit (W^T reads each of them t times)
+  double* Rs = nullptr;
+  if (tall && in_lds && (int64_t)lda * k + (int64_t)len * N <= LDS_DOUBLES) {
+    Rs = svd_lds + (int64_t)lda * k;
+    for (int idx = tid; idx < len * N; idx += NT) {
+      const int row = idx / N, col = idx - row * N;
+      Rs[idx] = aval(row, col);
+    }
+    __syncthreads();
+  }
   // W^T: ncol x t
   for (int64_t idx = tid; idx < (int64_t)N * t; idx += NT) {
     const int col = (int)(idx / t), i = (int)(idx - (int64_t)col * t);
@@ -381,7 +434,20 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
           const double* aj = A + (int64_t)j * lda;
           const int rmax = (tk.upper && col + 1 < len) ? col + 1 : len;   // R(row, col) = 0 below the diagonal
           double acc = 0.0;
-          for (int row = 0; row < rmax; ++row) acc += aj[row] * aval(row, col);
+          if (Rs) {
+            double a4[4] = {0.0, 0.0, 0.0, 0.0};   // four independent partial sums
+            for (int r0 = 0; r0 < rmax; r0 += 4) {
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                const int row = r0 + q < rmax ? r0 + q : 0;
+                const double term = aj[row] * Rs[row * N + col];
+                a4[q] += (r0 + q < rmax) ? term : 0.0;
+              }
+            }
+            acc = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+          } else {
+            for (int row = 0; row < rmax; ++row) acc += aj[row] * aval(row, col);
+          }
           v = acc / s;
         }
       } else {
