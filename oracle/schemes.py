@@ -2,8 +2,9 @@
 
 Literal transcriptions, in the paper's order and notation, of Section 3
 "Orthogonalization schemes": TT-CGS (Algorithm 1), TT-MGS (Algorithm 2),
-TT-CGS2 (Algorithm 3), TT-MGS2 (Algorithm 4) and TT-Gram (Algorithm 5), plus
-the loss of orthogonality of Section 3.4, equation (LOO).
+TT-CGS2 (Algorithm 3), TT-MGS2 (Algorithm 4), TT-Gram (Algorithm 5) and
+TT-Householder (Algorithms 6-8, Section 3.3), plus the loss of orthogonality
+of Section 3.4, equation (LOO).
 
 Inputs are lists of lazy sums ``[(coef, cores), ...]`` (a plain TT-vector is a
 one-term sum).  Sums are materialised before every dot product and rounding,
@@ -17,7 +18,16 @@ Readings taken where the paper is loose:
     (the equation of Section 3.2; the algorithm's R^{-1}(i, j) would read the
     zero lower triangle) and q_i is not renormalised after rounding;
   * the Gram matrix counts as numerically singular (Cholesky undefined, the
-    remark of Section 3.2) when a pivot L_jj^2 falls to m u G_jj or below.
+    remark of Section 3.2) when a pivot L_jj^2 falls to m u G_jj or below;
+  * TT-Householder: the canonical basis vector e_i is the rank-one TT-vector
+    of the multi-index phi(i), first index varying fastest (Section 3.3);
+    the diagonal entry takes the stable sign of the matrix construction,
+    R(i,i) = -s sqrt(||a||^2 - sum_{j<i} R(j,i)^2) with s = +1 when
+    <a, e_i> > 0 and -1 otherwise, so that the i-th entry of the Householder
+    vector is <a, e_i> + s gamma (the TTH-vec listing prints the opposite,
+    cancelling sign); the normalisation divides by the norm of the rounded
+    vector w; the input of the first Householder vector is a_1 as given
+    (not rounded), so one call takes 4m - 1 roundings (Table 1 counts 4m).
 """
 from __future__ import annotations
 
@@ -28,14 +38,19 @@ import scipy.linalg as sla
 
 from .tt import tt_sum, tt_dot, tt_norm, tt_round, tt_scale, tt_ranks, RoundLog
 
-__all__ = ["OrthoResult", "cgs", "mgs", "cgs2", "mgs2", "gram", "orthogonalize",
-           "loo_curve", "gram_of", "SCHEMES", "GramBreakdown"]
+__all__ = ["OrthoResult", "cgs", "mgs", "cgs2", "mgs2", "gram", "householder", "orthogonalize",
+           "loo_curve", "gram_of", "SCHEMES", "GramBreakdown", "HouseholderBreakdown", "canonical_index",
+           "canonical_tt", "tth_vec", "apply_h_vec"]
 
 SCHEMES = ("cgs", "mgs", "cgs2", "mgs2", "gram")
 
 
 class GramBreakdown(RuntimeError):
     """The Gram matrix is numerically not positive definite (Section 3.2 remark)."""
+
+
+class HouseholderBreakdown(RuntimeError):
+    """A vector to reflect has no component outside the span of the earlier canonical vectors."""
 
 
 @dataclass
@@ -46,6 +61,7 @@ class OrthoResult:
     pre_ranks: list = field(default_factory=list)    # ranks of each rounded vector before rounding
     post_ranks: list = field(default_factory=list)   # ranks after rounding
     logs: list = field(default_factory=list)
+    U: list = field(default_factory=list)            # Householder TT-vectors (TT-Householder only)
 
 
 def _as_sum(a):
@@ -174,8 +190,92 @@ def gram(A, delta):
     return res
 
 
+def canonical_index(i, ns):
+    """phi(i): the multi-index (i_1, ..., i_d) of the 1-based linear index i, the
+    inverse of psi(i_1, ..., i_d) = i_1 + sum_a (i_a - 1) prod_{b<a} n_b (Section 3.3)."""
+    rest = i - 1
+    idx = []
+    for n in ns:
+        idx.append(rest % n + 1)
+        rest //= n
+    if rest:
+        raise ValueError(f"canonical index {i} exceeds the tensor size")
+    return tuple(idx)
+
+
+def canonical_tt(i, ns):
+    """e_i = e_{i_1} x ... x e_{i_d} with (i_1, ..., i_d) = phi(i): a TT-vector of rank one."""
+    cores = []
+    for n, ik in zip(ns, canonical_index(i, ns)):
+        c = np.zeros((1, n, 1))
+        c[0, ik - 1, 0] = 1.0
+        cores.append(c)
+    return cores
+
+
+def tth_vec(a, F, delta, res):
+    """Householder TT-vector u and the first i entries r of a column of R (Algorithm 6).
+
+    The components of a along f_1..f_{i-1} are removed and the result rounded;
+    then the i-th component is replaced by r(i) = -s sqrt(||a||^2 - sum r(j)^2)
+    (stable sign, module docstring), rounded again and normalised.
+    """
+    i = len(F)
+    r = np.zeros(i)
+    s = 0.0
+    terms = [(1.0, a)]
+    for j in range(i - 1):
+        r[j] = tt_dot(a, F[j])
+        s = s + r[j] ** 2
+        terms.append((-r[j], F[j]))
+    w = _round(res, terms, delta)
+    gamma2 = tt_dot(a, a) - s
+    if not gamma2 > 0.0:
+        raise HouseholderBreakdown(f"no component left outside span(e_1..e_{i - 1})")
+    sign = 1.0 if tt_dot(a, F[i - 1]) > 0.0 else -1.0
+    r[i - 1] = -sign * np.sqrt(gamma2)
+    w = _round(res, [(1.0, w), (-r[i - 1], F[i - 1])], delta)
+    nw = tt_norm(w)
+    if not nw > 0.0:
+        raise HouseholderBreakdown("zero Householder vector")
+    return tt_scale(1.0 / nw, w), r
+
+
+def apply_h_vec(terms, u):
+    """b = a - 2 <a, u> u (Algorithm 7) on a lazy sum: one term is appended."""
+    a = tt_sum(terms)
+    return list(terms) + [(-2.0 * tt_dot(a, u), u)]
+
+
+def householder(A, delta):
+    """TT-Householder (Algorithm 8): Householder TT-vectors u_i against the
+    canonical basis, R column by column, then q_i = H_1 ... H_i e_i rounded."""
+    A = [_as_sum(a) for a in A]
+    m = len(A)
+    ns = [c.shape[1] for c in A[0][0][1]]
+    E = [canonical_tt(i, ns) for i in range(1, m + 1)]
+    R = np.zeros((m, m))
+    res = OrthoResult(Q=[], R=R)
+    At = [list(a) for a in A]               # the running a~_j as lazy sums
+    w = tt_sum(At[0])
+    for i in range(m):
+        u, r = tth_vec(w, E[:i + 1], delta, res)
+        R[:i + 1, i] = r
+        res.U.append(u)
+        for j in range(i, m):
+            At[j] = apply_h_vec(At[j], u)
+        if i < m - 1:
+            w = _round(res, At[i + 1], delta)
+    for i in range(m):
+        terms = [(1.0, E[i])]
+        for j in range(i, -1, -1):
+            terms = apply_h_vec(terms, res.U[j])
+        res.Q.append(_round(res, terms, delta))
+    return res
+
+
 def orthogonalize(scheme, A, delta):
-    fn = {"cgs": cgs, "mgs": mgs, "cgs2": cgs2, "mgs2": mgs2, "gram": gram}[scheme]
+    fn = {"cgs": cgs, "mgs": mgs, "cgs2": cgs2, "mgs2": mgs2, "gram": gram, "householder": householder}[scheme]
     return fn(A, delta)
 
 

@@ -1,0 +1,116 @@
+"""Pins of the oracle's TT-Householder (Algorithms 6-8, Section 3.3).
+
+Independent references:
+  * LAPACK's Householder QR (numpy.linalg.qr) of the vectorised inputs.  As the
+    rounding accuracy goes to zero the TT scheme is the matrix Householder QR
+    against the canonical basis taken in psi order (first index fastest), with
+    the stable sign of the matrix construction, which is also LAPACK's; so R,
+    signs included, and the first m columns of Q agree.  A wrong index order, the
+    cancelling sign or a dropped projection term each change R.
+  * Brute force on the index map: psi(phi(i)) = i and the dense form of e_i.
+  * Invariants: 4m - 1 roundings for one call, A = Q R up to O(delta), and a
+    loss of orthogonality of order delta (the Householder bound of Section 3.4
+    with the rounding accuracy in place of the unit round-off).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import tt_full
+from inputs import conditioned_inputs
+
+
+def f_order_columns(vectors):
+    """Vectorise with the first index varying fastest: entry psi(i_1..i_d) - 1."""
+    cols = []
+    for v in vectors:
+        if isinstance(v, list) and v and isinstance(v[0], tuple):
+            v = oracle.tt_sum(v)
+        cols.append(tt_full(v).ravel(order="F"))
+    return np.stack(cols, axis=1)
+
+
+def psi(idx, ns):
+    i, stride = 1, 1
+    for ik, n in zip(idx, ns):
+        i += (ik - 1) * stride
+        stride *= n
+    return i
+
+
+def test_canonical_index_inverts_psi_and_e_is_a_unit_vector():
+    ns = (3, 4, 2)
+    total = math.prod(ns)
+    for i in range(1, total + 1):
+        idx = oracle.canonical_index(i, ns)
+        assert psi(idx, ns) == i
+        e = f_order_columns([oracle.canonical_tt(i, ns)])[:, 0]
+        ref = np.zeros(total)
+        ref[i - 1] = 1.0
+        assert np.array_equal(e, ref)
+    with pytest.raises(ValueError):
+        oracle.canonical_index(total + 1, ns)
+
+
+@pytest.mark.parametrize("seed,m,d,n,kappa", [(71, 5, 3, 4, 1e4), (72, 6, 2, 4, 1e2), (73, 3, 1, 5, 10.0)])
+def test_matches_lapack_householder_qr(seed, m, d, n, kappa):
+    X, _, _ = conditioned_inputs(seed, m, d, n, 2, kappa)
+    res = oracle.householder(X, 1e-14)
+    A = f_order_columns(X)
+    Qd, Rd = np.linalg.qr(A)
+    tol = 1e-11 * math.sqrt(kappa)
+    assert np.allclose(res.R, Rd, rtol=0, atol=tol)
+    assert np.allclose(f_order_columns(res.Q), Qd, rtol=0, atol=tol)
+
+
+def test_matches_lapack_with_unequal_modes():
+    # Random lazy sums on modes (3, 4, 2): the index order matters here.
+    from paper_2211_08770_amd import synth
+    g = synth.rng(74)
+    ns = [3, 4, 2]
+    X = [[(1.0, synth.random_tt(g, ns, [1, 2, 2, 1])), (0.5, synth.random_tt(g, ns, [1, 1, 2, 1]))]
+         for _ in range(5)]
+    res = oracle.householder(X, 1e-14)
+    Qd, Rd = np.linalg.qr(f_order_columns(X))
+    assert np.allclose(res.R, Rd, rtol=0, atol=1e-10)
+    assert np.allclose(f_order_columns(res.Q), Qd, rtol=0, atol=1e-10)
+
+
+def test_round_count_and_householder_vectors():
+    X, _, _ = conditioned_inputs(75, 5, 3, 4, 2, 1e2)
+    res = oracle.householder(X, 1e-8)
+    assert res.rounds == 4 * 5 - 1
+    A = f_order_columns(X)
+    U = f_order_columns(res.U)
+    for i in range(5):
+        u = U[:, i]
+        assert abs(np.linalg.norm(u) - 1.0) < 1e-12
+        assert np.allclose(u[:i], 0.0, atol=1e-7)          # zero on e_1..e_{i-1} up to delta
+    # the reflections take a_1 to R(1,1) e_1
+    h1 = A[:, 0] - 2.0 * (U[:, 0] @ A[:, 0]) * U[:, 0]
+    ref = np.zeros_like(h1)
+    ref[0] = res.R[0, 0]
+    assert np.allclose(h1, ref, atol=1e-7)
+
+
+def test_residual_and_loo_of_order_delta():
+    delta = 1e-6
+    X, _, _ = conditioned_inputs(76, 6, 3, 4, 2, 1e6)
+    res = oracle.householder(X, delta)
+    A = f_order_columns(X)
+    Q = f_order_columns(res.Q)
+    for i in range(6):
+        r = A[:, i] - Q[:, : i + 1] @ res.R[: i + 1, i]
+        assert np.linalg.norm(r) <= 20 * (i + 1) * delta * np.linalg.norm(A[:, i])
+    assert np.allclose(np.tril(res.R, -1), 0)
+    loo = oracle.loo_curve(res.Q)
+    assert np.all(loo <= 20 * np.arange(1, 7) * delta)
+
+
+def test_breakdown_on_dependent_input():
+    X, _, _ = conditioned_inputs(77, 3, 3, 4, 2, 10.0)
+    X[2] = [(c, [a.copy() for a in t]) for c, t in X[0]]          # a_3 = a_1
+    with pytest.raises(oracle.HouseholderBreakdown):
+        oracle.householder(X, 1e-10)

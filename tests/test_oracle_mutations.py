@@ -1,9 +1,11 @@
 """Planted mistakes in copies of oracle routines must be caught by the pins.
 
 Each mutant is a plausible slip (a transposed operand, a misplaced
-coefficient, a wrong threshold, a strict instead of non-strict test); the
-same independent reference used by the pins has to reject it.  The real
-oracle is never modified.
+coefficient, a wrong threshold, a strict instead of non-strict test, the
+cancelling Householder sign, the wrong canonical index order); the same
+independent reference used by the pins has to reject it.  The oracle's files
+are never modified: a mutant is a separate function, swapped in for one test
+at most.
 """
 import math
 
@@ -77,3 +79,49 @@ def test_eckart_young_pin_catches_wrong_threshold():
     best = (U[:, :2] * sig[:2]) @ V[:, :2].T
     assert np.allclose(tt_full(oracle.tt_round(x, delta)), best, atol=1e-13)
     assert not np.allclose(tt_full(_round_wrong_threshold(x, delta)), best, atol=1e-6)
+
+
+def _tth_vec_cancelling_sign(a, F, delta, res):
+    # slip: the sign printed in the TTH-vec listing, r(i) = +s gamma
+    i = len(F)
+    r = np.zeros(i)
+    s = 0.0
+    terms = [(1.0, a)]
+    for j in range(i - 1):
+        r[j] = oracle.tt_dot(a, F[j])
+        s = s + r[j] ** 2
+        terms.append((-r[j], F[j]))
+    w = oracle.tt_round(oracle.tt_sum(terms), delta)
+    sign = 1.0 if oracle.tt_dot(a, F[i - 1]) > 0.0 else -1.0
+    r[i - 1] = sign * math.sqrt(oracle.tt_dot(a, a) - s)
+    w = oracle.tt_round(oracle.tt_sum([(1.0, w), (-r[i - 1], F[i - 1])]), delta)
+    return oracle.tt_scale(1.0 / oracle.tt_norm(w), w), r
+
+
+def _canonical_index_last_fastest(i, ns):
+    rest = i - 1
+    idx = []
+    for n in reversed(ns):                                      # slip: last index fastest
+        idx.append(rest % n + 1)
+        rest //= n
+    return tuple(reversed(idx))
+
+
+def _householder_vs_lapack(monkeypatch, name, mutant):
+    import oracle.schemes as sch
+    g = synth.rng(63)
+    ns = [3, 4, 2]
+    X = [[(1.0, synth.random_tt(g, ns, [1, 2, 2, 1]))] for _ in range(4)]
+    A = np.stack([tt_full(oracle.tt_sum(x)).ravel(order="F") for x in X], axis=1)
+    _, Rd = np.linalg.qr(A)
+    assert np.allclose(oracle.householder(X, 1e-14).R, Rd, atol=1e-10)
+    monkeypatch.setattr(sch, name, mutant)
+    return np.allclose(sch.householder(X, 1e-14).R, Rd, atol=1e-6)
+
+
+def test_lapack_pin_catches_cancelling_householder_sign(monkeypatch):
+    assert not _householder_vs_lapack(monkeypatch, "tth_vec", _tth_vec_cancelling_sign)
+
+
+def test_lapack_pin_catches_reversed_canonical_order(monkeypatch):
+    assert not _householder_vs_lapack(monkeypatch, "canonical_index", _canonical_index_last_fastest)
