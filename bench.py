@@ -156,6 +156,69 @@ def run_batched(tt, torch, reps=3):
             "workload": "256 uneven jobs: d~U{4..10}, n~U{16,32,64}, rank~U{8..128}, N(0,1) FP32 cores, delta=1e-5"}
 
 
+HH_WORKLOAD = dict(seed=10000, m=20, d=4, n=8, r=3, kappa=1e6, delta=1e-6)
+HH_DESC = ("TT-Householder of m=20 TT-vectors x_k = sum_{j<=k} c_kj t_j (private copies), t_j random rank-3 TTs "
+           "of order 4, n=8, cond(Gram(x)) = 1e6, delta=1e-6, FP64")
+
+
+def run_householder(tt, torch, reps=5):
+    """TT-Householder (Algorithms 6-8) on the m=20 order-4 workload; value in orthogonalizations/s."""
+    from paper_2211_08770_amd import synth
+    w = HH_WORKLOAD
+    t = synth.conditioned_terms(w["seed"], w["m"], w["d"], w["n"], w["r"])
+    dev = [tt.TT.from_cores(c, device="cuda", dtype=torch.float64) for c in t]
+    m = w["m"]
+    Gt = tt.dot_batched([(dev[i], dev[j]) for i in range(m) for j in range(m)]).reshape(m, m)
+    cm, _ = synth.mixing_coefficients(0.5 * (Gt + Gt.T), w["seed"], w["kappa"])
+    A = [[(float(cm[k, j]), tt.TT.from_cores(t[j], device="cuda", dtype=torch.float64)) for j in range(k + 1)]
+         for k in range(m)]
+    Q, R, loo, st = tt.orthogonalize("householder", A, w["delta"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        tt.orthogonalize("householder", A, w["delta"], with_loo=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx = tt._ctx()
+    ctx.lib.tt_ctx_set_profiling.argtypes = [C.c_void_p, C.c_int]
+    ctx.lib.tt_ctx_set_profiling(ctx.h, 1)
+    tt.orthogonalize("householder", A, w["delta"], with_loo=False)
+    torch.cuda.synchronize()
+    prof = profile_arrays(ctx)
+    ctx.lib.tt_ctx_set_profiling(ctx.h, 0)
+    busy = sum(v["ms"] for v in prof.values())
+    return {"value": round(1.0 / dt, 3), "unit": "orthogonalizations/s", "ms_per_call": round(1e3 * dt, 3),
+            "device_busy_ms": round(busy, 3), "rounds": st["rounds"], "max_loo": float(max(loo)),
+            "max_pre_rank": st["max_pre_rank"], "max_post_rank": st["max_post_rank"],
+            "roofline": roofline_of(prof), "workload": HH_DESC}
+
+
+def cpu_baseline_householder(reps_seconds=10.0):
+    """The oracle's TT-Householder on the same workload (its own FP64 Gram matrix of the generators)."""
+    import numpy as np
+    import oracle
+    from paper_2211_08770_amd import synth
+    w = HH_WORKLOAD
+    t = synth.conditioned_terms(w["seed"], w["m"], w["d"], w["n"], w["r"])
+    cm, _ = synth.mixing_coefficients(oracle.gram_of(t), w["seed"], w["kappa"])
+    A = [[(float(cm[k, j]), [c.copy() for c in t[j]]) for j in range(k + 1)] for k in range(w["m"])]
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.householder(A, w["delta"])
+        n += 1
+        if time.perf_counter() - t0 >= reps_seconds:
+            break
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return {"value": n / dt, "unit": "orthogonalizations/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} FP64 NumPy/LAPACK TT-Householder calls on the same workload ({dt:.1f} s)"}
+
+
 def run_serving(torch, qps=100.0, nreq=150):
     """Poisson serving trace: MGS2 steps of 64 simulated TT-GMRES solvers against resident bases."""
     from paper_2211_08770_amd import serve
@@ -244,8 +307,10 @@ def main():
     if not args.headline_only:
         line["batched_uneven"] = run_batched(tt, torch)
         line["serving"] = run_serving(torch)
+        line["householder"] = run_householder(tt, torch)
     if not args.no_cpu and not args.headline_only:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        line["householder"]["cpu_baseline"] = cpu_baseline_householder()
     print(json.dumps(line))
 
 

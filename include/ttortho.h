@@ -56,7 +56,7 @@ typedef enum {
 
 typedef enum { TT_F64 = 0, TT_F32 = 1 } tt_dtype;
 
-typedef enum { TT_CGS = 0, TT_MGS = 1, TT_CGS2 = 2, TT_MGS2 = 3, TT_GRAM = 4 } tt_scheme;
+typedef enum { TT_CGS = 0, TT_MGS = 1, TT_CGS2 = 2, TT_MGS2 = 3, TT_GRAM = 4, TT_HOUSEHOLDER = 5 } tt_scheme;
 
 /* One TT-vector (Section 2, TT representation).  Host struct, device data. */
 typedef struct tt_vec {
@@ -171,14 +171,21 @@ int64_t tt_round_workspace_bytes(const tt_sum* x);
 
 /* Orthogonalize m TT-vectors a[0..m-1] (each a lazy sum) with rounding
  * accuracy delta (Section 3):  TT_CGS Algorithm 1, TT_MGS Algorithm 2,
- * TT_CGS2 Algorithm 3, TT_MGS2 Algorithm 4, TT_GRAM Algorithm 5.
+ * TT_CGS2 Algorithm 3, TT_MGS2 Algorithm 4, TT_GRAM Algorithm 5,
+ * TT_HOUSEHOLDER Algorithms 6-8 (Section 3.3: Householder TT-vectors against
+ * the canonical basis e_i = e_{i_1} x ... x e_{i_d}, first index fastest; the
+ * diagonal of R takes the stable sign, R(i,i) = -sign(<a~_i, e_i>) times the
+ * remaining norm; 4m - 1 roundings; m must not exceed prod n_k; the
+ * Householder vectors live in the workspace, whose required size the library
+ * reports through TT_ECAPACITY before any work starts).
  * Outputs: q[0..m-1] (caller buffers with capacity; r written), R (HOST,
  * m*m column-major, upper triangular, A ~ Q R: column i holds the
  * projections of a_i), loo (HOST [m], nullable: ||I_k - Q_k^T Q_k||_2 for
  * k = 1..m), stats (nullable).  rank_guard > 0 stops with TT_EGUARD when a
  * vector to be rounded would exceed that bond rank; q and the columns of R of
- * the stats->m_reached completed vectors are then valid.  Errors:
- * TT_ENOTSPD (Gram: Cholesky fails), TT_EBREAKDOWN (||p|| = 0). */
+ * the stats->m_reached completed vectors are then valid (TT_HOUSEHOLDER forms
+ * every q at the end, so none).  Errors: TT_ENOTSPD (Gram: Cholesky fails),
+ * TT_EBREAKDOWN (||p|| = 0; Householder: a~_i in the span of e_0..e_{i-1}). */
 tt_status tt_orthogonalize(tt_ctx* ctx, tt_scheme scheme, int32_t m, const tt_sum* a, double delta,
                            int64_t rank_guard, tt_vec* q, double* R, double* loo,
                            tt_ortho_stats* stats);

@@ -775,6 +775,217 @@ tt_status loo_from_gram(tt_ctx* c, const double* Gq, int m, double* loo_host) {
   return TT_OK;
 }
 
+// A lazy sum under construction: coefficients and components on the host.
+struct LazySum {
+  std::vector<double> coef;
+  std::vector<tt_vec> comp;
+  void add(double a, const tt_vec& v) {
+    coef.push_back(a);
+    comp.push_back(v);
+  }
+  tt_sum view() const { return tt_sum{(int32_t)comp.size(), coef.data(), comp.data()}; }
+};
+
+// Packed size of a TT of shape `shape` whose bond ranks are b (already capped).
+int64_t packed_size(const tt_vec& shape, const int64_t* b) {
+  int64_t s = 0;
+  for (int k = 0; k < shape.d; ++k) s += b[k] * shape.n[k] * b[k + 1];
+  return s;
+}
+
+// TT-Householder (Section 3.3, Algorithms 6-8).  For i = 0..m-1: the Householder
+// TT-vector u_i of the (rounded) running vector w against e_0..e_i (two
+// roundings), column i of R, the reflection of the later a~_j by u_i (a term
+// appended to their lazy sums), and w = round(a~_{i+1}).  Then q_i = H_0..H_i e_i,
+// the reflections applied in reverse order to all q_i at once, and the m final
+// roundings in one batch.  The reflection of a~_i by its own u_i is skipped: the
+// algorithm never reads that result.  The u_i, two slots for w and one for the
+// first rounding of each u live in the workspace at sizes bounded before any
+// work starts (bond ranks of a rounded sum are at most those of the sum and the
+// rank caps).
+tt_status ortho_householder(tt_ctx* c, int m, const tt_sum* a, double delta, int64_t rank_guard, tt_vec* q,
+                            double* Rdev, double* R, double* loo, double* Gq, tt_ortho_stats& st) {
+  const tt_vec& s0 = a[0].comp[0];
+  const int d = s0.d;
+  const size_t esz = elt_size(s0.dtype);
+  hipError_t e;
+  tt_status s;
+  {
+    // the canonical basis must have m elements
+    int64_t total = 1;
+    for (int k = 0; k < d && total < m; ++k) total = std::min<int64_t>(total * s0.n[k], (int64_t)m);
+    if (total < m) return fail(c, TT_EINVAL, "householder: m exceeds the number of tensor entries");
+  }
+  int64_t caps[TT_MAXD + 1];
+  rank_caps(s0, caps);
+  auto cap_of = [&](int64_t* b) {
+    for (int k = 0; k <= d; ++k) {
+      b[k] = std::min(b[k], caps[k]);
+      if (rank_guard > 0) b[k] = std::min(b[k], rank_guard);
+    }
+    b[0] = b[d] = 1;
+  };
+  // a-priori bond bounds: w_0 = a_0; w_i <= a_i + sum_{l<i} u_l; first rounding <= w_i + i; u_i <= that + 1
+  std::vector<int64_t> bu((size_t)m * (d + 1)), sumu(d + 1, 0);
+  int64_t wmax = 0, w1max = 0;
+  std::vector<int64_t> uoff(m + 1, 0);
+  for (int i = 0; i < m; ++i) {
+    int64_t bw[TT_MAXD + 1], b1[TT_MAXD + 1];
+    for (int k = 0; k <= d; ++k) {
+      int64_t ra = 0;
+      for (int cc = 0; cc < a[i].ncomp; ++cc) ra += a[i].comp[cc].r[k];
+      bw[k] = ra + sumu[k];
+    }
+    cap_of(bw);
+    for (int k = 0; k <= d; ++k) b1[k] = bw[k] + i;
+    cap_of(b1);
+    int64_t* u = &bu[(size_t)i * (d + 1)];
+    for (int k = 0; k <= d; ++k) u[k] = b1[k] + 1;
+    cap_of(u);
+    for (int k = 0; k <= d; ++k) sumu[k] += u[k];
+    if (i > 0) wmax = std::max(wmax, packed_size(s0, bw));
+    w1max = std::max(w1max, packed_size(s0, b1));
+    uoff[i + 1] = uoff[i] + ((packed_size(s0, u) * (int64_t)esz + 255) & ~(int64_t)255) / (int64_t)esz;
+  }
+  int64_t S = 0;
+  for (int k = 0; k < d; ++k) S += s0.n[k];
+  char* Ebuf = (char*)ws_alloc(c, (size_t)m * S * esz);
+  char* Ubuf = (char*)ws_alloc(c, (size_t)uoff[m] * esz);
+  char* Wbuf[2] = {(char*)ws_alloc(c, (size_t)std::max<int64_t>(wmax, 1) * esz),
+                   (char*)ws_alloc(c, (size_t)std::max<int64_t>(wmax, 1) * esz)};
+  char* W1buf = (char*)ws_alloc(c, (size_t)w1max * esz);
+  if (!Ebuf || !Ubuf || !Wbuf[0] || !Wbuf[1] || !W1buf)
+    return fail(c, TT_ECAPACITY, "workspace too small for the Householder vectors: need " + std::to_string(c->required));
+  const size_t top = c->ws_off;
+  const int64_t* dn = (const int64_t*)upload_bytes(c, s0.n, (size_t)d * 8);
+  double* dots = (double*)dev_scratch(c, (size_t)(m + 1) * 8);
+  double* coefd = (double*)dev_scratch(c, (size_t)(m + 1) * 8);
+  double* nrm = (double*)dev_scratch(c, 8);
+  if (!dn || !dots || !coefd || !nrm) return fail(c, TT_ENOMEM, "householder buffers");
+  if ((e = launch_canonical(s0.dtype, Ebuf, dn, d, S, 0, m, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "canonical basis");
+  auto make_vec = [&](void* data, int64_t capacity) {
+    tt_vec v = s0;
+    for (int k = 0; k <= d; ++k) v.r[k] = 1;
+    v.data = data;
+    v.capacity = capacity;
+    return v;
+  };
+  std::vector<tt_vec> E(m), U(m);
+  for (int i = 0; i < m; ++i) E[i] = make_vec(Ebuf + (size_t)i * S * esz, S);
+  static const double one = 1.0;
+  std::vector<LazySum> At(m);   // a~_j
+  for (int j = 0; j < m; ++j)
+    for (int cc = 0; cc < a[j].ncomp; ++cc) At[j].add(a[j].coef[cc], a[j].comp[cc]);
+
+  // one rounding of `sum` into `out`, with the rank guard and the statistics
+  auto round_into = [&](const tt_sum& sum, tt_vec* out) -> tt_status {
+    RJob probe;
+    make_job(c, &sum, delta, 0, nullptr, probe);
+    const int64_t pre = max_bond(probe.R, d);
+    st.max_pre_rank = (int32_t)std::max<int64_t>(st.max_pre_rank, pre);
+    if (rank_guard > 0 && pre > rank_guard)
+      return fail(c, TT_EGUARD, "pre-round rank " + std::to_string(pre) + " exceeds the guard");
+    tt_status rs = round_one(c, &sum, delta, out);
+    if (rs != TT_OK) return rs;
+    ++st.rounds;
+    st.max_post_rank = (int32_t)std::max<int64_t>(st.max_post_rank, max_bond(out->r, d));
+    return TT_OK;
+  };
+
+  tt_vec w;                 // the running vector fed to the next Householder TT-vector
+  tt_sum wsum = a[0];       // w_0 = a_0 as given
+  std::vector<double> hc(m + 1);
+  for (int i = 0; i < m; ++i) {
+    c->ws_off = top;
+    // dots <w, e_j> (j <= i) and <w, w>, then column i of R
+    {
+      std::vector<tt_sum> xs(i + 2, wsum), ys(i + 2);
+      for (int j = 0; j <= i; ++j) ys[j] = tt_sum{1, &one, &E[j]};
+      ys[i + 1] = wsum;
+      if ((s = dot_pairs(c, i + 2, xs.data(), ys.data(), dots)) != TT_OK) return s;
+    }
+    if ((e = launch_hh_column(dots, i, Rdev + (size_t)i * m, coefd, c->stream)) != hipSuccess)
+      return hip_fail(c, e, "householder column");
+    if ((s = read_doubles(c, coefd, hc.data(), i + 1)) != TT_OK) return s;
+    if (!(hc[i] != 0.0) || !std::isfinite(hc[i]))
+      return fail(c, TT_EBREAKDOWN, "householder: vector " + std::to_string(i) + " lies in the span of the earlier ones");
+    // first rounding: w - sum_{j<i} R(j, i) e_j
+    LazySum p1;
+    for (int cc = 0; cc < wsum.ncomp; ++cc) p1.add(wsum.coef[cc], wsum.comp[cc]);
+    for (int j = 0; j < i; ++j) p1.add(hc[j], E[j]);
+    tt_vec w1 = make_vec(W1buf, w1max);
+    if ((s = round_into(p1.view(), &w1)) != TT_OK) return s;
+    // second rounding: w1 - R(i, i) e_i, normalised
+    U[i] = make_vec(Ubuf + (size_t)uoff[i] * esz, uoff[i + 1] - uoff[i]);
+    LazySum p2;
+    p2.add(1.0, w1);
+    p2.add(hc[i], E[i]);
+    if ((s = round_into(p2.view(), &U[i])) != TT_OK) return s;
+    int64_t off = 0;
+    for (int k = 0; k + 1 < d; ++k) off += U[i].r[k] * U[i].n[k] * U[i].r[k + 1];
+    const int64_t last = U[i].r[d - 1] * U[i].n[d - 1];
+    char* lastp = (char*)U[i].data + (size_t)off * esz;
+    if ((e = launch_sumsq(U[i].dtype, lastp, last, nrm, c->stream)) != hipSuccess) return hip_fail(c, e, "norm");
+    double hn = 0.0;
+    if ((s = read_doubles(c, nrm, &hn, 1)) != TT_OK) return s;
+    if (!(hn > 0.0) || !std::isfinite(hn))
+      return fail(c, TT_EBREAKDOWN, "householder: zero Householder vector at " + std::to_string(i));
+    if ((e = launch_scale(U[i].dtype, lastp, last, nrm, c->stream)) != hipSuccess) return hip_fail(c, e, "scale");
+    // reflect a~_j, j > i:  a~_j -= 2 <a~_j, u_i> u_i
+    const int nr = m - 1 - i;
+    if (nr > 0) {
+      std::vector<tt_sum> xs(nr), ys(nr, tt_sum{1, &one, &U[i]});
+      for (int j = 0; j < nr; ++j) xs[j] = At[i + 1 + j].view();
+      if ((s = dot_pairs(c, nr, xs.data(), ys.data(), dots)) != TT_OK) return s;
+      if ((e = launch_scale_vec(dots, -2.0, coefd, nr, c->stream)) != hipSuccess) return hip_fail(c, e, "reflect");
+      if ((s = read_doubles(c, coefd, hc.data(), nr)) != TT_OK) return s;
+      for (int j = 0; j < nr; ++j) At[i + 1 + j].add(hc[j], U[i]);
+      // w = round(a~_{i+1})
+      w = make_vec(Wbuf[(i + 1) & 1], wmax);
+      if ((s = round_into(At[i + 1].view(), &w)) != TT_OK) return s;
+      wsum = tt_sum{1, &one, &w};
+    }
+  }
+  // q_i = H_0 ... H_i e_i: reflections j = m-1..0 applied to every q_i with i >= j
+  c->ws_off = top;
+  std::vector<LazySum> Qs(m);
+  for (int i = 0; i < m; ++i) Qs[i].add(1.0, E[i]);
+  for (int j = m - 1; j >= 0; --j) {
+    const int nr = m - j;
+    std::vector<tt_sum> xs(nr), ys(nr, tt_sum{1, &one, &U[j]});
+    for (int t = 0; t < nr; ++t) xs[t] = Qs[j + t].view();
+    if ((s = dot_pairs(c, nr, xs.data(), ys.data(), dots)) != TT_OK) return s;
+    if ((e = launch_scale_vec(dots, -2.0, coefd, nr, c->stream)) != hipSuccess) return hip_fail(c, e, "reflect");
+    if ((s = read_doubles(c, coefd, hc.data(), nr)) != TT_OK) return s;
+    for (int t = 0; t < nr; ++t) Qs[j + t].add(hc[t], U[j]);
+  }
+  std::vector<tt_sum> qsums(m);
+  std::vector<RJob> jobs(m);
+  for (int i = 0; i < m; ++i) {
+    qsums[i] = Qs[i].view();
+    make_job(c, &qsums[i], delta, 0, &q[i], jobs[i]);
+    const int64_t pre = max_bond(jobs[i].R, d);
+    st.max_pre_rank = (int32_t)std::max<int64_t>(st.max_pre_rank, pre);
+    if (rank_guard > 0 && pre > rank_guard)
+      return fail(c, TT_EGUARD, "pre-round rank " + std::to_string(pre) + " of q exceeds the guard");
+  }
+  if ((s = round_jobs(c, jobs)) != TT_OK) return s;
+  for (auto& jb : jobs) {
+    if (jb.status != TT_OK) return fail(c, jb.status, "householder: output capacity of q");
+    st.max_post_rank = (int32_t)std::max<int64_t>(st.max_post_rank, max_bond(jb.out->r, d));
+  }
+  st.rounds += m;
+  st.m_reached = m;
+  if ((s = read_doubles(c, Rdev, R, (size_t)m * m)) != TT_OK) return s;
+  if (loo) {
+    for (int i = 0; i < m; ++i)
+      if ((s = gram_row(c, i, m, q, Gq)) != TT_OK) return s;
+    if ((s = loo_from_gram(c, Gq, m, loo)) != TT_OK) return s;
+  }
+  return TT_OK;
+}
+
 }  // namespace
 
 tt_status tt_loo(tt_ctx* c, int32_t m, const tt_vec* q, double* loo, double* gram) {
@@ -796,7 +1007,7 @@ tt_status tt_loo(tt_ctx* c, int32_t m, const tt_vec* q, double* loo, double* gra
 tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum* a, double delta, int64_t rank_guard,
                            tt_vec* q, double* R, double* loo, tt_ortho_stats* stats) {
   if (!c || m < 1 || !a || !q || !R) return fail(c, TT_EINVAL, "orthogonalize: bad arguments");
-  if (scheme < TT_CGS || scheme > TT_GRAM) return fail(c, TT_EINVAL, "orthogonalize: unknown scheme");
+  if (scheme < TT_CGS || scheme > TT_HOUSEHOLDER) return fail(c, TT_EINVAL, "orthogonalize: unknown scheme");
   if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(c, TT_EINVAL, "orthogonalize: delta must be >= 0");
   tt_status s;
   for (int i = 0; i < m; ++i) {
@@ -829,6 +1040,8 @@ tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum*
     if (stats) *stats = st;
     return rs;
   };
+
+  if (scheme == TT_HOUSEHOLDER) return finish(ortho_householder(c, m, a, delta, rank_guard, q, R1, R, loo, Gq, st));
 
   if (scheme == TT_GRAM) {
     // G(i, j) = <a_i, a_j>  (one batched launch), Cholesky, R^{-1}

@@ -192,6 +192,13 @@ hipError_t launch_coef_batched(const CoefTask* d_tasks, int ntasks, hipStream_t 
 
 hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int i, double* r, double* neg,
                               hipStream_t s);
+// TT-Householder (Algorithms 6-8): canonical rank-one TT-vectors e_first..e_{first+count-1}
+// (S = sum_k n_k elements each, d_n on the device), column i of R with the
+// coefficients of the Householder sum, and out[j] = alpha * a[j].
+hipError_t launch_canonical(int dtype, void* out, const int64_t* d_n, int d, int64_t S, int64_t first, int count,
+                            hipStream_t s);
+hipError_t launch_hh_column(const double* dots, int i, double* Rcol, double* coef, hipStream_t s);
+hipError_t launch_scale_vec(const double* a, double alpha, double* out, int n, hipStream_t s);
 // out[j] = a[j] + b[j]
 hipError_t launch_add(const double* a, const double* b, double* out, int n, hipStream_t s);
 hipError_t launch_neg(const double* a, double* out, int n, hipStream_t s);

@@ -235,6 +235,59 @@ __global__ void k_coef_batched(const CoefTask* __restrict__ tasks, int ntasks) {
   }
 }
 
+// Canonical basis TT-vectors e_{first}, ..., e_{first+count-1} (0-based linear
+// indices; Section 3.3): rank-one cores holding a one at i_k of the multi-index
+// phi(i), first index varying fastest, zero elsewhere.  Vector v is stored at
+// out[v*S, v*S + S) with S = sum_k n_k, core k at offset sum_{l<k} n_l.
+template <typename T>
+__global__ void k_canonical(T* __restrict__ out, const int64_t* __restrict__ nn, int d, int64_t S, int64_t first,
+                            int count) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S * count) return;
+  const int64_t v = e / S, pos = e - v * S;
+  int64_t rest = first + v, off = 0;
+  T val = (T)0;
+  for (int k = 0; k < d; ++k) {
+    const int64_t n = nn[k];
+    const int64_t ik = rest % n;
+    rest /= n;
+    if (pos < off + n) {
+      val = (pos - off == ik) ? (T)1 : (T)0;
+      break;
+    }
+    off += n;
+  }
+  out[e] = val;
+}
+
+// Column i of R and the coefficients of the Householder sum (Algorithm 6) from
+// dots[j] = <a, e_j> (j <= i) and dots[i+1] = <a, a>:  R(j, i) = dots[j] for
+// j < i; R(i, i) = -s sqrt(<a, a> - sum_{j<i} dots[j]^2) with s = +1 when
+// dots[i] > 0 and -1 otherwise (the stable sign); coef[j] = -R(j, i), j <= i.
+// A remainder that is not positive (a in the span of e_0..e_{i-1}) gives
+// R(i, i) = 0, which the host reports as a breakdown.
+__global__ void k_hh_column(const double* __restrict__ dots, int i, double* __restrict__ Rcol,
+                            double* __restrict__ coef) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int j = 0; j < i; ++j) {
+    const double r = dots[j];
+    Rcol[j] = r;
+    coef[j] = -r;
+    s = s + r * r;
+  }
+  const double g2 = dots[i + 1] - s;
+  const double sign = dots[i] > 0.0 ? 1.0 : -1.0;
+  const double rii = g2 > 0.0 ? -sign * sqrt(g2) : 0.0;
+  Rcol[i] = rii;
+  coef[i] = -rii;
+}
+
+__global__ void k_scale_vec(const double* __restrict__ a, double alpha, double* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = alpha * a[i];
+}
+
 // Deterministic values in [-1, 1) from an integer hash of the index (synthetic
 // matrices for timing tile shapes; the values do not matter to the timing).
 template <typename T>
@@ -288,6 +341,29 @@ hipError_t launch_axpy(int dtype, const AxpyTask* d_tasks, int ntasks, int64_t m
 hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int i, double* r, double* neg,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_mgs_correct, dim3(1), dim3(64), 0, s, dots, Gq, ldg, i, r, neg);
+  return hipGetLastError();
+}
+
+hipError_t launch_canonical(int dtype, void* out, const int64_t* d_n, int d, int64_t S, int64_t first, int count,
+                            hipStream_t s) {
+  const int64_t total = S * count;
+  if (total <= 0) return hipSuccess;
+  const int blocks = (int)((total + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_canonical<double>, dim3(blocks), dim3(256), 0, s, (double*)out, d_n, d, S, first, count);
+  else
+    hipLaunchKernelGGL(k_canonical<float>, dim3(blocks), dim3(256), 0, s, (float*)out, d_n, d, S, first, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_hh_column(const double* dots, int i, double* Rcol, double* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_hh_column, dim3(1), dim3(64), 0, s, dots, i, Rcol, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_vec(const double* a, double alpha, double* out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_vec, dim3((n + 255) / 256), dim3(256), 0, s, a, alpha, out, n);
   return hipGetLastError();
 }
 

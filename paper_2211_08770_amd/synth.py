@@ -14,7 +14,10 @@ TT-ranks, number of vectors m, rounding accuracy delta):
   * ``uneven_jobs``        - independent rounding jobs with d in [4, 10],
     n in {16, 32, 64} and one internal rank R in [8, 128];
   * ``correlation_with_spectrum`` - a unit-diagonal SPD matrix with a
-    prescribed eigenvalue set (Davies-Higham, via SciPy).
+    prescribed eigenvalue set (Davies-Higham, via SciPy);
+  * ``mixing_coefficients`` - the lower-triangular c_kj that give the x_k a
+    prescribed Gram matrix, from the Gram matrix of the t_j (computed by the
+    caller) and a correlation matrix: small dense linear algebra only.
 """
 from __future__ import annotations
 
@@ -140,3 +143,21 @@ def serving_request(g: np.random.Generator, solver, b):
     for j in range(min(b, len(solver["firsts"]))):
         w += c[j] * solver["firsts"][j]
     return w
+
+
+def mixing_coefficients(Gt, seed, kappa_gram):
+    """Coefficients C (lower triangular) with x_k = sum_{j<=k} C[k, j] t_j and Gram(x) = M.
+
+    Gt is the Gram matrix of the generators t_j.  With D = diag(Gt)^{-1/2},
+    L = chol(D Gt D), M a random correlation matrix whose eigenvalues are
+    geometric on [1, 1/kappa_gram] and B = chol(M): C = B L^{-1} D, so that
+    C Gt C^T = M, every ||x_k|| = 1 and cond(Gram(x)) = kappa_gram.
+    Returns (C, M).
+    """
+    m = Gt.shape[0]
+    Dm = np.diag(1.0 / np.sqrt(np.diag(Gt)))
+    L = np.linalg.cholesky(Dm @ Gt @ Dm)
+    M = correlation_with_spectrum(seed + 7, geometric_spectrum(m, kappa_gram))
+    B = np.linalg.cholesky(M)
+    C = np.tril(B @ np.linalg.inv(L) @ Dm)
+    return C, M

@@ -24,7 +24,7 @@ TT_MAXD = 64
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBNAME = "libttortho.so"
 
-SCHEMES = {"cgs": 0, "mgs": 1, "cgs2": 2, "mgs2": 3, "gram": 4}
+SCHEMES = {"cgs": 0, "mgs": 1, "cgs2": 2, "mgs2": 3, "gram": 4, "householder": 5}
 _F64, _F32 = 0, 1
 _STATUS = {0: "TT_OK", -1: "TT_EINVAL", -2: "TT_ENOMEM", -3: "TT_ECAPACITY", -4: "TT_ENOTSPD",
            -5: "TT_EBREAKDOWN", -6: "TT_ENONFINITE", -7: "TT_EDEVICE", -8: "TT_EGUARD", -9: "TT_ENOTIMPL"}
@@ -381,7 +381,7 @@ def round_batched(xs, deltas, max_ranks=None):
 
 def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: bool = True, q_capacity=None,
                   partial_on_guard: bool = False):
-    """Q, R (and the LOO curve) of the TT vectors / lazy sums A (Algorithms 1-5).
+    """Q, R (and the LOO curve) of the TT vectors / lazy sums A (Algorithms 1-8).
 
     With partial_on_guard, a stop at the rank guard returns the completed
     prefix (Q[:m_reached], R, None, stats with "guard": True) instead of raising.
@@ -400,15 +400,23 @@ def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: b
         caps.append(min(int(np.prod(first.n[:k], dtype=object)), int(np.prod(first.n[k:], dtype=object))))
     caps.append(1)
     ra = [[sum(t.r[k] for t in h.tts) for k in range(d + 1)] for h in hs]
+
+    def capped(b):
+        return [1 if k in (0, d) else min(b[k], caps[k], rank_guard if rank_guard > 0 else b[k]) for k in range(d + 1)]
     bounds, acc = [], [0] * (d + 1)
+    ubounds = []          # Householder: bounds of the u_i (w_i <= a_i + sum u_l; + i canonical terms; + 1)
     for i in range(m):
         if scheme == "gram":
             acc = [acc[k] + ra[i][k] for k in range(d + 1)]
             b = list(acc)
+        elif scheme == "householder":
+            bw = capped([ra[i][k] + sum(u[k] for u in ubounds) for k in range(d + 1)])
+            b1 = capped([bw[k] + i for k in range(d + 1)])
+            ubounds.append(capped([b1[k] + 1 for k in range(d + 1)]))
+            b = [1 + sum(u[k] for u in ubounds) for k in range(d + 1)]
         else:
             b = [ra[i][k] + sum(bb[k] for bb in bounds) for k in range(d + 1)]
-        b = [1 if k in (0, d) else min(b[k], caps[k], rank_guard if rank_guard > 0 else b[k]) for k in range(d + 1)]
-        bounds.append(b)
+        bounds.append(capped(b))
     sizes = [sum(b[k] * first.n[k] * b[k + 1] for k in range(d)) for b in bounds]
     if q_capacity is not None:
         sizes = [min(sz, int(q_capacity)) for sz in sizes]

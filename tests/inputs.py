@@ -24,13 +24,7 @@ def conditioned_inputs(seed, m, d, n, r, kappa_gram, dtype=np.float64):
     """
     t = synth.conditioned_terms(seed, m, d, n, r, dtype=dtype)
     t64 = [[c.astype(np.float64) for c in tj] for tj in t]
-    Gt = oracle.gram_of(t64)
-    Dm = np.diag(1.0 / np.sqrt(np.diag(Gt)))
-    L = np.linalg.cholesky(Dm @ Gt @ Dm)
-    M = synth.correlation_with_spectrum(seed + 7, synth.geometric_spectrum(m, kappa_gram))
-    B = np.linalg.cholesky(M)
-    C = B @ np.linalg.inv(L) @ Dm
-    C = np.tril(C)
+    C, M = synth.mixing_coefficients(oracle.gram_of(t64), seed, kappa_gram)
     X = []
     for k in range(m):
         X.append([(float(C[k, j]), [c.copy() for c in t[j]]) for j in range(k + 1)])
