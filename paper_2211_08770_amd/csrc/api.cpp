@@ -796,10 +796,13 @@ int64_t packed_size(const tt_vec& shape, const int64_t* b) {
 // TT-Householder (Section 3.3, Algorithms 6-8).  For i = 0..m-1: the Householder
 // TT-vector u_i of the (rounded) running vector w against e_0..e_i (two
 // roundings), column i of R, the reflection of the later a~_j by u_i (a term
-// appended to their lazy sums), and w = round(a~_{i+1}).  Then q_i = H_0..H_i e_i,
-// the reflections applied in reverse order to all q_i at once, and the m final
-// roundings in one batch.  The reflection of a~_i by its own u_i is skipped: the
-// algorithm never reads that result.  The u_i, two slots for w and one for the
+// appended to their lazy sums), and w = round(a~_{i+1}).  Then q_i = H_0..H_i e_i
+// and the m final roundings in one batch.  Every a~_j and q~_i is a lazy sum of
+// one original vector and Householder vectors, so each inner product with u_i is
+// taken in component form: the original's product with u_i plus the earlier
+// coefficients times the Gram matrix of the u (the same sum, each <u_l, u_i>
+// computed once instead of once per vector).  The reflection of a~_i by its own
+// u_i is skipped: the algorithm never reads that result.  The u_i, two slots for w and one for the
 // first rounding of each u live in the workspace at sizes bounded before any
 // work starts (bond ranks of a rounded sum are at most those of the sum and the
 // rank caps).
@@ -861,7 +864,15 @@ tt_status ortho_householder(tt_ctx* c, int m, const tt_sum* a, double delta, int
   double* dots = (double*)dev_scratch(c, (size_t)(m + 1) * 8);
   double* coefd = (double*)dev_scratch(c, (size_t)(m + 1) * 8);
   double* nrm = (double*)dev_scratch(c, 8);
-  if (!dn || !dots || !coefd || !nrm) return fail(c, TT_ENOMEM, "householder buffers");
+  // hbuf: <a_j, u_i> (first m) and the Gram matrix of the u (Gu = hbuf + m, row i holds
+  // <u_l, u_i>, l < i); Ct[l*m + j] = reflection coefficient of a~_j by u_l; EU[i*m + j] =
+  // <e_i, u_j>; Dq[i*m + j] = coefficient of u_j in q_i
+  double* hbuf = (double*)dev_scratch(c, (size_t)(m + m * m) * 8);
+  double* Ct = (double*)dev_scratch(c, (size_t)m * m * 8);
+  double* EU = (double*)dev_scratch(c, (size_t)m * m * 8);
+  double* Dq = (double*)dev_scratch(c, (size_t)m * m * 8);
+  if (!dn || !dots || !coefd || !nrm || !hbuf || !Ct || !EU || !Dq) return fail(c, TT_ENOMEM, "householder buffers");
+  double* Gu = hbuf + m;
   if ((e = launch_canonical(s0.dtype, Ebuf, dn, d, S, 0, m, c->stream)) != hipSuccess)
     return hip_fail(c, e, "canonical basis");
   auto make_vec = [&](void* data, int64_t capacity) {
@@ -898,14 +909,23 @@ tt_status ortho_householder(tt_ctx* c, int m, const tt_sum* a, double delta, int
   std::vector<double> hc(m + 1);
   for (int i = 0; i < m; ++i) {
     c->ws_off = top;
-    // dots <w, e_j> (j <= i) and <w, w>, then column i of R
+    // dots <w, e_j> (j <= i) and ||w||^2, then column i of R.  A rounded w has
+    // left-orthonormal cores 0..d-2, so its norm is that of its last core; w_0 = a_0
+    // is a lazy sum and takes <w, w>.
     {
-      std::vector<tt_sum> xs(i + 2, wsum), ys(i + 2);
+      const int np = (i == 0) ? i + 2 : i + 1;
+      std::vector<tt_sum> xs(np, wsum), ys(np, wsum);
       for (int j = 0; j <= i; ++j) ys[j] = tt_sum{1, &one, &E[j]};
-      ys[i + 1] = wsum;
-      if ((s = dot_pairs(c, i + 2, xs.data(), ys.data(), dots)) != TT_OK) return s;
+      if ((s = dot_pairs(c, np, xs.data(), ys.data(), dots)) != TT_OK) return s;
+      if (i > 0) {
+        int64_t off = 0;
+        for (int k = 0; k + 1 < d; ++k) off += w.r[k] * w.n[k] * w.r[k + 1];
+        if ((e = launch_sumsq(w.dtype, (const char*)w.data + (size_t)off * esz, w.r[d - 1] * w.n[d - 1], dots + i + 1,
+                              c->stream)) != hipSuccess)
+          return hip_fail(c, e, "norm of w");
+      }
     }
-    if ((e = launch_hh_column(dots, i, Rdev + (size_t)i * m, coefd, c->stream)) != hipSuccess)
+    if ((e = launch_hh_column(dots, i, i > 0 ? 1 : 0, Rdev + (size_t)i * m, coefd, c->stream)) != hipSuccess)
       return hip_fail(c, e, "householder column");
     if ((s = read_doubles(c, coefd, hc.data(), i + 1)) != TT_OK) return s;
     if (!(hc[i] != 0.0) || !std::isfinite(hc[i]))
@@ -932,14 +952,28 @@ tt_status ortho_householder(tt_ctx* c, int m, const tt_sum* a, double delta, int
     if (!(hn > 0.0) || !std::isfinite(hn))
       return fail(c, TT_EBREAKDOWN, "householder: zero Householder vector at " + std::to_string(i));
     if ((e = launch_scale(U[i].dtype, lastp, last, nrm, c->stream)) != hipSuccess) return hip_fail(c, e, "scale");
-    // reflect a~_j, j > i:  a~_j -= 2 <a~_j, u_i> u_i
+    // reflect a~_j, j > i:  a~_j -= 2 <a~_j, u_i> u_i, the inner product in component
+    // form from <a_j, u_i> and row i of the Gram matrix of the u (one batch)
     const int nr = m - 1 - i;
+    {
+      std::vector<tt_sum> xs, ys;
+      std::vector<int32_t> idx;
+      const tt_sum ui{1, &one, &U[i]};
+      for (int j = i + 1; j < m; ++j) {
+        xs.push_back(a[j]);
+        ys.push_back(ui);
+        idx.push_back(j - i - 1);
+      }
+      for (int l = 0; l < i; ++l) {
+        xs.push_back(tt_sum{1, &one, &U[l]});
+        ys.push_back(ui);
+        idx.push_back(m + i * m + l);
+      }
+      if (!xs.empty() && (s = dot_pairs_idx(c, (int)xs.size(), xs.data(), ys.data(), hbuf, &idx)) != TT_OK) return s;
+    }
     if (nr > 0) {
-      std::vector<tt_sum> xs(nr), ys(nr, tt_sum{1, &one, &U[i]});
-      for (int j = 0; j < nr; ++j) xs[j] = At[i + 1 + j].view();
-      if ((s = dot_pairs(c, nr, xs.data(), ys.data(), dots)) != TT_OK) return s;
-      if ((e = launch_scale_vec(dots, -2.0, coefd, nr, c->stream)) != hipSuccess) return hip_fail(c, e, "reflect");
-      if ((s = read_doubles(c, coefd, hc.data(), nr)) != TT_OK) return s;
+      if ((e = launch_hh_reflect(hbuf, Gu, Ct, m, i, c->stream)) != hipSuccess) return hip_fail(c, e, "reflect");
+      if ((s = read_doubles(c, Ct + (size_t)i * m + i + 1, hc.data(), nr)) != TT_OK) return s;
       for (int j = 0; j < nr; ++j) At[i + 1 + j].add(hc[j], U[i]);
       // w = round(a~_{i+1})
       w = make_vec(Wbuf[(i + 1) & 1], wmax);
@@ -947,18 +981,27 @@ tt_status ortho_householder(tt_ctx* c, int m, const tt_sum* a, double delta, int
       wsum = tt_sum{1, &one, &w};
     }
   }
-  // q_i = H_0 ... H_i e_i: reflections j = m-1..0 applied to every q_i with i >= j
+  // q_i = H_0 ... H_i e_i: <e_i, u_j> for j <= i in one batch, then the
+  // coefficients of every q_i from one recurrence kernel over the Gram matrix of the u
   c->ws_off = top;
+  {
+    std::vector<tt_sum> xs, ys;
+    std::vector<int32_t> idx;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j <= i; ++j) {
+        xs.push_back(tt_sum{1, &one, &E[i]});
+        ys.push_back(tt_sum{1, &one, &U[j]});
+        idx.push_back(i * m + j);
+      }
+    if ((s = dot_pairs_idx(c, (int)xs.size(), xs.data(), ys.data(), EU, &idx)) != TT_OK) return s;
+  }
+  if ((e = launch_hh_qcoef(EU, Gu, Dq, m, c->stream)) != hipSuccess) return hip_fail(c, e, "q coefficients");
+  std::vector<double> hD((size_t)m * m);
+  if ((s = read_doubles(c, Dq, hD.data(), hD.size())) != TT_OK) return s;
   std::vector<LazySum> Qs(m);
-  for (int i = 0; i < m; ++i) Qs[i].add(1.0, E[i]);
-  for (int j = m - 1; j >= 0; --j) {
-    const int nr = m - j;
-    std::vector<tt_sum> xs(nr), ys(nr, tt_sum{1, &one, &U[j]});
-    for (int t = 0; t < nr; ++t) xs[t] = Qs[j + t].view();
-    if ((s = dot_pairs(c, nr, xs.data(), ys.data(), dots)) != TT_OK) return s;
-    if ((e = launch_scale_vec(dots, -2.0, coefd, nr, c->stream)) != hipSuccess) return hip_fail(c, e, "reflect");
-    if ((s = read_doubles(c, coefd, hc.data(), nr)) != TT_OK) return s;
-    for (int t = 0; t < nr; ++t) Qs[j + t].add(hc[t], U[j]);
+  for (int i = 0; i < m; ++i) {
+    Qs[i].add(1.0, E[i]);
+    for (int j = i; j >= 0; --j) Qs[i].add(hD[(size_t)i * m + j], U[j]);
   }
   std::vector<tt_sum> qsums(m);
   std::vector<RJob> jobs(m);

@@ -194,11 +194,14 @@ hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int
                               hipStream_t s);
 // TT-Householder (Algorithms 6-8): canonical rank-one TT-vectors e_first..e_{first+count-1}
 // (S = sum_k n_k elements each, d_n on the device), column i of R with the
-// coefficients of the Householder sum, and out[j] = alpha * a[j].
+// coefficients of the Householder sum, the reflection coefficients of the later
+// vectors by u_i and the coefficients of every q_i, both in component form over
+// the Gram matrix of the Householder vectors.
 hipError_t launch_canonical(int dtype, void* out, const int64_t* d_n, int d, int64_t S, int64_t first, int count,
                             hipStream_t s);
-hipError_t launch_hh_column(const double* dots, int i, double* Rcol, double* coef, hipStream_t s);
-hipError_t launch_scale_vec(const double* a, double alpha, double* out, int n, hipStream_t s);
+hipError_t launch_hh_column(const double* dots, int i, int norm_given, double* Rcol, double* coef, hipStream_t s);
+hipError_t launch_hh_reflect(const double* dots_a, const double* G, double* Ct, int m, int i, hipStream_t s);
+hipError_t launch_hh_qcoef(const double* EU, const double* G, double* D, int m, hipStream_t s);
 // out[j] = a[j] + b[j]
 hipError_t launch_add(const double* a, const double* b, double* out, int n, hipStream_t s);
 hipError_t launch_neg(const double* a, double* out, int n, hipStream_t s);

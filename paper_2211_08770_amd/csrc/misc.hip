@@ -261,12 +261,12 @@ __global__ void k_canonical(T* __restrict__ out, const int64_t* __restrict__ nn,
 }
 
 // Column i of R and the coefficients of the Householder sum (Algorithm 6) from
-// dots[j] = <a, e_j> (j <= i) and dots[i+1] = <a, a>:  R(j, i) = dots[j] for
+// dots[j] = <a, e_j> (j <= i) and dots[i+1] = <a, a> (or ||a|| when norm_given):  R(j, i) = dots[j] for
 // j < i; R(i, i) = -s sqrt(<a, a> - sum_{j<i} dots[j]^2) with s = +1 when
 // dots[i] > 0 and -1 otherwise (the stable sign); coef[j] = -R(j, i), j <= i.
 // A remainder that is not positive (a in the span of e_0..e_{i-1}) gives
 // R(i, i) = 0, which the host reports as a breakdown.
-__global__ void k_hh_column(const double* __restrict__ dots, int i, double* __restrict__ Rcol,
+__global__ void k_hh_column(const double* __restrict__ dots, int i, int norm_given, double* __restrict__ Rcol,
                             double* __restrict__ coef) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double s = 0.0;
@@ -276,16 +276,41 @@ __global__ void k_hh_column(const double* __restrict__ dots, int i, double* __re
     coef[j] = -r;
     s = s + r * r;
   }
-  const double g2 = dots[i + 1] - s;
+  const double aa = norm_given ? dots[i + 1] * dots[i + 1] : dots[i + 1];
+  const double g2 = aa - s;
   const double sign = dots[i] > 0.0 ? 1.0 : -1.0;
   const double rii = g2 > 0.0 ? -sign * sqrt(g2) : 0.0;
   Rcol[i] = rii;
   coef[i] = -rii;
 }
 
-__global__ void k_scale_vec(const double* __restrict__ a, double alpha, double* __restrict__ out, int n) {
+// Reflection of the later vectors by u_i in component form (Algorithm 8 with
+// a~_j = a_j + sum_{l<i} C(j, l) u_l):  <a~_j, u_i> = <a_j, u_i> + sum_{l<i}
+// C(j, l) <u_l, u_i>, and C(j, i) = -2 <a~_j, u_i> for j = i+1..m-1.
+// dots_a[j-i-1] = <a_j, u_i>; G[i*m + l] = <u_l, u_i> (l < i); Ct[l*m + j] = C(j, l).
+__global__ void k_hh_reflect(const double* __restrict__ dots_a, const double* __restrict__ G,
+                             double* __restrict__ Ct, int m, int i) {
+  const int j = i + 1 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double s = dots_a[j - i - 1];
+  for (int l = 0; l < i; ++l) s += Ct[(int64_t)l * m + j] * G[(int64_t)i * m + l];
+  Ct[(int64_t)i * m + j] = -2.0 * s;
+}
+
+// Coefficients of q_i = H_0 ... H_i e_i (Algorithm 8) in component form: the
+// reflections j = i, i-1, ..., 0 in turn, <q~_i, u_j> = <e_i, u_j> +
+// sum_{l=j+1..i} D(i, l) <u_l, u_j> and D(i, j) = -2 <q~_i, u_j>.
+// EU[i*m + j] = <e_i, u_j> (j <= i), G[l*m + j] = <u_l, u_j> (j < l),
+// D[i*m + j].  One thread per i (the recurrence runs down j).
+__global__ void k_hh_qcoef(const double* __restrict__ EU, const double* __restrict__ G, double* __restrict__ D,
+                           int m) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = alpha * a[i];
+  if (i >= m) return;
+  for (int j = i; j >= 0; --j) {
+    double s = EU[(int64_t)i * m + j];
+    for (int l = j + 1; l <= i; ++l) s += D[(int64_t)i * m + l] * G[(int64_t)l * m + j];
+    D[(int64_t)i * m + j] = -2.0 * s;
+  }
 }
 
 // Deterministic values in [-1, 1) from an integer hash of the index (synthetic
@@ -356,14 +381,21 @@ hipError_t launch_canonical(int dtype, void* out, const int64_t* d_n, int d, int
   return hipGetLastError();
 }
 
-hipError_t launch_hh_column(const double* dots, int i, double* Rcol, double* coef, hipStream_t s) {
-  hipLaunchKernelGGL(k_hh_column, dim3(1), dim3(64), 0, s, dots, i, Rcol, coef);
+hipError_t launch_hh_column(const double* dots, int i, int norm_given, double* Rcol, double* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_hh_column, dim3(1), dim3(64), 0, s, dots, i, norm_given, Rcol, coef);
   return hipGetLastError();
 }
 
-hipError_t launch_scale_vec(const double* a, double alpha, double* out, int n, hipStream_t s) {
+hipError_t launch_hh_reflect(const double* dots_a, const double* G, double* Ct, int m, int i, hipStream_t s) {
+  const int n = m - 1 - i;
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale_vec, dim3((n + 255) / 256), dim3(256), 0, s, a, alpha, out, n);
+  hipLaunchKernelGGL(k_hh_reflect, dim3((n + 63) / 64), dim3(64), 0, s, dots_a, G, Ct, m, i);
+  return hipGetLastError();
+}
+
+hipError_t launch_hh_qcoef(const double* EU, const double* G, double* D, int m, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hh_qcoef, dim3((m + 63) / 64), dim3(64), 0, s, EU, G, D, m);
   return hipGetLastError();
 }
 

@@ -114,3 +114,36 @@ def test_breakdown_on_dependent_input():
     X[2] = [(c, [a.copy() for a in t]) for c, t in X[0]]          # a_3 = a_1
     with pytest.raises(oracle.HouseholderBreakdown):
         oracle.householder(X, 1e-10)
+
+
+def test_component_form_of_the_reflections_matches_direct():
+    # The GPU path takes <a~_j, u_i> as <a_j, u_i> + sum_{l<i} C(j,l) <u_l, u_i> and the
+    # coefficients of q_i from <e_i, u_j> and the same Gram matrix; by bilinearity these are
+    # the inner products Algorithm 8 takes on the lazy sums.  Checked with the oracle's own u.
+    m = 5
+    X, _, _ = conditioned_inputs(78, m, 3, 4, 2, 1e2)
+    res = oracle.householder(X, 1e-8)
+    U = res.U
+    G = oracle.gram_of(U)
+    ns = [c.shape[1] for c in U[0]]
+    At = [list(a) for a in X]
+    C = np.zeros((m, m))
+    Cc = np.zeros((m, m))
+    for i in range(m):
+        for j in range(i + 1, m):
+            C[j, i] = -2.0 * oracle.tt_dot(oracle.tt_sum(At[j]), U[i])
+            At[j].append((C[j, i], U[i]))
+            s = oracle.tt_dot(oracle.tt_sum(X[j]), U[i]) + sum(Cc[j, l] * G[l, i] for l in range(i))
+            Cc[j, i] = -2.0 * s
+    assert np.allclose(C, Cc, rtol=0, atol=1e-12)
+    D = np.zeros((m, m))
+    Dc = np.zeros((m, m))
+    for i in range(m):
+        e = oracle.canonical_tt(i + 1, ns)
+        terms = [(1.0, e)]
+        for j in range(i, -1, -1):
+            D[i, j] = -2.0 * oracle.tt_dot(oracle.tt_sum(terms), U[j])
+            terms.append((D[i, j], U[j]))
+            s = oracle.tt_dot(e, U[j]) + sum(Dc[i, l] * G[l, j] for l in range(j + 1, i + 1))
+            Dc[i, j] = -2.0 * s
+    assert np.allclose(D, Dc, rtol=0, atol=1e-12)
