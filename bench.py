@@ -47,6 +47,8 @@ def parse():
                    help="only run a plain 256 MiB device-to-device copy (reference for the HBM byte counters)")
     p.add_argument("--headline-only", action="store_true",
                    help="time only the headline configuration (for profiler runs); no FP64 side runs, no CPU baseline")
+    p.add_argument("--householder-only", action="store_true",
+                   help="only the TT-Householder measurement (for profiler runs); prints its JSON object")
     return p.parse_args()
 
 
@@ -273,6 +275,9 @@ def main():
         return
     torch.cuda.set_device(0)
     tt._load()
+    if args.householder_only:
+        print(json.dumps(run_householder(tt, torch)))
+        return
     res32 = run_config(tt, torch, torch.float32, 1e-4, args.steps, args.warmup, profile=True)
     if args.headline_only:
         res64 = res64b = None

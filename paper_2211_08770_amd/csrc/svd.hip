@@ -220,6 +220,75 @@ __device__ __attribute__((always_inline)) int jacobi(double* Ag, double* Jg, boo
   return sweep;
 }
 
+// The sweeps of jacobi() on A in LDS (lda == GL * EPL) run by one wave alone,
+// for k <= 2 * 64 / GL: one GL-lane group per pair of a round.  The LDS
+// operations of one wave take effect in the order they are issued, so the
+// rounds need no workgroup barrier; the other waves wait at one barrier after
+// the sweeps.  Same rotations and stopping rule as jacobi().
+template <int GL, int EPL>
+__device__ __attribute__((always_inline)) int jacobi_wave(bool with_j, int len, int lda, int k) {
+  double* A = svd_lds;
+  double* J = with_j ? svd_lds + (int64_t)lda * k : nullptr;
+  const int lane = threadIdx.x & 63, gl = lane % GL, grp = lane / GL;
+  const int kp = k + (k & 1);
+  const double tol = (double)len * 1.1102230246251565e-16;
+  const double tol2 = tol * tol;
+  int sweep = 0;
+  for (; sweep < 64 && kp >= 2; ++sweep) {
+    bool rotated = false;
+    for (int round = 0; round < kp - 1; ++round) {
+      int p = 0, q = 0;
+      if (grp < kp / 2) rr_pair(round, grp, kp, p, q);
+      const bool live = grp < kp / 2 && q < k;
+      double* ap = A + (int64_t)p * lda;
+      double* aq = A + (int64_t)q * lda;
+      double x[EPL], y[EPL];
+      if (live) {
+#pragma unroll
+        for (int t = 0; t < EPL; ++t) {
+          x[t] = ap[gl + GL * t];
+          y[t] = aq[gl + GL * t];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < EPL; ++t) x[t] = y[t] = 0.0;
+      }
+      double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int t = 0; t < EPL; ++t) {
+        al += x[t] * x[t];
+        be += y[t] * y[t];
+        ga += x[t] * y[t];
+      }
+      al = group_sum<GL>(al);
+      be = group_sum<GL>(be);
+      ga = group_sum<GL>(ga);
+      if (live && ga != 0.0 && ga * ga > tol2 * al * be) {
+        double c, s;
+        rotation(al, be, ga, c, s);
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          ap[gl + GL * e] = c * x[e] - s * y[e];
+          aq[gl + GL * e] = s * x[e] + c * y[e];
+        }
+        if (J) {
+          double* jp = J + (int64_t)p * k;
+          double* jq = J + (int64_t)q * k;
+          for (int i = gl; i < k; i += GL) {
+            const double u = jp[i], v = jq[i];
+            jp[i] = c * u - s * v;
+            jq[i] = s * u + c * v;
+          }
+        }
+        rotated = true;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (__ballot(rotated) == 0) break;
+  }
+  return sweep;
+}
+
 __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   __shared__ int perm[MAXC + 2];
   __shared__ int act[MAXC];
@@ -357,7 +426,21 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   }
   __syncthreads();
   int sweeps = 0;
-  if (k > 0) {
+  // one wave alone when every pair of a round fits in it with groups of 16 or 8 lanes
+  // (narrower groups lengthen each lane's chain more than the barriers save)
+  const int wgl = mode <= 0 ? 0 : (k <= 8 ? 16 : k <= 16 ? 8 : 0);
+  const int wepl = wgl > 0 ? lda / wgl : 0;
+  const bool one_wave = wgl > 0 && wepl <= 16;
+  if (k > 0 && one_wave) {
+    if (wave == 0) {
+      if (wgl == 16 && wepl == 4) sweeps = jacobi_wave<16, 4>(!tall, len, lda, k);
+      else if (wgl == 16 && wepl == 8) sweeps = jacobi_wave<16, 8>(!tall, len, lda, k);
+      else if (wgl == 16) sweeps = jacobi_wave<16, 16>(!tall, len, lda, k);
+      else if (wgl == 8 && wepl == 8) sweeps = jacobi_wave<8, 8>(!tall, len, lda, k);
+      else sweeps = jacobi_wave<8, 16>(!tall, len, lda, k);
+    }
+    __syncthreads();
+  } else if (k > 0) {
     if (mode < 0) sweeps = jacobi<false, JGL, 0>(tk.A, tk.acc, !tall, len, lda, k, &rots);
     else if (mode == 4) sweeps = jacobi<true, JGL, 4>(nullptr, nullptr, !tall, len, lda, k, &rots);
     else if (mode == 8) sweeps = jacobi<true, JGL, 8>(nullptr, nullptr, !tall, len, lda, k, &rots);
