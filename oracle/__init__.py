@@ -10,3 +10,4 @@ against dense brute force, closed forms and invariants.
 from .tt import *          # noqa: F401,F403
 from .schemes import *     # noqa: F401,F403
 from . import dense        # noqa: F401
+from .laplace import *     # noqa: F401,F403
