@@ -190,6 +190,23 @@ tt_status tt_orthogonalize(tt_ctx* ctx, tt_scheme scheme, int32_t m, const tt_su
                            int64_t rank_guard, tt_vec* q, double* R, double* loo,
                            tt_ortho_stats* stats);
 
+/* y = alpha * Delta_d x: the discrete Laplacian of order d with Dirichlet
+ * boundary conditions (Section 4, the operator of the Krylov inputs) as the
+ * rank-two TT-matrix with cores [L, I], [[I, 0], [L, I]], [I; L], where
+ * L = (n_k + 1)^2 tridiag(1, -2, 1) on mode k.  out (device, capacity set by
+ * the caller, no aliasing with x) receives ranks r_0 = r_d = 1 and 2 r_k in
+ * between (rank 1 when d = 1); alpha goes on the first core.  Errors:
+ * TT_EINVAL (shapes, non-finite alpha, aliasing), TT_ECAPACITY. */
+tt_status tt_laplacian(tt_ctx* ctx, const tt_vec* x, double alpha, tt_vec* out);
+
+/* The m input vectors of the experiments of Section 4: x_1 is the TT-vector
+ * of ones; a_j is x_j rounded with the accuracy replaced by the rank cap one
+ * and normalised; x_{j+1} = -Delta_d a_j.  a[0..m-1]: device outputs of one
+ * shape (d, n, dtype taken from a[0]), capacity >= sum_k n_k each; their ranks
+ * are written (all 1).  Works in the context workspace (4 sum_k n_k elements
+ * plus one rounding).  Errors: TT_EINVAL, TT_ECAPACITY, TT_EBREAKDOWN. */
+tt_status tt_krylov_laplacian(tt_ctx* ctx, int32_t m, tt_vec* a);
+
 /* Loss of orthogonality ||I_k - Q_k^T Q_k||_2, k = 1..m (Section 3.4):
  * Gram matrix of q by TT inner products, then the largest |eigenvalue| of
  * each leading block (symmetric Jacobi on the device).  loo: HOST [m];

@@ -1031,6 +1031,106 @@ tt_status ortho_householder(tt_ctx* c, int m, const tt_sum* a, double delta, int
 
 }  // namespace
 
+tt_status tt_laplacian(tt_ctx* c, const tt_vec* x, double alpha, tt_vec* out) {
+  if (!c) return TT_EINVAL;
+  tt_status s;
+  if ((s = check_vec(c, x, "x", true)) != TT_OK) return s;
+  if ((s = check_vec(c, out, "out", false)) != TT_OK) return s;
+  if (!same_shape(*x, *out)) return fail(c, TT_EINVAL, "laplacian: out differs from x in d, n or dtype");
+  if (!std::isfinite(alpha)) return fail(c, TT_EINVAL, "laplacian: non-finite alpha");
+  if (x->data == out->data) return fail(c, TT_EINVAL, "laplacian: out must not alias x");
+  const int d = x->d;
+  int64_t yr[TT_MAXD + 1];
+  yr[0] = yr[d] = 1;
+  for (int k = 1; k < d; ++k) yr[k] = 2 * x->r[k];
+  int64_t need = 0;
+  for (int k = 0; k < d; ++k) need += yr[k] * x->n[k] * yr[k + 1];
+  if (out->capacity < need)
+    return fail(c, TT_ECAPACITY, "laplacian: out capacity " + std::to_string(out->capacity) + " < " + std::to_string(need));
+  CallScope scope(c);
+  const size_t esz = elt_size(x->dtype);
+  int64_t xo = 0, yo = 0;
+  for (int k = 0; k < d; ++k) {
+    const int kind = (d == 1) ? 3 : (k == 0) ? 0 : (k == d - 1) ? 2 : 1;
+    hipError_t e = launch_laplacian_core(x->dtype, (const char*)x->data + (size_t)xo * esz, x->r[k], x->n[k],
+                                         x->r[k + 1], kind, alpha, (char*)out->data + (size_t)yo * esz, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "laplacian");
+    xo += x->r[k] * x->n[k] * x->r[k + 1];
+    yo += yr[k] * x->n[k] * yr[k + 1];
+  }
+  for (int k = 0; k <= d; ++k) out->r[k] = yr[k];
+  return TT_OK;
+}
+
+tt_status tt_krylov_laplacian(tt_ctx* c, int32_t m, tt_vec* a) {
+  if (!c || m < 1 || !a) return fail(c, TT_EINVAL, "krylov: bad arguments");
+  tt_status s;
+  int64_t S = 0;
+  for (int j = 0; j < m; ++j) {
+    if ((s = check_vec(c, &a[j], "a", false)) != TT_OK) return s;
+    if (!same_shape(a[j], a[0])) return fail(c, TT_EINVAL, "krylov: outputs differ in shape");
+  }
+  const tt_vec& s0 = a[0];
+  const int d = s0.d;
+  for (int k = 0; k < d; ++k) S += s0.n[k];
+  for (int j = 0; j < m; ++j)
+    if (a[j].capacity < S) return fail(c, TT_ECAPACITY, "krylov: output capacity below sum_k n_k");
+  CallScope scope(c);
+  const size_t mark = c->ws_off;
+  struct Mark {
+    tt_ctx* c;
+    size_t off;
+    ~Mark() { c->ws_off = off; }
+  } wmark{c, mark};
+  const size_t esz = elt_size(s0.dtype);
+  // x (ones, then -Delta_d a_j with ranks 2 on interior bonds: at most 4 sum_k n_k elements)
+  char* xbuf = (char*)ws_alloc(c, (size_t)4 * S * esz);
+  double* nrm = (double*)dev_scratch(c, 8);
+  if (!xbuf) return fail(c, TT_ECAPACITY, "workspace too small for the Krylov vector: need " + std::to_string(c->required));
+  if (!nrm) return fail(c, TT_ENOMEM, "krylov buffers");
+  hipError_t e;
+  tt_vec x = s0;
+  for (int k = 0; k <= d; ++k) x.r[k] = 1;
+  x.data = xbuf;
+  x.capacity = 4 * S;
+  if ((e = launch_fill_const(s0.dtype, xbuf, S, 1.0, c->stream)) != hipSuccess) return hip_fail(c, e, "ones");
+  static const double one = 1.0;
+  for (int j = 0; j < m; ++j) {
+    // a_j = x_j rounded to TT-rank one (accuracy 0, rank cap 1), then normalised
+    tt_sum xs{1, &one, &x};
+    std::vector<RJob> jobs(1);
+    make_job(c, &xs, 0.0, 1, &a[j], jobs[0]);
+    if ((s = round_jobs(c, jobs)) != TT_OK) return s;
+    if (jobs[0].status != TT_OK) return fail(c, jobs[0].status, "krylov: output capacity");
+    int64_t off = 0;
+    for (int k = 0; k + 1 < d; ++k) off += a[j].r[k] * a[j].n[k] * a[j].r[k + 1];
+    char* lastp = (char*)a[j].data + (size_t)off * esz;
+    const int64_t last = a[j].r[d - 1] * a[j].n[d - 1];
+    if ((e = launch_sumsq(s0.dtype, lastp, last, nrm, c->stream)) != hipSuccess) return hip_fail(c, e, "norm");
+    if ((e = launch_scale(s0.dtype, lastp, last, nrm, c->stream)) != hipSuccess) return hip_fail(c, e, "scale");
+    if (j + 1 < m) {
+      // x_{j+1} = -Delta_d a_j
+      int64_t xo = 0, yo = 0;
+      for (int k = 0; k < d; ++k) {
+        const int kind = (d == 1) ? 3 : (k == 0) ? 0 : (k == d - 1) ? 2 : 1;
+        if ((e = launch_laplacian_core(s0.dtype, (const char*)a[j].data + (size_t)xo * esz, a[j].r[k], a[j].n[k],
+                                       a[j].r[k + 1], kind, -1.0, xbuf + (size_t)yo * esz, c->stream)) != hipSuccess)
+          return hip_fail(c, e, "laplacian");
+        xo += a[j].r[k] * a[j].n[k] * a[j].r[k + 1];
+        const int64_t y0 = (k == 0) ? 1 : 2 * a[j].r[k], y1 = (k == d - 1) ? 1 : 2 * a[j].r[k + 1];
+        yo += y0 * a[j].n[k] * y1;
+      }
+      x.r[0] = x.r[d] = 1;
+      for (int k = 1; k < d; ++k) x.r[k] = 2 * a[j].r[k];
+    }
+  }
+  // a zero vector cannot be normalised: report it (the all-ones start and -Delta_d keep every a_j nonzero)
+  double hn = 0.0;
+  if ((s = read_doubles(c, nrm, &hn, 1)) != TT_OK) return s;
+  if (!(hn > 0.0) || !std::isfinite(hn)) return fail(c, TT_EBREAKDOWN, "krylov: zero or non-finite vector");
+  return TT_OK;
+}
+
 tt_status tt_loo(tt_ctx* c, int32_t m, const tt_vec* q, double* loo, double* gram) {
   if (!c || m < 1 || !q || !loo) return fail(c, TT_EINVAL, "loo: bad arguments");
   tt_status s;

@@ -202,6 +202,11 @@ hipError_t launch_canonical(int dtype, void* out, const int64_t* d_n, int d, int
 hipError_t launch_hh_column(const double* dots, int i, int norm_given, double* Rcol, double* coef, hipStream_t s);
 hipError_t launch_hh_reflect(const double* dots_a, const double* G, double* Ct, int m, int i, hipStream_t s);
 hipError_t launch_hh_qcoef(const double* EU, const double* G, double* D, int m, hipStream_t s);
+// One core of y = alpha * Delta_d x (Dirichlet Laplacian as a rank-two TT-matrix);
+// kind 0 first, 1 interior, 2 last, 3 only core.  x[0..n) = v.
+hipError_t launch_laplacian_core(int dtype, const void* X, int64_t r0, int64_t n, int64_t r1, int kind, double alpha,
+                                 void* Y, hipStream_t s);
+hipError_t launch_fill_const(int dtype, void* x, int64_t n, double v, hipStream_t s);
 // out[j] = a[j] + b[j]
 hipError_t launch_add(const double* a, const double* b, double* out, int n, hipStream_t s);
 hipError_t launch_neg(const double* a, double* out, int n, hipStream_t s);

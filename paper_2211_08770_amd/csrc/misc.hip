@@ -313,6 +313,50 @@ __global__ void k_hh_qcoef(const double* __restrict__ EU, const double* __restri
   }
 }
 
+// One core of y = alpha * Delta_d x (Section 4: the Dirichlet Laplacian of
+// order d as the rank-two TT-matrix with cores [L, I], [[I, 0], [L, I]] and
+// [I; L], L = (n+1)^2 tridiag(1, -2, 1)).  kind: 0 first core (1 x n x 2r1:
+// blocks L X, X), 1 interior (2r0 x n x 2r1: blocks X, 0 / L X, X), 2 last core
+// (2r0 x n x 1: blocks X / L X), 3 the only core (L X).  X row-major
+// [r0][n][r1]; one thread per output element; the second difference reads the
+// neighbours of mode index i (zero outside [0, n)).
+template <typename T>
+__global__ void k_laplacian_core(const T* __restrict__ X, int64_t r0, int64_t n, int64_t r1, int kind,
+                                 double alpha, T* __restrict__ Y) {
+  const int64_t R0 = (kind == 1 || kind == 2) ? 2 * r0 : r0;
+  const int64_t R1 = (kind == 0 || kind == 1) ? 2 * r1 : r1;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= R0 * n * R1) return;
+  const int64_t A = e / (n * R1), rem = e - A * n * R1, i = rem / R1, B = rem - i * R1;
+  const int ba = (A >= r0) ? 1 : 0, bb = (B >= r1) ? 1 : 0;   // block row and column
+  const int64_t a = A - ba * r0, b = B - bb * r1;
+  // which block: 0 zero, 1 X, 2 L X
+  int blk;
+  if (kind == 3) blk = 2;
+  else if (kind == 0) blk = bb ? 1 : 2;
+  else if (kind == 2) blk = ba ? 2 : 1;
+  else blk = (ba == 0) ? (bb ? 0 : 1) : (bb ? 1 : 2);
+  double v = 0.0;
+  const T* xa = X + (a * n) * r1 + b;
+  if (blk == 1) {
+    v = (double)xa[i * r1];
+  } else if (blk == 2) {
+    const double s = (double)(n + 1) * (double)(n + 1);
+    double t = -2.0 * (double)xa[i * r1];
+    if (i > 0) t += (double)xa[(i - 1) * r1];
+    if (i + 1 < n) t += (double)xa[(i + 1) * r1];
+    v = s * t;
+  }
+  if (kind == 0 || kind == 3) v *= alpha;
+  Y[e] = (T)v;
+}
+
+template <typename T>
+__global__ void k_fill_const(T* __restrict__ x, int64_t n, double v) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) x[e] = (T)v;
+}
+
 // Deterministic values in [-1, 1) from an integer hash of the index (synthetic
 // matrices for timing tile shapes; the values do not matter to the timing).
 template <typename T>
@@ -383,6 +427,32 @@ hipError_t launch_canonical(int dtype, void* out, const int64_t* d_n, int d, int
 
 hipError_t launch_hh_column(const double* dots, int i, int norm_given, double* Rcol, double* coef, hipStream_t s) {
   hipLaunchKernelGGL(k_hh_column, dim3(1), dim3(64), 0, s, dots, i, norm_given, Rcol, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_laplacian_core(int dtype, const void* X, int64_t r0, int64_t n, int64_t r1, int kind, double alpha,
+                                 void* Y, hipStream_t s) {
+  const int64_t R0 = (kind == 1 || kind == 2) ? 2 * r0 : r0;
+  const int64_t R1 = (kind == 0 || kind == 1) ? 2 * r1 : r1;
+  const int64_t total = R0 * n * R1;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = (total + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_laplacian_core<double>, dim3((unsigned)blocks), dim3(256), 0, s, (const double*)X, r0, n, r1,
+                       kind, alpha, (double*)Y);
+  else
+    hipLaunchKernelGGL(k_laplacian_core<float>, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)X, r0, n, r1,
+                       kind, alpha, (float*)Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_const(int dtype, void* x, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  if (dtype == 0) hipLaunchKernelGGL(k_fill_const<double>, dim3((unsigned)blocks), dim3(256), 0, s, (double*)x, n, v);
+  else hipLaunchKernelGGL(k_fill_const<float>, dim3((unsigned)blocks), dim3(256), 0, s, (float*)x, n, v);
   return hipGetLastError();
 }
 

@@ -17,7 +17,8 @@ import threading
 import numpy as np
 import torch
 
-__all__ = ["TT", "dot", "dot_batched", "axpy", "norm", "round", "round_batched", "orthogonalize", "loo",
+__all__ = ["TT", "dot", "dot_batched", "axpy", "norm", "round", "round_batched", "orthogonalize", "loo", "laplacian",
+           "krylov_laplacian",
            "Engine", "TTError", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
 
 TT_MAXD = 64
@@ -109,6 +110,10 @@ def _load():
         lib.tt_orthogonalize.restype = C.c_int
         lib.tt_loo.argtypes = [P, C.c_int32, C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.tt_loo.restype = C.c_int
+        lib.tt_laplacian.argtypes = [P, C.POINTER(_Vec), C.c_double, C.POINTER(_Vec)]
+        lib.tt_laplacian.restype = C.c_int
+        lib.tt_krylov_laplacian.argtypes = [P, C.c_int32, C.POINTER(_Vec)]
+        lib.tt_krylov_laplacian.restype = C.c_int
         lib.tt_ctx_set_autotune.argtypes = [P, C.c_int]
         lib.tt_ctx_set_autotune.restype = C.c_int
         lib.tt_tune_tsqr.argtypes = [P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
@@ -290,6 +295,30 @@ def axpy(alpha: float, x: TT, y: TT) -> TT:
     ctx.check(ctx.lib.tt_axpy(ctx.h, float(alpha), C.byref(vx), C.byref(vy), C.byref(vz)))
     z.r = [int(vz.r[k]) for k in range(x.d + 1)]
     return z
+
+
+def laplacian(x: TT, alpha: float = 1.0) -> TT:
+    """alpha * Delta_d x (Dirichlet Laplacian as a rank-two TT-matrix; interior ranks double)."""
+    ctx = _ctx(x.data.device.index)
+    ranks = [1] + [2 * r for r in x.r[1:-1]] + [1]
+    size = sum(ranks[k] * x.n[k] * ranks[k + 1] for k in range(x.d))
+    y = TT(torch.empty(size, dtype=x.dtype, device=x.data.device), x.n, ranks)
+    vx, vy = x._vec(), y._vec()
+    ctx.check(ctx.lib.tt_laplacian(ctx.h, C.byref(vx), float(alpha), C.byref(vy)))
+    y.r = [int(vy.r[k]) for k in range(x.d + 1)]
+    return y
+
+
+def krylov_laplacian(ns, m: int, dtype=torch.float64, device=None):
+    """The m rank-one Krylov inputs of the paper's experiments (ones, -Delta_d, rank-one rounding)."""
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+    ctx = _ctx(dev.index)
+    size = int(sum(ns))
+    A = [TT(torch.empty(size, dtype=dtype, device=dev), list(ns), [1] * (len(ns) + 1)) for _ in range(m)]
+    va = (_Vec * m)(*[a._vec() for a in A])
+    ctx.ensure_ws(64 << 20)
+    ctx.call_with_ws(lambda: ctx.lib.tt_krylov_laplacian(ctx.h, m, va))
+    return [_finish_out(a, va[i]) for i, a in enumerate(A)]
 
 
 def round_out_capacity(x) -> int:
