@@ -98,3 +98,20 @@ def test_householder_rank_guard():
     with pytest.raises(tt.TTError) as ei:
         tt.orthogonalize("householder", A, 1e-8, rank_guard=2)
     assert ei.value.status == "TT_EGUARD"
+
+
+def test_householder_full_basis_and_exact_zero_components():
+    # m equal to the number of tensor entries, and inputs with exactly zero entries along the
+    # canonical directions, so that the sign rule takes its "not positive" branch
+    tt = need_gpu()
+    ns = [2, 3]
+    # a_1 = e_2 (zero along e_1), a_2 = e_1 + e_3, a_3..a_6 random: rank-one TTs and lazy sums
+    e = [oracle.canonical_tt(i, ns) for i in range(1, 7)]
+    g = synth.rng(606)
+    X = [[(1.0, e[1])], [(1.0, e[0]), (1.0, e[2])]]
+    for _ in range(4):
+        X.append([(1.0, synth.random_tt(g, ns, [1, 2, 1])), (0.3, e[5])])
+    ref, Q, R, loo, st = run_both(X, 1e-12)
+    compare(ref, Q, R, loo, st, 1e-9, 100 * 1.1e-16)
+    assert ref.R[0, 0] == pytest.approx(1.0)          # <a_1, e_1> = 0 takes s = -1: R(1,1) = +||a_1||
+    assert max(loo) < 1e-10

@@ -124,3 +124,22 @@ def test_gram_on_krylov_inputs():
         fl = 100 * k * 1.1e-16 * max(1.0, kappa[k - 1] ** 2)
         a, b = max(loo[k - 1], fl), max(ref_loo[k - 1], fl)
         assert a <= 2 * b and b <= 2 * a, (k, loo[k - 1], ref_loo[k - 1])
+
+
+def test_laplacian_rejects_aliasing_and_bad_alpha():
+    tt = need_gpu()
+    from paper_2211_08770_amd.tt import TT
+    g = synth.rng(82)
+    x = dev_tt(synth.random_tt(g, [4, 5], [1, 2, 1]))
+    lib = tt._load()
+    ctx = tt._ctx()
+    vx = x._vec()
+    big = TT(torch.empty(4 * x.data.numel(), dtype=x.dtype, device=x.data.device), x.n, [1, 1, 1])
+    vb = big._vec()
+    import ctypes as C
+    assert lib.tt_laplacian(ctx.h, C.byref(vx), 1.0, C.byref(vx)) == -1          # out aliases x
+    assert lib.tt_laplacian(ctx.h, C.byref(vx), float("nan"), C.byref(vb)) == -1  # non-finite alpha
+    small = TT(torch.empty(3, dtype=x.dtype, device=x.data.device), x.n, [1, 1, 1])
+    vs = small._vec()
+    assert lib.tt_laplacian(ctx.h, C.byref(vx), 1.0, C.byref(vs)) == -3          # capacity
+    assert lib.tt_laplacian(ctx.h, C.byref(vx), 2.0, C.byref(vb)) == 0
