@@ -11,3 +11,4 @@ from .tt import *          # noqa: F401,F403
 from .schemes import *     # noqa: F401,F403
 from . import dense        # noqa: F401
 from .laplace import *     # noqa: F401,F403
+from .randomized import *  # noqa: F401,F403
