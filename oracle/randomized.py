@@ -30,8 +30,10 @@ def sketch_contractions(x, sketch):
     W = [None] * (d + 1)
     W[d] = np.ones((1, 1))
     for k in range(d - 1, 0, -1):
-        # W_k[a, l] = sum_{i, b, j} X_{k+1}[a, i, b] W_{k+1}[b, j] S_{k+1}[l, i, j]
-        W[k] = np.einsum("aib,bj,lij->al", x[k], W[k + 1], sketch[k])
+        # W_k[a, l] = sum_{i, b, j} X_{k+1}[a, i, b] W_{k+1}[b, j] S_{k+1}[l, i, j], as two products
+        a, n, b = x[k].shape
+        T = x[k].reshape(a * n, b) @ W[k + 1]                     # (a n) x l_{k+1}
+        W[k] = T.reshape(a, -1) @ sketch[k].reshape(sketch[k].shape[0], -1).T
     return W
 
 
@@ -51,6 +53,7 @@ def tt_round_rto(terms, sketch, delta=0.0):
         Q, _ = np.linalg.qr(Z)
         out.append(Q.reshape(p0, n, Q.shape[1]))
         M = Q.T @ L
-        G = np.einsum("ab,bic->aic", M, x[k + 1])
+        r1, n1, r2 = x[k + 1].shape
+        G = (M @ x[k + 1].reshape(r1, n1 * r2)).reshape(M.shape[0], n1, r2)
     out.append(G)
     return tt_round(out, delta) if delta > 0 else out
