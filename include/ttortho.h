@@ -190,6 +190,20 @@ tt_status tt_orthogonalize(tt_ctx* ctx, tt_scheme scheme, int32_t m, const tt_su
                            int64_t rank_guard, tt_vec* q, double* R, double* loo,
                            tt_ortho_stats* stats);
 
+/* Randomized rounding of a lazy sum (the cheaper rounding of sums that the
+ * paper cites for output ranks far below those of the sum):
+ * Randomize-then-Orthogonalize with the Gaussian sketch TT-vector `sketch`
+ * (ranks l_k, drawn by the caller, same d and n as x): W_k = partial
+ * contractions of x and the sketch from the right; from the left, core k of
+ * the result is Q of Z_k = L(G_k) W_{k+1} and M_k = Q^T L(G_k) is absorbed into
+ * core k+1.  Result ranks min(l_k, p_{k-1} n_k); with delta > 0 the result is
+ * then rounded deterministically at delta (as tt_round).  FP64 only (else
+ * TT_ENOTIMPL); d = 1 returns the (rounded) sum.  out: device, capacity set
+ * by the caller (out->r written).  No QR of the R_k-column unfoldings of the
+ * sum is formed, so R_k may exceed the tile limits of tt_round; the sketch
+ * ranks must keep Z_k within them (TT_ENOTIMPL otherwise). */
+tt_status tt_round_randomized(tt_ctx* ctx, const tt_sum* x, const tt_vec* sketch, double delta, tt_vec* out);
+
 /* y = alpha * Delta_d x: the discrete Laplacian of order d with Dirichlet
  * boundary conditions (Section 4, the operator of the Krylov inputs) as the
  * rank-two TT-matrix with cores [L, I], [[I, 0], [L, I]], [I; L], where

@@ -1031,6 +1031,25 @@ tt_status ortho_householder(tt_ctx* c, int m, const tt_sum* a, double delta, int
 
 }  // namespace
 
+tt_status tt_round_randomized(tt_ctx* c, const tt_sum* x, const tt_vec* sketch, double delta, tt_vec* out) {
+  if (!c) return TT_EINVAL;
+  tt_status s;
+  if ((s = check_sum(c, x, "x")) != TT_OK) return s;
+  if ((s = check_vec(c, sketch, "sketch", true)) != TT_OK) return s;
+  if ((s = check_vec(c, out, "out", false)) != TT_OK) return s;
+  const tt_vec& s0 = x->comp[0];
+  if (s0.dtype != TT_F64 || sketch->dtype != TT_F64 || out->dtype != TT_F64)
+    return fail(c, TT_ENOTIMPL, "randomized rounding: FP64 only");
+  if (!same_shape(s0, *sketch) || !same_shape(s0, *out))
+    return fail(c, TT_EINVAL, "randomized rounding: x, sketch and out differ in d or n");
+  if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(c, TT_EINVAL, "randomized rounding: delta must be >= 0");
+  for (int k = 1; k < s0.d; ++k)
+    if (sketch->r[k] > 1024) return fail(c, TT_ENOTIMPL, "randomized rounding: sketch rank above 1024");
+  CallScope scope(c);
+  if (s0.d == 1) return round_one(c, x, delta, out);
+  return round_randomized(c, x, sketch, delta, out);
+}
+
 tt_status tt_laplacian(tt_ctx* c, const tt_vec* x, double alpha, tt_vec* out) {
   if (!c) return TT_EINVAL;
   tt_status s;

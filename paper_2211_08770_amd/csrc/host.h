@@ -163,6 +163,9 @@ struct RJob {
 tt_status make_job(tt_ctx* c, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out, RJob& job);
 tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs);
 int64_t round_workspace_bytes(const std::vector<RJob>& jobs);
+// Randomize-then-Orthogonalize rounding of a lazy FP64 sum with the sketch TT
+// sk (ranks l_k); with delta > 0 the result is then rounded deterministically.
+tt_status round_randomized(tt_ctx* c, const tt_sum* x, const tt_vec* sk, double delta, tt_vec* out);
 
 // ---- inner products ----------------------------------------------------------
 // out_dev[p] = <xs[p], ys[p]> (device doubles)

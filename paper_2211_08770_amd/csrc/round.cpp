@@ -1142,4 +1142,238 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
   return TT_OK;
 }
 
+// ============================================================================
+// Randomized rounding of a lazy sum (Randomize-then-Orthogonalize, FP64).
+//   W_k = cores k..d-1 of x contracted with those of the sketch (R_k x l_k),
+//         right to left, per sum component (block rows of W_k);
+//   left to right, core k = 0..d-2:
+//     Z_k = L(G_k) W_{k+1};  Z_k = Q R (tile QR tree);  core k of the result = Q
+//     M_k = Q^T L(G_k);      G_{k+1} = M_k x_1 core k+1 (per component block)
+//   last core = G_{d-1};  with delta > 0 the result is rounded deterministically.
+// G_0 is the side-by-side first core with the sum coefficients; the last core
+// stacks the components' last cores.  Every product is a strided GEMM.
+// ============================================================================
+namespace {
+
+struct Gemms {
+  std::vector<GemmSTask> t;
+  int max_m = 0, max_n = 0;
+  void add(const void* A, int64_t a_rs, int64_t a_cs, const double* B, int64_t b_rs, int64_t b_cs, void* C,
+           int64_t c_rs, int64_t c_cs, int64_t M, int64_t N, int64_t K) {
+    if (M <= 0 || N <= 0) return;
+    GemmSTask g;
+    std::memset(&g, 0, sizeof(g));
+    g.A = A;
+    g.a_rs = a_rs;
+    g.a_cs = a_cs;
+    g.B = B;
+    g.b_rs = b_rs;
+    g.b_cs = b_cs;
+    g.C = C;
+    g.c_rs = c_rs;
+    g.c_cs = c_cs;
+    g.M = (int32_t)M;
+    g.N = (int32_t)N;
+    g.K = (int32_t)K;
+    t.push_back(g);
+    max_m = std::max<int>(max_m, (int)M);
+    max_n = std::max<int>(max_n, (int)N);
+  }
+  tt_status run(tt_ctx* c) {
+    if (t.empty()) return TT_OK;
+    const GemmSTask* dt = upload(c, t);
+    if (!dt) return fail(c, TT_ENOMEM, "gemm task upload");
+    double fl = 0.0;
+    if (c->prof)
+      for (const auto& g : t) fl += 2.0 * g.M * g.N * (double)g.K;
+    const int pr = prof_begin(c, PK_GEMM, fl, 0.0);
+    hipError_t e = launch_gemm_strided(TT_F64, dt, (int)t.size(), max_m, max_n, c->stream);
+    prof_end(c, pr);
+    if (e != hipSuccess) return hip_fail(c, e, "gemm");
+    t.clear();
+    max_m = max_n = 0;
+    return TT_OK;
+  }
+};
+
+tt_status run_copies(tt_ctx* c, const std::vector<CopySeg>& segs) {
+  if (segs.empty()) return TT_OK;
+  const CopySeg* ds = upload(c, segs);
+  if (!ds) return fail(c, TT_ENOMEM, "copy upload");
+  hipError_t e = launch_copy_segs(TT_F64, ds, (int)segs.size(), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "copy");
+  return TT_OK;
+}
+
+}  // namespace
+
+tt_status round_randomized(tt_ctx* c, const tt_sum* x, const tt_vec* sk, double delta, tt_vec* out) {
+  RJob jb;
+  make_job(c, x, 0.0, 0, nullptr, jb);
+  const int d = jb.d;
+  const int nc = (int)jb.comps.size();
+  const int64_t* n = jb.n;
+  const int64_t* R = jb.R;
+  const size_t mark = c->ws_off;
+  struct Mark {
+    tt_ctx* c;
+    size_t off;
+    ~Mark() { c->ws_off = off; }
+  } wmark{c, mark};
+  c->ws_overflow = false;
+  int64_t l[TT_MAXD + 1], p[TT_MAXD + 1];
+  for (int k = 0; k <= d; ++k) l[k] = sk->r[k];
+  p[0] = p[d] = 1;
+  for (int k = 1; k < d; ++k) p[k] = std::min<int64_t>(l[k], p[k - 1] * n[k - 1]);
+  auto roff = [&](int ci, int k) { return jb.roff[(size_t)ci * (d + 1) + k]; };
+  auto core = [&](int ci, int k) { return (const double*)jb.comps[ci].data + jb.comps[ci].core_off[k]; };
+  auto rc = [&](int ci, int k) { return jb.comps[ci].r[k]; };
+  // sketch cores
+  const double* S[TT_MAXD];
+  {
+    int64_t off = 0;
+    for (int k = 0; k < d; ++k) {
+      S[k] = (const double*)sk->data + off;
+      off += sk->r[k] * sk->n[k] * sk->r[k + 1];
+    }
+  }
+  // ---- buffers (workspace)
+  Carver ws;
+  ws.ctx = c;
+  double* WT[TT_MAXD + 1] = {nullptr};
+  size_t t1max = 1, gmax = 1, zmax = 1, mmax = 1, pmax = 1;
+  for (int k = 1; k < d; ++k) WT[k] = (double*)ws.take((size_t)l[k] * R[k] * 8);
+  for (int k = 1; k + 1 < d; ++k) t1max = std::max<size_t>(t1max, (size_t)(R[k] * n[k] * l[k + 1]));
+  for (int k = 0; k + 1 < d; ++k) {
+    gmax = std::max<size_t>(gmax, (size_t)(p[k] * n[k] * R[k + 1]));
+    zmax = std::max<size_t>(zmax, (size_t)(p[k] * n[k] * l[k + 1]));
+    mmax = std::max<size_t>(mmax, (size_t)(p[k + 1] * R[k + 1]));
+    pmax = std::max<size_t>(pmax, (size_t)p[k + 1]);
+  }
+  double* T1 = (double*)ws.take(t1max * 8);
+  double* Gb[2] = {(double*)ws.take(gmax * 8), (double*)ws.take(gmax * 8)};
+  double* Z = (double*)ws.take(zmax * 8);
+  double* Mb = (double*)ws.take(mmax * 8);
+  double* Xs = (double*)ws.take((size_t)(R[d - 1] * n[d - 1]) * 8);
+  double* eye = (double*)ws.take(pmax * pmax * 8);
+  int64_t need = 0;
+  for (int k = 0; k < d; ++k) need += p[k] * n[k] * p[k + 1];
+  tt_vec res = *out;
+  for (int k = 0; k <= d; ++k) res.r[k] = p[k];
+  if (delta > 0.0) {
+    res.data = ws.take((size_t)need * 8);
+    res.capacity = need;
+  } else if (out->capacity < need) {
+    return fail(c, TT_ECAPACITY, "randomized rounding: out capacity " + std::to_string(out->capacity) + " < " +
+                                     std::to_string(need));
+  }
+  if (c->ws_overflow || !T1 || !Gb[0] || !Gb[1] || !Z || !Mb || !Xs || !eye || (delta > 0.0 && !res.data))
+    return fail(c, TT_ECAPACITY, "workspace too small for randomized rounding: need " + std::to_string(c->required));
+  for (int k = 1; k < d; ++k)
+    if (!WT[k]) return fail(c, TT_ECAPACITY, "workspace too small for randomized rounding");
+  tt_status s;
+  hipError_t e;
+  // ---- sketch contractions, right to left: WT_k (l_k x R_k), block columns per component
+  Gemms gm;
+  for (int k = d - 1; k >= 1; --k) {
+    // T1^c = L(X^c_k) W^c_{k+1}  ((r^c_k n_k) x l_{k+1}); for k = d-1, W_d = 1 and T1^c = X^c_{d-1}
+    std::vector<const double*> t1(nc);
+    if (k + 1 < d) {
+      int64_t off = 0;
+      for (int ci = 0; ci < nc; ++ci) {
+        t1[ci] = T1 + off;
+        gm.add(core(ci, k), rc(ci, k + 1), 1, WT[k + 1] + roff(ci, k + 1), 1, R[k + 1], T1 + off, l[k + 1], 1,
+               rc(ci, k) * n[k], l[k + 1], rc(ci, k + 1));
+        off += rc(ci, k) * n[k] * l[k + 1];
+      }
+      if ((s = gm.run(c)) != TT_OK) return s;
+    } else {
+      for (int ci = 0; ci < nc; ++ci) t1[ci] = core(ci, k);
+    }
+    // WT_k[j][roff + a] = sum_q T1^c[a][q] S_k[j][q]   (q over n_k l_{k+1})
+    const int64_t K = n[k] * l[k + 1];
+    for (int ci = 0; ci < nc; ++ci)
+      gm.add(t1[ci], K, 1, S[k], 1, K, WT[k] + roff(ci, k), 1, R[k], rc(ci, k), l[k], K);
+    if ((s = gm.run(c)) != TT_OK) return s;
+  }
+  // ---- G_0: first cores side by side, with the sum coefficients
+  {
+    std::vector<CopySeg> segs;
+    for (int ci = 0; ci < nc; ++ci)
+      for (int64_t i = 0; i < n[0]; ++i) {
+        CopySeg g;
+        std::memset(&g, 0, sizeof(g));
+        g.src = core(ci, 0) + i * rc(ci, 1);
+        g.dst = Gb[0] + i * R[1] + roff(ci, 1);
+        g.count = rc(ci, 1);
+        g.coef = jb.comps[ci].coef;
+        segs.push_back(g);
+      }
+    if ((s = run_copies(c, segs)) != TT_OK) return s;
+  }
+  // ---- left to right
+  int64_t ooff = 0;
+  for (int k = 0; k + 1 < d; ++k) {
+    double* G = Gb[k & 1];
+    double* Gn = Gb[(k + 1) & 1];
+    const int64_t Mz = p[k] * n[k];
+    // Z = L(G_k) W_{k+1}
+    gm.add(G, R[k + 1], 1, WT[k + 1], 1, R[k + 1], Z, l[k + 1], 1, Mz, l[k + 1], R[k + 1]);
+    if ((s = gm.run(c)) != TT_OK) return s;
+    // Q of Z: tile QR tree, then Q [I; 0] into core k of the result
+    Tree tree;
+    std::string why;
+    if (!plan_tree(ws, tree, Mz, l[k + 1], TT_F64, Z, l[k + 1], 1, &why))
+      return fail(c, c->ws_overflow ? TT_ECAPACITY : TT_ENOTIMPL, "randomized rounding: " + why);
+    if (tree.kr() != p[k + 1]) return fail(c, TT_EINVAL, "randomized rounding: unexpected rank of Z");
+    std::vector<Tree*> trees{&tree};
+    if ((s = launch_levels_factor(c, trees)) != TT_OK) return s;
+    if ((e = launch_eye(eye, (int)p[k + 1], c->stream)) != hipSuccess) return hip_fail(c, e, "eye");
+    double* Qk = (double*)res.data + ooff;
+    std::vector<std::vector<ApplyLevel>> plans(1);
+    plan_apply(ws, tree, eye, p[k + 1], p[k + 1], Qk, TT_F64, p[k + 1], 1, plans[0]);
+    if (c->ws_overflow) return fail(c, TT_ECAPACITY, "workspace too small for randomized rounding: need " +
+                                                         std::to_string(c->required));
+    if ((s = launch_apply_plans(c, plans, TT_F64)) != TT_OK) return s;
+    ooff += Mz * p[k + 1];
+    // M = Q^T L(G_k)   (p_{k+1} x R_{k+1})
+    gm.add(Qk, 1, p[k + 1], G, R[k + 1], 1, Mb, R[k + 1], 1, p[k + 1], R[k + 1], Mz);
+    if ((s = gm.run(c)) != TT_OK) return s;
+    if (k + 2 < d) {
+      // G_{k+1}[a][i][roff_c + b] = sum_b' M[a][roff'_c + b'] X^c_{k+1}[b'][i][b]
+      for (int ci = 0; ci < nc; ++ci)
+        for (int64_t i = 0; i < n[k + 1]; ++i)
+          gm.add(Mb + roff(ci, k + 1), R[k + 1], 1, core(ci, k + 1) + i * rc(ci, k + 2), n[k + 1] * rc(ci, k + 2), 1,
+                 Gn + i * R[k + 2] + roff(ci, k + 2), n[k + 1] * R[k + 2], 1, p[k + 1], rc(ci, k + 2), rc(ci, k + 1));
+      if ((s = gm.run(c)) != TT_OK) return s;
+    } else {
+      // last core: the components' last cores stacked, then M times the stack
+      std::vector<CopySeg> segs;
+      for (int ci = 0; ci < nc; ++ci) {
+        CopySeg g;
+        std::memset(&g, 0, sizeof(g));
+        g.src = core(ci, d - 1);
+        g.dst = Xs + roff(ci, d - 1) * n[d - 1];
+        g.count = rc(ci, d - 1) * n[d - 1];
+        g.coef = 1.0;
+        segs.push_back(g);
+      }
+      if ((s = run_copies(c, segs)) != TT_OK) return s;
+      gm.add(Mb, R[d - 1], 1, Xs, n[d - 1], 1, (double*)res.data + ooff, n[d - 1], 1, p[d - 1], n[d - 1], R[d - 1]);
+      if ((s = gm.run(c)) != TT_OK) return s;
+    }
+  }
+  if (delta > 0.0) {
+    static const double one = 1.0;
+    tt_sum rs{1, &one, &res};
+    std::vector<RJob> jobs(1);
+    make_job(c, &rs, delta, 0, out, jobs[0]);
+    if ((s = round_jobs(c, jobs)) != TT_OK) return s;
+    if (jobs[0].status != TT_OK) return fail(c, jobs[0].status, "randomized rounding: output capacity");
+  } else {
+    for (int k = 0; k <= d; ++k) out->r[k] = p[k];
+  }
+  return TT_OK;
+}
+
 }  // namespace tto

@@ -17,7 +17,8 @@ import threading
 import numpy as np
 import torch
 
-__all__ = ["TT", "dot", "dot_batched", "axpy", "norm", "round", "round_batched", "orthogonalize", "loo", "laplacian",
+__all__ = ["TT", "dot", "dot_batched", "axpy", "norm", "round", "round_batched", "round_randomized", "orthogonalize",
+           "loo", "laplacian",
            "krylov_laplacian",
            "Engine", "TTError", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
 
@@ -110,6 +111,8 @@ def _load():
         lib.tt_orthogonalize.restype = C.c_int
         lib.tt_loo.argtypes = [P, C.c_int32, C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.tt_loo.restype = C.c_int
+        lib.tt_round_randomized.argtypes = [P, C.POINTER(_Sum), C.POINTER(_Vec), C.c_double, C.POINTER(_Vec)]
+        lib.tt_round_randomized.restype = C.c_int
         lib.tt_laplacian.argtypes = [P, C.POINTER(_Vec), C.c_double, C.POINTER(_Vec)]
         lib.tt_laplacian.restype = C.c_int
         lib.tt_krylov_laplacian.argtypes = [P, C.c_int32, C.POINTER(_Vec)]
@@ -295,6 +298,27 @@ def axpy(alpha: float, x: TT, y: TT) -> TT:
     ctx.check(ctx.lib.tt_axpy(ctx.h, float(alpha), C.byref(vx), C.byref(vy), C.byref(vz)))
     z.r = [int(vz.r[k]) for k in range(x.d + 1)]
     return z
+
+
+def round_randomized(x, sketch: TT, delta: float = 0.0):
+    """Randomize-then-Orthogonalize rounding of a TT or lazy sum with the given Gaussian sketch TT
+    (FP64); delta > 0 rounds the result deterministically afterwards."""
+    h = _SumHolder(x)
+    first = h.tts[0]
+    ctx = _ctx(first.data.device.index)
+    d = first.d
+    p = [1] * (d + 1)
+    for k in range(1, d):
+        p[k] = min(sketch.r[k], p[k - 1] * first.n[k - 1])
+    cap = sum(p[k] * first.n[k] * p[k + 1] for k in range(d))
+    if d == 1:
+        cap = first.n[0]
+    out = TT(torch.empty(max(cap, 1), dtype=first.dtype, device=first.data.device), first.n, [1] * (d + 1))
+    vo = out._vec()
+    vs = sketch._vec()
+    ctx.ensure_ws(64 << 20)
+    ctx.call_with_ws(lambda: ctx.lib.tt_round_randomized(ctx.h, C.byref(h.s), C.byref(vs), float(delta), C.byref(vo)))
+    return _finish_out(out, vo)
 
 
 def laplacian(x: TT, alpha: float = 1.0) -> TT:
