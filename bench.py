@@ -221,6 +221,56 @@ def cpu_baseline_householder(reps_seconds=10.0):
             "sample": f"{n} FP64 NumPy/LAPACK TT-Householder calls on the same workload ({dt:.1f} s)"}
 
 
+RTO_DESC = ("randomized rounding (Randomize-then-Orthogonalize) of the headline lazy sum in FP64: Gaussian sketch "
+            "TT of ranks 30 (seed 50001), then deterministic rounding at delta=1e-4")
+
+
+def rto_inputs(tt, torch, np_mod):
+    from paper_2211_08770_amd import synth
+    terms = synth.sum_of_graded_terms(dtype=np_mod.float64)
+    sk = synth.random_tt(synth.rng(50001), [32] * 8, [1] + [30] * 7 + [1])
+    return terms, sk
+
+
+def run_randomized(tt, torch, steps=10):
+    """Randomized rounding of the graded sum (FP64): roundings/s, error, ranks."""
+    import numpy as np
+    terms, sk = rto_inputs(tt, torch, np)
+    x = [(a, tt.TT.from_cores(c, device="cuda", dtype=torch.float64)) for a, c in terms]
+    s_dev = tt.TT.from_cores(sk, device="cuda", dtype=torch.float64)
+    out = tt.round_randomized(x, s_dev, 1e-4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = tt.round_randomized(x, s_dev, 1e-4)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    nx = tt.norm(x)
+    return {"value": round(1.0 / dt, 3), "unit": "TT-roundings/s", "ms_per_step": round(1e3 * dt, 4),
+            "rel_err": tt.norm(x + [(-1.0, out)]) / nx, "out_ranks": out.r, "workload": RTO_DESC}
+
+
+def cpu_baseline_randomized(seconds=5.0):
+    import numpy as np
+    import oracle
+    terms, sk = rto_inputs(None, None, np)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.tt_round_rto(terms, sk, 1e-4)
+        n += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    return {"value": n / dt, "unit": "TT-roundings/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"{n} FP64 NumPy randomized roundings of the same sum with the same sketch ({dt:.1f} s)"}
+
+
 PAPER_SCHEMES = ["cgs", "mgs", "cgs2", "mgs2", "gram", "householder"]
 PAPER_DESC = ("Section 4 order-3 experiment: m=20 Krylov TT-vectors of the Dirichlet Laplacian (d=3, n=15; ones, "
               "-Delta_d, rank-one rounding, normalisation) generated on the GPU, then each scheme at delta=1e-5, FP64")
@@ -373,10 +423,12 @@ def main():
         line["serving"] = run_serving(torch)
         line["householder"] = run_householder(tt, torch)
         line["paper_experiment"] = run_paper_experiment(tt, torch)
+        line["randomized"] = run_randomized(tt, torch)
     if not args.no_cpu and not args.headline_only:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
         line["householder"]["cpu_baseline"] = cpu_baseline_householder()
         line["paper_experiment"]["cpu_baseline"] = cpu_baseline_paper_experiment()
+        line["randomized"]["cpu_baseline"] = cpu_baseline_randomized()
     print(json.dumps(line))
 
 
