@@ -130,7 +130,8 @@ __device__ inline void rotation(double al, double be, double ga, double& c, doub
 // accesses compile to LDS instructions; otherwise Ag / Jg in global memory.
 // A group of GL lanes handles one pair; EPL > 0 (lda == GL * EPL) keeps the
 // pair's two columns in registers between the dot products and the rotation.
-// Returns the number of sweeps used.
+// rots[0] / rots[1] (shared): a rotation / a rotation with cosine above
+// sqrt(tol) took place in the current sweep.  Returns the number of sweeps used.
 template <bool SH, int GL, int EPL>
 __device__ __attribute__((always_inline)) int jacobi(double* Ag, double* Jg, bool with_j, int len, int lda,
                                                      int k, int* rots) {
@@ -145,7 +146,10 @@ __device__ __attribute__((always_inline)) int jacobi(double* Ag, double* Jg, boo
   const double tol2 = tol * tol;
   int sweep = 0;
   for (; sweep < 64 && kp >= 2; ++sweep) {
-    if (tid == 0) *rots = 0;
+    if (tid == 0) {
+      rots[0] = 0;
+      rots[1] = 0;
+    }
     __syncthreads();
     for (int round = 0; round < kp - 1; ++round) {
       for (int pb = 0; pb < kp / 2; pb += NG) {   // uniform trip count: every group takes part in the sums
@@ -208,14 +212,20 @@ __device__ __attribute__((always_inline)) int jacobi(double* Ag, double* Jg, boo
               jq[i] = s * u + c * v;
             }
           }
-          if (gl == 0) *rots = 1;
+          if (gl == 0) {
+            rots[0] = 1;
+            if (ga * ga > tol * al * be) rots[1] = 1;   // a cosine above sqrt(tol)
+          }
         }
       }
       __syncthreads();
     }
-    const int r = *rots;
+    const int r = rots[0], rbig = rots[1];
     __syncthreads();
-    if (r == 0) break;
+    // no rotation, or only rotations with cosines below sqrt(tol): cyclic Jacobi converges
+    // quadratically, so every pair is now orthogonal to about tol and a further sweep would
+    // only confirm it
+    if (r == 0 || rbig == 0) break;
   }
   return sweep;
 }
@@ -235,7 +245,7 @@ __device__ __attribute__((always_inline)) int jacobi_wave(bool with_j, int len, 
   const double tol2 = tol * tol;
   int sweep = 0;
   for (; sweep < 64 && kp >= 2; ++sweep) {
-    bool rotated = false;
+    bool rotated = false, big = false;
     for (int round = 0; round < kp - 1; ++round) {
       int p = 0, q = 0;
       if (grp < kp / 2) rr_pair(round, grp, kp, p, q);
@@ -281,10 +291,11 @@ __device__ __attribute__((always_inline)) int jacobi_wave(bool with_j, int len, 
           }
         }
         rotated = true;
+        if (ga * ga > tol * al * be) big = true;
       }
       __builtin_amdgcn_wave_barrier();
     }
-    if (__ballot(rotated) == 0) break;
+    if (__ballot(rotated) == 0 || __ballot(big) == 0) break;
   }
   return sweep;
 }
@@ -294,7 +305,7 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   __shared__ int act[MAXC];
   __shared__ double nrm2[MAXC];
   __shared__ double red[NW];
-  __shared__ int rots, kact, lenact, tsel;
+  __shared__ int rots[2], kact, lenact, tsel;
   __shared__ int wcount[NW], wmax[NW];
   __shared__ double edrop;
 
@@ -441,11 +452,11 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
     }
     __syncthreads();
   } else if (k > 0) {
-    if (mode < 0) sweeps = jacobi<false, JGL, 0>(tk.A, tk.acc, !tall, len, lda, k, &rots);
-    else if (mode == 4) sweeps = jacobi<true, JGL, 4>(nullptr, nullptr, !tall, len, lda, k, &rots);
-    else if (mode == 8) sweeps = jacobi<true, JGL, 8>(nullptr, nullptr, !tall, len, lda, k, &rots);
-    else if (mode == 16) sweeps = jacobi<true, JGL, 16>(nullptr, nullptr, !tall, len, lda, k, &rots);
-    else sweeps = jacobi<true, JGL, 0>(nullptr, nullptr, !tall, len, lda, k, &rots);
+    if (mode < 0) sweeps = jacobi<false, JGL, 0>(tk.A, tk.acc, !tall, len, lda, k, rots);
+    else if (mode == 4) sweeps = jacobi<true, JGL, 4>(nullptr, nullptr, !tall, len, lda, k, rots);
+    else if (mode == 8) sweeps = jacobi<true, JGL, 8>(nullptr, nullptr, !tall, len, lda, k, rots);
+    else if (mode == 16) sweeps = jacobi<true, JGL, 16>(nullptr, nullptr, !tall, len, lda, k, rots);
+    else sweeps = jacobi<true, JGL, 0>(nullptr, nullptr, !tall, len, lda, k, rots);
   }
 
   // ---- singular values, order, rank
