@@ -923,6 +923,31 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
   }
   std::vector<hipEvent_t> out_done(maxd, nullptr);
   hipEvent_t last_side = nullptr;
+  // The output cores of step k go to the side stream once the main stream's next step has
+  // been issued: nothing on the critical path reads them, so the next step starts sooner.
+  struct PendingOut {
+    int k = -1;
+    hipEvent_t ready = nullptr;
+    std::vector<std::vector<ApplyLevel>> plans;
+  } pend;
+  auto flush_out = [&]() -> tt_status {
+    if (pend.k < 0) return TT_OK;
+    hipStream_t side = side_stream(c);
+    hipEvent_t done = dep_event(c);
+    if (!side || !done) return fail(c, TT_EDEVICE, "side stream");
+    hipError_t e2;
+    if ((e2 = hipStreamWaitEvent(side, pend.ready, 0)) != hipSuccess) return hip_fail(c, e2, "event");
+    c->upload_stream = side;
+    tt_status r2 = launch_apply_plans(c, pend.plans, dtype, side);
+    c->upload_stream = nullptr;
+    if (r2 != TT_OK) return r2;
+    if ((e2 = hipEventRecord(done, side)) != hipSuccess) return hip_fail(c, e2, "event");
+    out_done[pend.k] = done;
+    last_side = done;
+    pend.k = -1;
+    pend.plans.clear();
+    return TT_OK;
+  };
   for (int k = 0; k + 1 < maxd; ++k) {
     std::vector<int> act;
     for (int j = 0; j < nj; ++j)
@@ -985,6 +1010,10 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
         prof_end(c, pr);
         if (e != hipSuccess) return hip_fail(c, e, "explicit-Q contraction");
       }
+    }
+    {
+      tt_status fs = flush_out();   // output cores of the previous step
+      if (fs != TT_OK) return fs;
     }
     // (2) TSQR of L(C_k), into the tree block of this step's parity once the output
     // core of step k-2 (side stream) no longer reads it
@@ -1051,7 +1080,13 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     if ((e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=
         hipSuccess)
       return hip_fail(c, e, "rank readback");
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "sync");
+    // wait for the ranks by polling an event (wakes up sooner than a blocking synchronisation)
+    hipEvent_t rk_ev = dep_event(c);
+    if (!rk_ev) return fail(c, TT_EDEVICE, "event");
+    if ((e = hipEventRecord(rk_ev, s)) != hipSuccess) return hip_fail(c, e, "event");
+    while ((e = hipEventQuery(rk_ev)) == hipErrorNotReady) {
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "rank readback");
     // (4) output core k = Q_M [U_t; 0]
     std::vector<std::vector<ApplyLevel>> plans;
     for (int j : act) {
@@ -1076,21 +1111,17 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       plans.push_back(std::move(pl));
       js.out_off += sz;
     }
-    // on the side stream: the next step only needs W (already final), not this core
+    // on the side stream, after the next step's first launch: the next step only needs W
+    // (already final), not this core; rk_ev marks the U factor and the tree as ready
     if (!plans.empty()) {
-      hipStream_t side = side_stream(c);
-      hipEvent_t ready = dep_event(c), done = dep_event(c);
-      if (!side || !ready || !done) return fail(c, TT_EDEVICE, "side stream");
-      if ((e = hipEventRecord(ready, s)) != hipSuccess) return hip_fail(c, e, "event");
-      if ((e = hipStreamWaitEvent(side, ready, 0)) != hipSuccess) return hip_fail(c, e, "event");
-      c->upload_stream = side;
-      rs = launch_apply_plans(c, plans, dtype, side);
-      c->upload_stream = nullptr;
-      if (rs != TT_OK) return rs;
-      if ((e = hipEventRecord(done, side)) != hipSuccess) return hip_fail(c, e, "event");
-      out_done[k] = done;
-      last_side = done;
+      pend.k = k;
+      pend.ready = rk_ev;
+      pend.plans = std::move(plans);
     }
+  }
+  {
+    tt_status fs = flush_out();
+    if (fs != TT_OK) return fs;
   }
   // the output cores written on the side stream are complete before anything reads them
   if (last_side && (e = hipStreamWaitEvent(s, last_side, 0)) != hipSuccess) return hip_fail(c, e, "event");
