@@ -1080,13 +1080,11 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     if ((e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=
         hipSuccess)
       return hip_fail(c, e, "rank readback");
-    // wait for the ranks by polling an event (wakes up sooner than a blocking synchronisation)
+    // rk_ev marks the U factors and trees of this step as ready for the side stream
     hipEvent_t rk_ev = dep_event(c);
     if (!rk_ev) return fail(c, TT_EDEVICE, "event");
     if ((e = hipEventRecord(rk_ev, s)) != hipSuccess) return hip_fail(c, e, "event");
-    while ((e = hipEventQuery(rk_ev)) == hipErrorNotReady) {
-    }
-    if (e != hipSuccess) return hip_fail(c, e, "rank readback");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "sync");
     // (4) output core k = Q_M [U_t; 0]
     std::vector<std::vector<ApplyLevel>> plans;
     for (int j : act) {
@@ -1112,11 +1110,17 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       js.out_off += sz;
     }
     // on the side stream, after the next step's first launch: the next step only needs W
-    // (already final), not this core; rk_ev marks the U factor and the tree as ready
+    // (already final), not this core
     if (!plans.empty()) {
       pend.k = k;
       pend.ready = rk_ev;
       pend.plans = std::move(plans);
+      // with many jobs the side stream carries as much work as the main one and planning the
+      // next step takes long: launch the output cores now
+      if (act.size() > 4) {
+        tt_status fs = flush_out();
+        if (fs != TT_OK) return fs;
+      }
     }
   }
   {
