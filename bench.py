@@ -70,15 +70,16 @@ def recorded_traffic(kernel):
     return int(kv["traffic_bytes_per_launch"])
 
 
-def roofline_of(prof):
+def roofline_of(prof, bulk_fp32=True):
     """Roofline object of the kernel kind with the largest device time in a library profile: its
     algorithmic flops over its summed launch durations, against the MFMA peak of its precision."""
     name, p = max(prof.items(), key=lambda kv: kv[1]["ms"])
     achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
     # FP32-bulk leaves are factored and applied on the FP32 MFMA (157.3 TF/s); tree nodes and the SVD are
     # FP64 (78.6 TF/s).  The apply kind mixes leaf and node tiles: it is priced at the FP32 peak, so its
-    # fraction is a lower bound.
-    peak = PEAK["fp32_mfma"] if name in ("qr_factor_leaf", "qr_apply") else PEAK["fp64_mfma"]
+    # fraction is a lower bound.  An FP64 workload runs every kind on the FP64 units.
+    fp32_kinds = ("qr_factor_leaf", "qr_apply") if bulk_fp32 else ()
+    peak = PEAK["fp32_mfma"] if name in fp32_kinds else PEAK["fp64_mfma"]
     return {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5), "traffic": None, "kernel": name,
             "avg_launch_ms": round(p["ms"] / max(p["launches"], 1), 5), "launches": p["launches"],
@@ -192,7 +193,7 @@ def run_householder(tt, torch, reps=5):
     return {"value": round(1.0 / dt, 3), "unit": "orthogonalizations/s", "ms_per_call": round(1e3 * dt, 3),
             "device_busy_ms": round(busy, 3), "rounds": st["rounds"], "max_loo": float(max(loo)),
             "max_pre_rank": st["max_pre_rank"], "max_post_rank": st["max_post_rank"],
-            "roofline": roofline_of(prof), "workload": HH_DESC}
+            "roofline": roofline_of(prof, bulk_fp32=False), "workload": HH_DESC}
 
 
 def cpu_baseline_householder(reps_seconds=10.0):
