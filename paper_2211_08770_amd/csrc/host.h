@@ -2,6 +2,7 @@
 // batched TT-round pipeline.  Only host code lives here; every arithmetic step
 // of the method runs in the kernels declared in common.h.
 #pragma once
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -83,6 +84,22 @@ template <typename T>
 T* upload(tt_ctx* c, const std::vector<T>& v) {
   if (v.empty()) return nullptr;
   return (T*)upload_bytes(c, v.data(), v.size() * sizeof(T));
+}
+// two host arrays in one upload (one copy on the stream); b starts at a 256-byte boundary
+template <typename A, typename B>
+bool upload_pair(tt_ctx* c, const std::vector<A>& a, const std::vector<B>& b, const A** da, const B** db) {
+  *da = nullptr;
+  *db = nullptr;
+  if (a.empty() && b.empty()) return true;
+  const size_t na = a.size() * sizeof(A), off = (na + 255) & ~(size_t)255, nb = b.size() * sizeof(B);
+  std::vector<char> h(off + nb);
+  if (na) std::memcpy(h.data(), a.data(), na);
+  if (nb) std::memcpy(h.data() + off, b.data(), nb);
+  char* d = (char*)upload_bytes(c, h.data(), h.size());
+  if (!d) return false;
+  *da = a.empty() ? nullptr : (const A*)d;
+  *db = b.empty() ? nullptr : (const B*)(d + off);
+  return true;
 }
 void* dev_scratch(tt_ctx* c, size_t bytes);
 

@@ -455,9 +455,8 @@ tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
           }
         }
         if (tasks.empty()) continue;
-        const QrTask* dt = upload(c, tasks);
-        const QrTask* dc = children.empty() ? nullptr : upload(c, children);
-        if (!dt || (!children.empty() && !dc)) return fail(c, TT_ENOMEM, "task upload");
+        const QrTask *dt = nullptr, *dc = nullptr;
+        if (!upload_pair(c, tasks, children, &dt, &dc) || !dt) return fail(c, TT_ENOMEM, "task upload");
         double fl = 0.0, by = 0.0;
         if (c->prof)
           for (const QrTask& q : tasks) {
@@ -885,8 +884,9 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
         max_n = std::max(max_n, g.N);
       }
     }
-    const GemmTask* dgt = upload(c, gt);
-    const GemmPart* dgp = upload(c, gp);
+    const GemmTask* dgt = nullptr;
+    const GemmPart* dgp = nullptr;
+    if (!upload_pair(c, gt, gp, &dgt, &dgp)) return fail(c, TT_ENOMEM, "task upload");
     double gfl = 0.0, gby = 0.0;
     for (const GemmTask& g : gt)
       for (int pi = 0; pi < g.nparts; ++pi) {
