@@ -138,3 +138,26 @@ def test_round_is_deterministic():
     a = tt.round(dev_sum(terms), 1e-6)
     b = tt.round(dev_sum(terms), 1e-6)
     assert a.r == b.r and torch.equal(a.data, b.data)
+
+
+def test_round_maximum_order():
+    # d = 64, the largest order the library takes: 63 dependent steps in each sweep
+    terms = rand_terms(320, [2] * 64, [[1] + [2] * 63 + [1], [1] + [1] * 63 + [1]], coefs=[1.0, -0.5])
+    check_round(terms, 1e-10, torch.float64)
+
+
+def test_round_order_above_maximum_is_rejected():
+    tt = need_gpu()
+    from paper_2211_08770_amd.tt import TT
+    x = TT(torch.ones(65 * 2, dtype=torch.float64, device="cuda"), [2] * 65, [1] * 66)
+    with pytest.raises(Exception):
+        tt.round(x, 1e-8)
+
+
+def test_round_at_the_tile_limits():
+    # 40 components of rank 10 on order 4, n = 32: the right-to-left unfoldings are 1024 x 400,
+    # the most columns a tile tree takes above 800 rows (nodes of two stacked 400 x 400
+    # triangles fill an 800-row tile)
+    terms = rand_terms(321, [32, 32, 32, 32], [[1, 10, 10, 10, 1]] * 40,
+                       scales=[2.0 ** -(j % 7) for j in range(40)])
+    check_round(terms, 1e-6, torch.float64)
