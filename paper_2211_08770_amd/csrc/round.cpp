@@ -1360,6 +1360,8 @@ tt_status round_randomized(tt_ctx* c, const tt_sum* x, const tt_vec* sk, double 
     std::string why;
     if (!plan_tree(ws, tree, Mz, l[k + 1], TT_F64, Z, l[k + 1], 1, &why))
       return fail(c, c->ws_overflow ? TT_ECAPACITY : TT_ENOTIMPL, "randomized rounding: " + why);
+    if (c->ws_overflow)   // a tile or T buffer of the tree did not fit: launch nothing
+      return fail(c, TT_ECAPACITY, "workspace too small for randomized rounding: need " + std::to_string(c->required));
     if (tree.kr() != p[k + 1]) return fail(c, TT_EINVAL, "randomized rounding: unexpected rank of Z");
     std::vector<Tree*> trees{&tree};
     if ((s = launch_levels_factor(c, trees)) != TT_OK) return s;
