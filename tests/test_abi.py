@@ -24,7 +24,8 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("tt_round", "tt_round_batched", "tt_norm", "tt_engine_step", "tt_axpy", "tt_dot", "tt_dot_batched",
-                     "tt_orthogonalize", "tt_loo", "tt_ctx_create", "tt_ctx_destroy"):
+                     "tt_orthogonalize", "tt_loo", "tt_ctx_create", "tt_ctx_destroy", "tt_laplacian",
+                     "tt_krylov_laplacian", "tt_round_randomized"):
         assert required in names
 
 
@@ -51,3 +52,12 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(tt, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         tt._load()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
