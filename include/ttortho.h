@@ -197,8 +197,10 @@ tt_status tt_orthogonalize(tt_ctx* ctx, tt_scheme scheme, int32_t m, const tt_su
  * contractions of x and the sketch from the right; from the left, core k of
  * the result is Q of Z_k = L(G_k) W_{k+1} and M_k = Q^T L(G_k) is absorbed into
  * core k+1.  Result ranks min(l_k, p_{k-1} n_k); with delta > 0 the result is
- * then rounded deterministically at delta (as tt_round).  FP64 only (else
- * TT_ENOTIMPL); d = 1 returns the (rounded) sum.  out: device, capacity set
+ * then rounded deterministically at delta (as tt_round).  The sketch is FP64;
+ * x and out are FP64, or FP32 (the components are converted to FP64 in the
+ * workspace, the sweep runs in FP64, its result is converted back and the
+ * rounding at delta is FP32-bulk); d = 1 returns the (rounded) sum.  out: device, capacity set
  * by the caller (out->r written).  No QR of the R_k-column unfoldings of the
  * sum is formed, so R_k may exceed the tile limits of tt_round; the sketch
  * ranks must keep Z_k within them (TT_ENOTIMPL otherwise). */

@@ -1038,10 +1038,11 @@ tt_status tt_round_randomized(tt_ctx* c, const tt_sum* x, const tt_vec* sketch, 
   if ((s = check_vec(c, sketch, "sketch", true)) != TT_OK) return s;
   if ((s = check_vec(c, out, "out", false)) != TT_OK) return s;
   const tt_vec& s0 = x->comp[0];
-  if (s0.dtype != TT_F64 || sketch->dtype != TT_F64 || out->dtype != TT_F64)
-    return fail(c, TT_ENOTIMPL, "randomized rounding: FP64 only");
-  if (!same_shape(s0, *sketch) || !same_shape(s0, *out))
-    return fail(c, TT_EINVAL, "randomized rounding: x, sketch and out differ in d or n");
+  if (sketch->dtype != TT_F64) return fail(c, TT_EINVAL, "randomized rounding: the sketch must be FP64");
+  bool shape_ok = sketch->d == s0.d;
+  for (int k = 0; shape_ok && k < s0.d; ++k) shape_ok = sketch->n[k] == s0.n[k];
+  if (!shape_ok || !same_shape(s0, *out))
+    return fail(c, TT_EINVAL, "randomized rounding: x, sketch and out differ in d or n (or x and out in dtype)");
   if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(c, TT_EINVAL, "randomized rounding: delta must be >= 0");
   for (int k = 1; k < s0.d; ++k)
     if (sketch->r[k] > 1024) return fail(c, TT_ENOTIMPL, "randomized rounding: sketch rank above 1024");

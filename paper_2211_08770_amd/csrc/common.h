@@ -207,6 +207,8 @@ hipError_t launch_hh_qcoef(const double* EU, const double* G, double* D, int m, 
 hipError_t launch_laplacian_core(int dtype, const void* X, int64_t r0, int64_t n, int64_t r1, int kind, double alpha,
                                  void* Y, hipStream_t s);
 hipError_t launch_fill_const(int dtype, void* x, int64_t n, double v, hipStream_t s);
+// y[0..n) = x[0..n) converted from src_dtype to dst_dtype (0 f64, 1 f32)
+hipError_t launch_cast(int src_dtype, const void* x, int dst_dtype, void* y, int64_t n, hipStream_t s);
 // out[j] = a[j] + b[j]
 hipError_t launch_add(const double* a, const double* b, double* out, int n, hipStream_t s);
 hipError_t launch_neg(const double* a, double* out, int n, hipStream_t s);

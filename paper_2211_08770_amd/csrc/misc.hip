@@ -351,6 +351,12 @@ __global__ void k_laplacian_core(const T* __restrict__ X, int64_t r0, int64_t n,
   Y[e] = (T)v;
 }
 
+template <typename TS, typename TD>
+__global__ void k_cast(const TS* __restrict__ x, TD* __restrict__ y, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) y[e] = (TD)x[e];
+}
+
 template <typename T>
 __global__ void k_fill_const(T* __restrict__ x, int64_t n, double v) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -444,6 +450,18 @@ hipError_t launch_laplacian_core(int dtype, const void* X, int64_t r0, int64_t n
   else
     hipLaunchKernelGGL(k_laplacian_core<float>, dim3((unsigned)blocks), dim3(256), 0, s, (const float*)X, r0, n, r1,
                        kind, alpha, (float*)Y);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(int src_dtype, const void* x, int dst_dtype, void* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 g((unsigned)blocks), b(256);
+  if (src_dtype == 1 && dst_dtype == 0) hipLaunchKernelGGL((k_cast<float, double>), g, b, 0, s, (const float*)x, (double*)y, n);
+  else if (src_dtype == 0 && dst_dtype == 1) hipLaunchKernelGGL((k_cast<double, float>), g, b, 0, s, (const double*)x, (float*)y, n);
+  else if (src_dtype == 0) hipLaunchKernelGGL((k_cast<double, double>), g, b, 0, s, (const double*)x, (double*)y, n);
+  else hipLaunchKernelGGL((k_cast<float, float>), g, b, 0, s, (const float*)x, (float*)y, n);
   return hipGetLastError();
 }
 

@@ -1263,6 +1263,20 @@ tt_status round_randomized(tt_ctx* c, const tt_sum* x, const tt_vec* sk, double 
   auto roff = [&](int ci, int k) { return jb.roff[(size_t)ci * (d + 1) + k]; };
   auto core = [&](int ci, int k) { return (const double*)jb.comps[ci].data + jb.comps[ci].core_off[k]; };
   auto rc = [&](int ci, int k) { return jb.comps[ci].r[k]; };
+  // FP32 storage: the components are converted to FP64 in the workspace, the sweep runs in
+  // FP64 and its result is converted back before the rounding at delta (FP32-bulk)
+  const bool f32 = (jb.dtype == TT_F32);
+  if (f32) {
+    for (int ci = 0; ci < nc; ++ci) {
+      int64_t sz = 0;
+      for (int k = 0; k < d; ++k) sz += rc(ci, k) * n[k] * rc(ci, k + 1);
+      double* cp = (double*)ws_alloc(c, (size_t)sz * 8);
+      if (!cp) return fail(c, TT_ECAPACITY, "workspace too small for randomized rounding: need " + std::to_string(c->required));
+      hipError_t ce = launch_cast(TT_F32, jb.comps[ci].data, TT_F64, cp, sz, c->stream);
+      if (ce != hipSuccess) return hip_fail(c, ce, "cast");
+      jb.comps[ci].data = (const char*)cp;
+    }
+  }
   // sketch cores
   const double* S[TT_MAXD];
   {
@@ -1294,15 +1308,21 @@ tt_status round_randomized(tt_ctx* c, const tt_sum* x, const tt_vec* sk, double 
   int64_t need = 0;
   for (int k = 0; k < d; ++k) need += p[k] * n[k] * p[k + 1];
   tt_vec res = *out;
+  res.dtype = TT_F64;
   for (int k = 0; k <= d; ++k) res.r[k] = p[k];
-  if (delta > 0.0) {
+  void* res32 = nullptr;   // FP32 copy of the result, rounded at delta into out
+  if (delta > 0.0 || f32) {
     res.data = ws.take((size_t)need * 8);
     res.capacity = need;
-  } else if (out->capacity < need) {
+    if (f32 && delta > 0.0) res32 = ws.take((size_t)need * 4);
+    if ((f32 && delta > 0.0 && !res32))
+      return fail(c, TT_ECAPACITY, "workspace too small for randomized rounding: need " + std::to_string(c->required));
+  }
+  if (delta <= 0.0 && out->capacity < need) {
     return fail(c, TT_ECAPACITY, "randomized rounding: out capacity " + std::to_string(out->capacity) + " < " +
                                      std::to_string(need));
   }
-  if (c->ws_overflow || !T1 || !Gb[0] || !Gb[1] || !Z || !Mb || !Xs || !eye || (delta > 0.0 && !res.data))
+  if (c->ws_overflow || !T1 || !Gb[0] || !Gb[1] || !Z || !Mb || !Xs || !eye || ((delta > 0.0 || f32) && !res.data))
     return fail(c, TT_ECAPACITY, "workspace too small for randomized rounding: need " + std::to_string(c->required));
   for (int k = 1; k < d; ++k)
     if (!WT[k]) return fail(c, TT_ECAPACITY, "workspace too small for randomized rounding");
@@ -1400,9 +1420,15 @@ tt_status round_randomized(tt_ctx* c, const tt_sum* x, const tt_vec* sk, double 
       if ((s = gm.run(c)) != TT_OK) return s;
     }
   }
+  tt_vec fin = res;   // the result in the storage precision
+  if (f32) {
+    fin.dtype = TT_F32;
+    fin.data = (delta > 0.0) ? res32 : out->data;
+    if ((e = launch_cast(TT_F64, res.data, TT_F32, fin.data, need, c->stream)) != hipSuccess) return hip_fail(c, e, "cast");
+  }
   if (delta > 0.0) {
     static const double one = 1.0;
-    tt_sum rs{1, &one, &res};
+    tt_sum rs{1, &one, &fin};
     std::vector<RJob> jobs(1);
     make_job(c, &rs, delta, 0, out, jobs[0]);
     if ((s = round_jobs(c, jobs)) != TT_OK) return s;

@@ -3,7 +3,7 @@
 Both sides get the same lazy sum and the same Gaussian sketch TT-vector (the
 random numbers of the method are an input), so the results are compared by
 the norm of their difference (cores differ only by orthogonal factors) and by
-their ranks, at 1e-12 relative in FP64.
+their ranks, at 1e-12 relative in FP64 and max(delta, 1e-5) with FP32 storage.
 """
 import numpy as np
 import pytest
@@ -75,13 +75,28 @@ def test_randomized_rounds_a_sum_beyond_the_tile_limits():
     assert diff_norm(host_cores(out), ref) <= 1e-10 * oracle.tt_norm(ref)
 
 
-def test_randomized_rejects_fp32_and_mismatched_sketch():
+@pytest.mark.parametrize("delta", [0.0, 1e-4])
+def test_randomized_fp32_storage(delta):
+    # FP32 components (converted to FP64 for the sweep, the result stored in FP32 and rounded
+    # FP32-bulk): within max(delta, 1e-5) of the oracle on the same FP32 values and sketch
+    tt = need_gpu()
+    terms32 = [(a, [c.astype(np.float32) for c in x]) for a, x in graded(100, [8, 8, 8, 8], 6, 4)]
+    terms64 = [(a, [c.astype(np.float64) for c in x]) for a, x in terms32]
+    sk = synth.random_tt(synth.rng(101), [8, 8, 8, 8], [1, 8, 20, 8, 1])
+    ref = oracle.tt_round_rto(terms64, sk, delta)
+    out = tt.round_randomized(dev_sum(terms32, torch.float32), dev_tt(sk), delta)
+    assert out.dtype == torch.float32
+    assert out.r == oracle.tt_ranks(ref)
+    assert diff_norm(host_cores(out), ref) <= max(delta, 1e-5) * oracle.tt_norm(ref)
+
+
+def test_randomized_rejects_fp32_sketch_and_mismatched_sketch():
     tt = need_gpu()
     g = synth.rng(99)
     x = synth.random_tt(g, [4, 4, 4], [1, 2, 2, 1])
     with pytest.raises(tt.TTError) as ei:
-        tt.round_randomized(dev_tt(x, torch.float32), dev_tt(synth.random_tt(g, [4, 4, 4], [1, 2, 2, 1]), torch.float32))
-    assert ei.value.status == "TT_ENOTIMPL"
+        tt.round_randomized(dev_tt(x), dev_tt(synth.random_tt(g, [4, 4, 4], [1, 2, 2, 1]), torch.float32))
+    assert ei.value.status == "TT_EINVAL"
     with pytest.raises(tt.TTError) as ei:
         tt.round_randomized(dev_tt(x), dev_tt(synth.random_tt(g, [4, 5, 4], [1, 2, 2, 1])))
     assert ei.value.status == "TT_EINVAL"
