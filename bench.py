@@ -78,9 +78,15 @@ def roofline_of(prof, bulk_fp32=True):
     # FP32-bulk leaves are factored and applied on the FP32 MFMA (157.3 TF/s); tree nodes and the SVD are
     # FP64 (78.6 TF/s).  The apply kind mixes leaf and node tiles: it is priced at the FP32 peak, so its
     # fraction is a lower bound.  An FP64 workload runs every kind on the FP64 units.
-    fp32_kinds = ("qr_factor_leaf", "qr_apply") if bulk_fp32 else ()
-    peak = PEAK["fp32_mfma"] if name in fp32_kinds else PEAK["fp64_mfma"]
-    return {"bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+    # The Jacobi SVD, the component GEMMs and the TT dots run on the vector ALU ("alu"; the
+    # component GEMMs are FP32 in an FP32-bulk workload), the tile QR kernels on MFMA.
+    alu = name in ("svd_jacobi", "contraction_gemm", "tt_dot", "other")
+    if alu:
+        peak = PEAK["fp32_vector"] if (bulk_fp32 and name == "contraction_gemm") else PEAK["fp64_vector"]
+    else:
+        fp32_kinds = ("qr_factor_leaf", "qr_apply") if bulk_fp32 else ()
+        peak = PEAK["fp32_mfma"] if name in fp32_kinds else PEAK["fp64_mfma"]
+    return {"bound": "alu" if alu else "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5), "traffic": None, "kernel": name,
             "avg_launch_ms": round(p["ms"] / max(p["launches"], 1), 5), "launches": p["launches"],
             "share_of_kernel_time": round(p["ms"] / sum(v["ms"] for v in prof.values()), 4)}
@@ -247,8 +253,17 @@ def run_randomized(tt, torch, steps=10):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     nx = tt.norm(x)
+    # one more call with the library profiler on (not part of the rate): the dominant kernel kind
+    ctx = tt._ctx()
+    ctx.lib.tt_ctx_set_profiling.argtypes = [C.c_void_p, C.c_int]
+    ctx.lib.tt_ctx_set_profiling(ctx.h, 1)
+    tt.round_randomized(x, s_dev, 1e-4)
+    torch.cuda.synchronize()
+    prof = profile_arrays(ctx)
+    ctx.lib.tt_ctx_set_profiling(ctx.h, 0)
     return {"value": round(1.0 / dt, 3), "unit": "TT-roundings/s", "ms_per_step": round(1e3 * dt, 4),
-            "rel_err": tt.norm(x + [(-1.0, out)]) / nx, "out_ranks": out.r, "workload": RTO_DESC}
+            "rel_err": tt.norm(x + [(-1.0, out)]) / nx, "out_ranks": out.r,
+            "roofline": roofline_of(prof, bulk_fp32=False), "workload": RTO_DESC}
 
 
 def cpu_baseline_randomized(seconds=5.0):
