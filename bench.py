@@ -49,6 +49,8 @@ def parse():
                    help="time only the headline configuration (for profiler runs); no FP64 side runs, no CPU baseline")
     p.add_argument("--householder-only", action="store_true",
                    help="only the TT-Householder measurement (for profiler runs); prints its JSON object")
+    p.add_argument("--randomized-only", action="store_true",
+                   help="only the randomized-rounding measurement (for profiler runs); prints its JSON object")
     return p.parse_args()
 
 
@@ -402,6 +404,9 @@ def main():
     tt._load()
     if args.householder_only:
         print(json.dumps(run_householder(tt, torch)))
+        return
+    if args.randomized_only:
+        print(json.dumps(run_randomized(tt, torch)))
         return
     res32 = run_config(tt, torch, torch.float32, 1e-4, args.steps, args.warmup, profile=True)
     if args.headline_only:
