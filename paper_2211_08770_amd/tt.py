@@ -432,6 +432,39 @@ def round_batched(xs, deltas, max_ranks=None):
     return [_finish_out(o, vos[i]) for i, o in enumerate(outs)]
 
 
+def q_rank_bounds(scheme: str, ra, ns, rank_guard: int = 0):
+    """Upper bounds of the bond ranks of every q_i an orthogonalization returns (output capacity).
+
+    ra[i][k]: summed component ranks of input i at bond k.  Bounds: the rank caps of the mode
+    sizes, the pre-round ranks (Gram: sum_{k<=i} rank(a_k); the Gram-Schmidt schemes:
+    rank(a_i) + sum_{j<i} bound(q_j), which also bounds their second pass; Householder:
+    1 + sum_{l<=i} bound(u_l) with u_l <= a_l + sum_{j<l} u_j + l canonical terms + 1) and the
+    rank guard.
+    """
+    d = len(ns)
+    caps = [1]
+    for k in range(1, d):
+        caps.append(min(int(np.prod(ns[:k], dtype=object)), int(np.prod(ns[k:], dtype=object))))
+    caps.append(1)
+
+    def capped(b):
+        return [1 if k in (0, d) else min(b[k], caps[k], rank_guard if rank_guard > 0 else b[k]) for k in range(d + 1)]
+    bounds, acc, ubounds = [], [0] * (d + 1), []
+    for i in range(len(ra)):
+        if scheme == "gram":
+            acc = [acc[k] + ra[i][k] for k in range(d + 1)]
+            b = list(acc)
+        elif scheme == "householder":
+            bw = capped([ra[i][k] + sum(u[k] for u in ubounds) for k in range(d + 1)])
+            b1 = capped([bw[k] + i for k in range(d + 1)])
+            ubounds.append(capped([b1[k] + 1 for k in range(d + 1)]))
+            b = [1 + sum(u[k] for u in ubounds) for k in range(d + 1)]
+        else:
+            b = [ra[i][k] + sum(bb[k] for bb in bounds) for k in range(d + 1)]
+        bounds.append(capped(b))
+    return bounds
+
+
 def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: bool = True, q_capacity=None,
                   partial_on_guard: bool = False):
     """Q, R (and the LOO curve) of the TT vectors / lazy sums A (Algorithms 1-8).
@@ -444,32 +477,9 @@ def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: b
     first = hs[0].tts[0]
     ctx = _ctx(first.data.device.index)
     sums = (_Sum * m)(*[h.s for h in hs])
-    # output capacity of q_i: bond ranks bounded by the rank caps of the mode sizes, by the pre-round
-    # ranks (Gram: sum_{k<=i} rank(a_k); the Gram-Schmidt schemes: rank(a_i) + sum_{j<i} bound(q_j),
-    # which also bounds their second pass) and by the rank guard
     d = first.d
-    caps = [1]
-    for k in range(1, d):
-        caps.append(min(int(np.prod(first.n[:k], dtype=object)), int(np.prod(first.n[k:], dtype=object))))
-    caps.append(1)
     ra = [[sum(t.r[k] for t in h.tts) for k in range(d + 1)] for h in hs]
-
-    def capped(b):
-        return [1 if k in (0, d) else min(b[k], caps[k], rank_guard if rank_guard > 0 else b[k]) for k in range(d + 1)]
-    bounds, acc = [], [0] * (d + 1)
-    ubounds = []          # Householder: bounds of the u_i (w_i <= a_i + sum u_l; + i canonical terms; + 1)
-    for i in range(m):
-        if scheme == "gram":
-            acc = [acc[k] + ra[i][k] for k in range(d + 1)]
-            b = list(acc)
-        elif scheme == "householder":
-            bw = capped([ra[i][k] + sum(u[k] for u in ubounds) for k in range(d + 1)])
-            b1 = capped([bw[k] + i for k in range(d + 1)])
-            ubounds.append(capped([b1[k] + 1 for k in range(d + 1)]))
-            b = [1 + sum(u[k] for u in ubounds) for k in range(d + 1)]
-        else:
-            b = [ra[i][k] + sum(bb[k] for bb in bounds) for k in range(d + 1)]
-        bounds.append(capped(b))
+    bounds = q_rank_bounds(scheme, ra, first.n, rank_guard)
     sizes = [sum(b[k] * first.n[k] * b[k + 1] for k in range(d)) for b in bounds]
     if q_capacity is not None:
         sizes = [min(sz, int(q_capacity)) for sz in sizes]
