@@ -203,7 +203,13 @@ tt_status tt_orthogonalize(tt_ctx* ctx, tt_scheme scheme, int32_t m, const tt_su
  * rounding at delta is FP32-bulk); d = 1 returns the (rounded) sum.  out: device, capacity set
  * by the caller (out->r written).  No QR of the R_k-column unfoldings of the
  * sum is formed, so R_k may exceed the tile limits of tt_round; the sketch
- * ranks must keep Z_k within them (TT_ENOTIMPL otherwise). */
+ * ranks must keep Z_k within them.  Works in the context workspace (the
+ * sketch contractions, the sketched cores and their QR trees; FP32 inputs add
+ * an FP64 copy of the components).  Errors: TT_EINVAL (shapes, an FP32
+ * sketch, x and out differing in dtype, delta < 0), TT_ECAPACITY (out or the
+ * workspace too small; the required workspace is then reported by
+ * tt_ctx_required_bytes), TT_ENOTIMPL (a sketch rank above 1024, or a sketched
+ * core beyond the tile limits). */
 tt_status tt_round_randomized(tt_ctx* ctx, const tt_sum* x, const tt_vec* sketch, double delta, tt_vec* out);
 
 /* y = alpha * Delta_d x: the discrete Laplacian of order d with Dirichlet
