@@ -125,3 +125,55 @@ def test_lapack_pin_catches_cancelling_householder_sign(monkeypatch):
 
 def test_lapack_pin_catches_reversed_canonical_order(monkeypatch):
     assert not _householder_vs_lapack(monkeypatch, "canonical_index", _canonical_index_last_fastest)
+
+
+def _tt_laplacian_transposed_blocks(cores, alpha=1.0):
+    # slip: interior cores [[X, L X], [0, X]] (the block of the Laplacian in the wrong corner)
+    d = len(cores)
+    X = [np.asarray(c, dtype=np.float64) for c in cores]
+    out = []
+    for k in range(d):
+        r0, n, r1 = X[k].shape
+        LX = oracle.apply_along_mode(oracle.laplacian_1d(n), X[k])
+        if k == 0:
+            Y = np.concatenate([LX, X[k]], axis=2) * alpha
+        elif k == d - 1:
+            Y = np.concatenate([X[k], LX], axis=0)
+        else:
+            Y = np.zeros((2 * r0, n, 2 * r1))
+            Y[:r0, :, :r1] = X[k]
+            Y[:r0, :, r1:] = LX
+            Y[r0:, :, r1:] = X[k]
+        out.append(Y)
+    return out
+
+
+def test_dense_kronecker_pin_catches_misplaced_laplacian_block():
+    g = synth.rng(64)
+    ns = [3, 4, 3]
+    x = synth.random_tt(g, ns, [1, 2, 2, 1])
+    T = tt_full(x)
+    ref = np.zeros_like(T)
+    for k, n in enumerate(ns):
+        ref += np.moveaxis(np.tensordot(oracle.laplacian_1d(n), T, axes=(1, k)), 0, k)
+    assert np.allclose(tt_full(oracle.tt_laplacian(x)), ref, atol=1e-9 * np.abs(ref).max())
+    assert not np.allclose(tt_full(_tt_laplacian_transposed_blocks(x)), ref, atol=1e-3 * np.abs(ref).max())
+
+
+def _rto_wrong_sketch_core(terms, sketch, delta=0.0):
+    # slip: the contraction for bond k uses sketch core k - 1 (off by one) where shapes allow
+    sk = [sketch[0], sketch[0].reshape(sketch[1].shape) if sketch[0].size == sketch[1].size else sketch[1]]
+    return oracle.tt_round_rto(terms, sk, delta)
+
+
+def test_range_finder_pin_catches_a_wrong_sketch():
+    g = synth.rng(65)
+    ns = [6, 6]
+    terms = [(1.0, synth.random_tt(g, ns, [1, 4, 1])), (0.5, synth.random_tt(g, ns, [1, 3, 1]))]
+    sketch = synth.random_tt(g, ns, [1, 3, 1])
+    X = sum(a * tt_full(x) for a, x in terms)
+    Omega = sketch[1][:, :, 0].T
+    Q, _ = np.linalg.qr(X @ Omega)
+    assert np.allclose(tt_full(oracle.tt_round_rto(terms, sketch)), Q @ (Q.T @ X), atol=1e-12)
+    bad = _rto_wrong_sketch_core(terms, sketch)
+    assert not np.allclose(tt_full(bad), Q @ (Q.T @ X), atol=1e-6)
