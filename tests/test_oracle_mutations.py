@@ -177,3 +177,29 @@ def test_range_finder_pin_catches_a_wrong_sketch():
     assert np.allclose(tt_full(oracle.tt_round_rto(terms, sketch)), Q @ (Q.T @ X), atol=1e-12)
     bad = _rto_wrong_sketch_core(terms, sketch)
     assert not np.allclose(tt_full(bad), Q @ (Q.T @ X), atol=1e-6)
+
+
+def _krylov_without_minus(ns, m):
+    # slip: x_{j+1} = +Delta_d a_j
+    x = oracle.tt_ones(ns)
+    A = []
+    for j in range(m):
+        a = oracle.tt_round(x, 0.0, max_rank=1)
+        a = oracle.tt_scale(1.0 / oracle.tt_norm(a), a)
+        A.append(a)
+        x = oracle.tt_laplacian(a, 1.0)
+    return A
+
+
+def test_power_sequence_pin_catches_the_missing_minus_sign():
+    n, m = 7, 4
+    L = oracle.laplacian_1d(n)
+    v, ref = np.ones(n), []
+    for _ in range(m):
+        w = v / np.linalg.norm(v)
+        ref.append(w)
+        v = -L @ w
+    good = oracle.krylov_inputs([n], m)
+    bad = _krylov_without_minus([n], m)
+    assert all(np.allclose(tt_full(a), r, atol=1e-12) for a, r in zip(good, ref))
+    assert not all(np.allclose(tt_full(a), r, atol=1e-6) for a, r in zip(bad, ref))
