@@ -127,7 +127,9 @@ const char* tt_last_error(const tt_ctx* ctx);
 /* <x, y> for two lazy sums (Section 2, Euclidean inner product; used by every
  * algorithm of Section 3).  Computed as sum over component pairs of
  * coef * coef' * <x_c, y_c'>, each by the left-to-right contraction
- * W_k = sum_i X_k(i)^T W_{k-1} Y_k(i).  out: HOST double. */
+ * W_k = sum_i X_k(i)^T W_{k-1} Y_k(i) on the FP64 matrix cores: FP32 cores are
+ * widened exactly, so for either dtype every product and sum is FP64.
+ * out: HOST double. */
 tt_status tt_dot(tt_ctx* ctx, const tt_sum* x, const tt_sum* y, double* out);
 
 /* npairs inner products <xs[p], ys[p]> in one batched launch. out: HOST [npairs]. */
@@ -234,6 +236,18 @@ tt_status tt_krylov_laplacian(tt_ctx* ctx, int32_t m, tt_vec* a);
  * each leading block (symmetric Jacobi on the device).  loo: HOST [m];
  * gram (HOST m*m, nullable) receives Q^T Q. */
 tt_status tt_loo(tt_ctx* ctx, int32_t m, const tt_vec* q, double* loo, double* gram);
+
+/* Condition numbers kappa(A_k) = sigma_max / sigma_min of A_k = [a_0 .. a_{k-1}],
+ * k = 1..m, for m lazy sums of one shape (the conditioning against which
+ * Section 3.4 bounds the loss of orthogonality of each scheme and Section 4
+ * plots it): the FP64 Gram matrix G(i, j) = <a_i, a_j> by TT inner products
+ * (FP64 accumulation for either dtype), then kappa(A_k) = sqrt(kappa(G_k)) from
+ * the singular values of each leading block (symmetric Jacobi on the device).
+ * Meaningful while kappa(G_k) stays well below 1 / u_64, i.e. kappa(A_k) below
+ * about 1e7; beyond that the smallest eigenvalue of G_k is rounding noise.
+ * kappa: HOST [m] (INFINITY where G_k is singular to working precision); gram:
+ * HOST m*m row-major or NULL.  Errors: TT_EINVAL (shapes), TT_ECAPACITY. */
+tt_status tt_cond(tt_ctx* ctx, int32_t m, const tt_sum* a, double* kappa, double* gram);
 
 /* ---------------------------------------------------------------------------
  * Serving engine: continuous batching of orthogonalization requests.

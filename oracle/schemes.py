@@ -36,11 +36,11 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
-from .tt import tt_sum, tt_dot, tt_norm, tt_round, tt_scale, tt_ranks, RoundLog
+from .tt import tt_sum, tt_dot, tt_norm, tt_round, tt_scale, tt_ranks, tt_full, RoundLog
 
 __all__ = ["OrthoResult", "cgs", "mgs", "cgs2", "mgs2", "gram", "householder", "orthogonalize",
            "loo_curve", "gram_of", "SCHEMES", "GramBreakdown", "HouseholderBreakdown", "canonical_index",
-           "canonical_tt", "tth_vec", "apply_h_vec"]
+           "canonical_tt", "tth_vec", "apply_h_vec", "cond_curve"]
 
 SCHEMES = ("cgs", "mgs", "cgs2", "mgs2", "gram")
 
@@ -290,4 +290,18 @@ def loo_curve(Q):
     for k in range(1, len(Q) + 1):
         E = np.eye(k) - G[:k, :k]
         out.append(float(np.max(np.abs(np.linalg.eigvalsh(E)))))
+    return np.array(out)
+
+
+def cond_curve(A):
+    """kappa(A_k) = sigma_max / sigma_min of the matrix whose columns are the
+    vectorised a_1..a_k, k = 1..m (the conditioning that the bounds of Section
+    3.4 and the plots of Section 4 are stated against), from a dense SVD of
+    the full tensors (small dense dimension only)."""
+    cols = [tt_full(tt_sum(_as_sum(a))).ravel() for a in A]
+    Am = np.stack(cols, axis=1)
+    out = []
+    for k in range(1, Am.shape[1] + 1):
+        s = np.linalg.svd(Am[:, :k], compute_uv=False)
+        out.append(float(s[0] / s[-1]) if s[-1] > 0 else np.inf)
     return np.array(out)

@@ -339,7 +339,7 @@ tt_status dot_pairs_idx(tt_ctx* c, int npairs, const tt_sum* xs, const tt_sum* y
   while (i0 < pairs.size()) {
     size_t bytes = 0, i1 = i0;
     while (i1 < pairs.size()) {
-      const size_t need = ((size_t)(2 * pairs[i1].wcap + pairs[i1].tcap) * elt + 511) & ~(size_t)255;
+      const size_t need = ((size_t)(2 * pairs[i1].wcap + pairs[i1].tcap) * sizeof(double) + 511) & ~(size_t)255;
       if (i1 > i0 && bytes + need > budget) break;
       bytes += need;
       ++i1;
@@ -361,10 +361,10 @@ tt_status dot_pairs_idx(tt_ctx* c, int npairs, const tt_sum* xs, const tt_sum* y
       t.coef = pr.coef;
       t.w = scratch + o;
       t.wcap = pr.wcap;
-      o += (size_t)2 * pr.wcap * elt;
+      o += (size_t)2 * pr.wcap * sizeof(double);   // W and tmp are FP64 in both precisions
       o = (o + 255) & ~(size_t)255;
       t.tmp = scratch + o;
-      o += (size_t)pr.tcap * elt;
+      o += (size_t)pr.tcap * sizeof(double);
       o = (o + 255) & ~(size_t)255;
       t.out = slots + i;
       tasks.push_back(t);
@@ -725,7 +725,11 @@ tt_status gram_row(tt_ctx* c, int i, int m, const tt_vec* q, double* Gq) {
   return TT_OK;
 }
 
-tt_status loo_from_gram(tt_ctx* c, const double* Gq, int m, double* loo_host) {
+// Singular values of the leading blocks of the FP64 Gram matrix Gq (m x m):
+// of I - G_k when minus_identity (its largest is ||I_k - Q_k^T Q_k||_2, Section
+// 3.4), else of G_k itself.  sig_host[k-1] receives the k values of block k
+// (sorted decreasing) at offset (k-1)k/2.
+tt_status block_spectra(tt_ctx* c, const double* Gq, int m, int minus_identity, double* sig_host) {
   size_t esz = 0;
   for (int k = 1; k <= m; ++k) esz += (size_t)k * k;
   double* E = (double*)dev_scratch(c, esz * 8);
@@ -735,7 +739,7 @@ tt_status loo_from_gram(tt_ctx* c, const double* Gq, int m, double* loo_host) {
   if (!E || !scratch || !zero || !ranks) return fail(c, TT_ENOMEM, "loo buffers");
   hipError_t e = hipMemsetAsync(zero, 0, 8, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "loo");
-  if ((e = launch_loo_mats(Gq, m, E, c->stream)) != hipSuccess) return hip_fail(c, e, "loo mats");
+  if ((e = launch_loo_mats(Gq, m, E, minus_identity, c->stream)) != hipSuccess) return hip_fail(c, e, "loo mats");
   std::vector<SvdTask> tasks;
   size_t eo = 0, so = 0;
   for (int k = 1; k <= m; ++k) {
@@ -768,10 +772,18 @@ tt_status loo_from_gram(tt_ctx* c, const double* Gq, int m, double* loo_host) {
   const SvdTask* dt = upload(c, tasks);
   if (!dt) return fail(c, TT_ENOMEM, "loo tasks");
   if ((e = launch_svd(dt, m, c->stream)) != hipSuccess) return hip_fail(c, e, "loo svd");
-  for (int k = 0; k < m; ++k) {
-    tt_status s = read_doubles(c, tasks[k].sigma, &loo_host[k], 1);
+  for (int k = 1; k <= m; ++k) {
+    tt_status s = read_doubles(c, tasks[k - 1].sigma, sig_host + (size_t)(k - 1) * k / 2, k);
     if (s != TT_OK) return s;
   }
+  return TT_OK;
+}
+
+tt_status loo_from_gram(tt_ctx* c, const double* Gq, int m, double* loo_host) {
+  std::vector<double> sig((size_t)m * (m + 1) / 2);
+  tt_status s = block_spectra(c, Gq, m, 1, sig.data());
+  if (s != TT_OK) return s;
+  for (int k = 1; k <= m; ++k) loo_host[k - 1] = sig[(size_t)(k - 1) * k / 2];
   return TT_OK;
 }
 
@@ -1167,6 +1179,39 @@ tt_status tt_loo(tt_ctx* c, int32_t m, const tt_vec* q, double* loo, double* gra
   return loo_from_gram(c, Gq, m, loo);
 }
 
+tt_status tt_cond(tt_ctx* c, int32_t m, const tt_sum* a, double* kappa, double* gram) {
+  if (!c || m < 1 || !a || !kappa) return fail(c, TT_EINVAL, "cond: bad arguments");
+  tt_status s;
+  for (int i = 0; i < m; ++i) {
+    if ((s = check_sum(c, &a[i], "a")) != TT_OK) return s;
+    if (!same_shape(a[i].comp[0], a[0].comp[0])) return fail(c, TT_EINVAL, "cond: inputs differ in shape");
+  }
+  CallScope scope(c);
+  double* G = (double*)dev_scratch(c, (size_t)m * m * 8);
+  if (!G) return fail(c, TT_ENOMEM, "cond gram");
+  // G(i, j) = <a_i, a_j>, j <= i, in one batched launch, then mirrored
+  std::vector<tt_sum> xs, ys;
+  std::vector<int32_t> idx;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j <= i; ++j) {
+      xs.push_back(a[i]);
+      ys.push_back(a[j]);
+      idx.push_back(i * m + j);
+    }
+  if ((s = dot_pairs_idx(c, (int)xs.size(), xs.data(), ys.data(), G, &idx)) != TT_OK) return s;
+  hipError_t e = launch_sym_lower(G, m, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "cond sym");
+  if (gram && (s = read_doubles(c, G, gram, (size_t)m * m)) != TT_OK) return s;
+  std::vector<double> sig((size_t)m * (m + 1) / 2);
+  if ((s = block_spectra(c, G, m, 0, sig.data())) != TT_OK) return s;
+  for (int k = 1; k <= m; ++k) {
+    const double* sk = sig.data() + (size_t)(k - 1) * k / 2;
+    const double hi = sk[0], lo = sk[k - 1];
+    kappa[k - 1] = lo > 0.0 ? std::sqrt(hi / lo) : INFINITY;
+  }
+  return TT_OK;
+}
+
 tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum* a, double delta, int64_t rank_guard,
                            tt_vec* q, double* R, double* loo, tt_ortho_stats* stats) {
   if (!c || m < 1 || !a || !q || !R) return fail(c, TT_EINVAL, "orthogonalize: bad arguments");
@@ -1222,6 +1267,9 @@ tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum*
     if (!G || !Rinv || !info) return finish(fail(c, TT_ENOMEM, "gram buffers"));
     if ((s = dot_pairs_idx(c, (int)xs.size(), xs.data(), ys.data(), G, &idx)) != TT_OK) return finish(s);
     if ((e = launch_sym_lower(G, m, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "sym"));
+    // The dots are FP64 for either dtype, but FP32-bulk inputs carry their
+    // storage error of u_32 relative to each vector, so their Gram matrix is
+    // known to that level only: the singularity test uses the storage precision.
     const double udot = (a[0].comp[0].dtype == TT_F64) ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
     if ((e = launch_cholinv(G, m, Rinv, info, udot, c->stream)) != hipSuccess) return finish(hip_fail(c, e, "cholesky"));
     int32_t* hinfo = (int32_t*)c->pin.alloc(8);

@@ -119,9 +119,9 @@ struct DotTask {
   const int64_t* rx;      // device [d+1] ranks of x
   const int64_t* ry;      // device [d+1] ranks of y
   double coef;
-  void* w;                // scratch 2 * wcap elements (compute dtype)
+  void* w;                // scratch 2 * wcap doubles (FP64 for both input dtypes)
   int64_t wcap;           // >= max_k rx_k * ry_k
-  void* tmp;              // scratch >= max_k rx_k * n_k * ry_{k+1} elements
+  void* tmp;              // scratch >= max_k rx_k * n_k * ry_{k+1} doubles
   double* out;            // result slot: coef * <x, y>
 };
 
@@ -159,7 +159,8 @@ hipError_t launch_copy_segs(int dtype, const CopySeg* d_segs, int nsegs, hipStre
 hipError_t launch_segsum(const double* slots, const int32_t* seg, const int32_t* idx, int nout, double* out,
                          hipStream_t s);
 hipError_t launch_cholinv(double* G, int m, double* Rinv, int32_t* info, double u, hipStream_t s);
-hipError_t launch_loo_mats(const double* G, int m, double* E, hipStream_t s);
+// Leading blocks of G packed: E_k = I - G_k (minus_identity = 1) or G_k (0).
+hipError_t launch_loo_mats(const double* G, int m, double* E, int minus_identity, hipStream_t s);
 
 // z core = alpha*x core (+) y core in the TT-sum layout (block concatenation).
 struct AxpyTask {

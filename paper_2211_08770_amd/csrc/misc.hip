@@ -5,6 +5,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "mfma.h"
 #include "wave.h"
 
 namespace tto {
@@ -25,52 +26,130 @@ __device__ inline double block_sum256(double v, double* red) {
 }
 
 // <x, y> for one component pair:  W_k = sum_i X_k(i)^T W_{k-1} Y_k(i)  (left to right).
-// Step k first forms tmp = W_{k-1} * Y_k (as rx_k x (n_k ry_{k+1})), then
-// W_k = L(X_k)^T * tmp (viewing tmp as (rx_k n_k) x ry_{k+1}).
+// Step k first forms tmp = W_{k-1} * Y_k (rx_k x (n_k ry_{k+1})), then
+// W_k = L(X_k)^T * tmp (tmp viewed as (rx_k n_k) x ry_{k+1}).  Both products run
+// on the FP64 16x16x4 matrix cores; FP32 cores are widened to double on load, so
+// every product is exact and W, tmp and all sums are FP64 in both precisions.
+// Four waves per pair; the long reduction of the second product is split over
+// the waves when it has fewer than four output tiles, and the partial tiles are
+// added in wave order (the result does not depend on timing).
+constexpr int DOT_WAVES = NT / 64;
+
+template <typename T>
+__device__ __attribute__((always_inline)) inline double ld_d(gptr<const T> p, int64_t i) {
+  return (double)p[i];
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_dot(const DotTask* __restrict__ tasks) {
+  typedef Mma<double> M;
+  __shared__ double part[DOT_WAVES][256];
   const DotTask tk = tasks[blockIdx.x];
   const int d = tk.d;
   const int64_t* nn = tk.nn;
   const int64_t* rx = tk.rx;
   const int64_t* ry = tk.ry;
-  const T* X = (const T*)tk.x;
-  const T* Y = (const T*)tk.y;
-  T* W = (T*)tk.w;
-  T* Wn = W + tk.wcap;
-  T* tmp = (T*)tk.tmp;
-  const int tid = threadIdx.x;
-  if (tid == 0) W[0] = (T)1;
+  const gptr<const T> X = glb((const T*)tk.x);
+  const gptr<const T> Y = glb((const T*)tk.y);
+  gptr<double> W = glb((double*)tk.w);
+  gptr<double> Wn = W + tk.wcap;
+  const gptr<double> tmp = glb((double*)tk.tmp);
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  if (tid == 0) W[0] = 1.0;
   __syncthreads();
   int64_t xo = 0, yo = 0;
   for (int k = 0; k < d; ++k) {
     const int64_t n = nn[k], a0 = rx[k], a1 = rx[k + 1], b0 = ry[k], b1 = ry[k + 1];
-    const T* Xk = X + xo;
-    const T* Yk = Y + yo;
-    const int64_t nt = a0 * n * b1;
-    for (int64_t e = tid; e < nt; e += NT) {
-      const int64_t a = e / (n * b1);
-      const int64_t rem = e - a * n * b1;   // = i * b1 + c
-      T s = (T)0;
-      for (int64_t b = 0; b < b0; ++b) s += W[a * b0 + b] * Yk[b * n * b1 + rem];
-      tmp[e] = s;
+    const gptr<const T> Xk = X + xo;
+    const gptr<const T> Yk = Y + yo;
+    // tmp (a0 x nb1) = W (a0 x b0) * Yk (b0 x nb1)
+    {
+      const int64_t nb1 = n * b1;
+      const int64_t mt = (a0 + 15) >> 4, ntl = (nb1 + 15) >> 4;
+      for (int64_t t = wv; t < mt * ntl; t += DOT_WAVES) {
+        const int64_t r0 = (t / ntl) << 4, c0 = (t % ntl) << 4;
+        const int64_t ra = r0 + lr, cb = c0 + lr;
+        const bool rok = ra < a0, cok = cb < nb1;
+        M::acc_t acc = M::zero();
+        for (int64_t kk = 0; kk < b0; kk += 4) {
+          const int64_t kq = kk + lk;
+          const bool kok = kq < b0;
+          const double av = (rok && kok) ? W[ra * b0 + kq] : 0.0;
+          const double bv = (cok && kok) ? ld_d<T>(Yk, kq * nb1 + cb) : 0.0;
+          acc = M::mma(av, bv, acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t r = r0 + M::row(lane, v);
+          if (r < a0 && cok) tmp[r * nb1 + cb] = acc[v];
+        }
+      }
     }
     __syncthreads();
-    const int64_t nw = a1 * b1, q_n = a0 * n;
-    for (int64_t e = tid; e < nw; e += NT) {
-      const int64_t p = e / b1, c = e - p * b1;
-      T s = (T)0;
-      for (int64_t q = 0; q < q_n; ++q) s += Xk[q * a1 + p] * tmp[q * b1 + c];
-      Wn[e] = s;
+    // Wn (a1 x b1) = L(Xk)^T (a1 x a0 n) * tmp (a0 n x b1)
+    {
+      const int64_t K = a0 * n;
+      const int mt = (int)((a1 + 15) >> 4), ntl = (int)((b1 + 15) >> 4), tiles = mt * ntl;
+      const int ks = tiles >= DOT_WAVES ? 1 : (DOT_WAVES / tiles);
+      const int64_t kchunk = ((K + 4 * ks - 1) / (4 * ks)) * 4;
+      for (int u = wv; u < tiles * ks; u += DOT_WAVES) {
+        const int t = u / ks, part_i = u % ks;
+        const int64_t r0 = (int64_t)(t / ntl) << 4, c0 = (int64_t)(t % ntl) << 4;
+        const int64_t ra = r0 + lr, cb = c0 + lr;
+        const bool rok = ra < a1, cok = cb < b1;
+        const int64_t klo = part_i * kchunk, khi = (klo + kchunk) < K ? (klo + kchunk) : K;
+        M::acc_t acc0 = M::zero(), acc1 = M::zero();
+        int64_t kk = klo;
+        for (; kk + 8 <= khi; kk += 8) {
+          const int64_t q0 = kk + lk, q1 = kk + 4 + lk;
+          const double a0v = rok ? ld_d<T>(Xk, q0 * a1 + ra) : 0.0;
+          const double b0v = cok ? tmp[q0 * b1 + cb] : 0.0;
+          const double a1v = rok ? ld_d<T>(Xk, q1 * a1 + ra) : 0.0;
+          const double b1v = cok ? tmp[q1 * b1 + cb] : 0.0;
+          acc0 = M::mma(a0v, b0v, acc0);
+          acc1 = M::mma(a1v, b1v, acc1);
+        }
+        for (; kk < khi; kk += 4) {
+          const int64_t q = kk + lk;
+          const bool kok = q < khi;
+          const double av = (rok && kok) ? ld_d<T>(Xk, q * a1 + ra) : 0.0;
+          const double bv = (cok && kok) ? tmp[q * b1 + cb] : 0.0;
+          acc0 = M::mma(av, bv, acc0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc0[v] += acc1[v];
+        if (ks == 1) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t r = r0 + M::row(lane, v);
+            if (r < a1 && cok) Wn[r * b1 + cb] = acc0[v];
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) part[wv][M::row(lane, v) * 16 + lr] = acc0[v];
+        }
+      }
+      if (ks > 1) {
+        __syncthreads();
+        // tile t's partials are in waves t*ks .. t*ks + ks - 1: add them in that order
+        for (int e = tid; e < tiles * 256; e += NT) {
+          const int t = e >> 8, w = e & 255;
+          const int64_t r = ((int64_t)(t / ntl) << 4) + (w >> 4), c = ((int64_t)(t % ntl) << 4) + (w & 15);
+          double s = part[t * ks][w];
+          for (int j = 1; j < ks; ++j) s += part[t * ks + j][w];
+          if (r < a1 && c < b1) Wn[r * b1 + c] = s;
+        }
+      }
     }
     __syncthreads();
-    T* sw = W;
+    gptr<double> sw = W;
     W = Wn;
     Wn = sw;
     xo += a0 * n * a1;
     yo += b0 * n * b1;
   }
-  if (tid == 0) *tk.out = tk.coef * (double)W[0];
+  if (tid == 0) *tk.out = tk.coef * W[0];
 }
 
 template <typename T>
@@ -175,12 +254,14 @@ __global__ __launch_bounds__(NT) void k_cholinv(double* __restrict__ G, int m, d
 }
 
 // E_k = I_k - G[:k, :k] for k = 1..m, stored back to back (row-major k x k).
-__global__ void k_loo_mats(const double* __restrict__ G, int m, double* __restrict__ E) {
+// Leading k x k blocks of the m x m matrix G, packed one after another:
+// E_k = I - G_k (loss of orthogonality) or E_k = G_k (condition numbers).
+__global__ void k_loo_mats(const double* __restrict__ G, int m, double* __restrict__ E, int minus_identity) {
   const int k = blockIdx.x + 1;
   double* Ek = E + (int64_t)(k - 1) * k * (2 * k - 1) / 6;
   for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
     const int r = e / k, c = e - r * k;
-    Ek[e] = (r == c ? 1.0 : 0.0) - G[r * m + c];
+    Ek[e] = minus_identity ? (r == c ? 1.0 : 0.0) - G[r * m + c] : G[r * m + c];
   }
 }
 
@@ -579,9 +660,9 @@ hipError_t launch_cholinv(double* G, int m, double* Rinv, int32_t* info, double 
   return hipGetLastError();
 }
 
-hipError_t launch_loo_mats(const double* G, int m, double* E, hipStream_t s) {
+hipError_t launch_loo_mats(const double* G, int m, double* E, int minus_identity, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_loo_mats, dim3(m), dim3(NT), 0, s, G, m, E);
+  hipLaunchKernelGGL(k_loo_mats, dim3(m), dim3(NT), 0, s, G, m, E, minus_identity);
   return hipGetLastError();
 }
 

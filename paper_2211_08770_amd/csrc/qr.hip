@@ -25,6 +25,7 @@
 //    the panel starting at column p0 only touch, in each child block, the
 //    rows i < p0 + 16: every panel works on that compacted row list.
 #include "common.h"
+#include "mfma.h"
 #include "wave.h"
 
 namespace tto {
@@ -40,26 +41,6 @@ constexpr int XSTRIDE = ((MAXR + 63) / 64) * 64;   // a published column: every 
 // LDS scratch after the panel: two column buffers during the panel
 // factorisation, partial V^T A of row-split tiles during the update.
 constexpr int SCR_DOUBLES = (2 * XSTRIDE > NWV * NB * NB) ? 2 * XSTRIDE : NWV * NB * NB;
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-
-// 16x16x4 MFMA in the precision of the tile.  Operands: lane l holds
-// A[l%16][l/16] and B[l/16][l%16].  Result row of register v for lane l:
-// f64: 4v + l/16 ; f32: 4(l/16) + v ; result column l%16.
-template <typename T> struct Mma;
-template <> struct Mma<double> {
-  typedef v4d acc_t;
-  __device__ static acc_t zero() { return acc_t{0.0, 0.0, 0.0, 0.0}; }
-  __device__ static acc_t mma(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }
-};
-template <> struct Mma<float> {
-  typedef v4f acc_t;
-  __device__ static acc_t zero() { return acc_t{0.f, 0.f, 0.f, 0.f}; }
-  __device__ static acc_t mma(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
-};
 
 // Active tile rows of the panel [p0, p0 + nb) in increasing order; returns the count.
 // Dense tile (nchild == 0): rows p0..m-1.  Node: in child block b (offset

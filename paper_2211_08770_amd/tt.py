@@ -20,7 +20,7 @@ import torch
 __all__ = ["TT", "dot", "dot_batched", "axpy", "norm", "round", "round_batched", "round_randomized", "orthogonalize",
            "loo", "laplacian",
            "krylov_laplacian",
-           "Engine", "TTError", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
+           "Engine", "TTError", "cond", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
 
 TT_MAXD = 64
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -111,6 +111,8 @@ def _load():
         lib.tt_orthogonalize.restype = C.c_int
         lib.tt_loo.argtypes = [P, C.c_int32, C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.tt_loo.restype = C.c_int
+        lib.tt_cond.argtypes = [P, C.c_int32, C.POINTER(_Sum), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        lib.tt_cond.restype = C.c_int
         lib.tt_round_randomized.argtypes = [P, C.POINTER(_Sum), C.POINTER(_Vec), C.c_double, C.POINTER(_Vec)]
         lib.tt_round_randomized.restype = C.c_int
         lib.tt_laplacian.argtypes = [P, C.POINTER(_Vec), C.c_double, C.POINTER(_Vec)]
@@ -526,6 +528,20 @@ def loo(Q):
     G = (C.c_double * (m * m))()
     ctx.ensure_ws(64 << 20)
     ctx.call_with_ws(lambda: ctx.lib.tt_loo(ctx.h, m, vq, out, G))
+    return np.array(out[:]), np.array(G[:]).reshape(m, m)
+
+
+def cond(A):
+    """kappa(A_k) = sqrt(kappa(G_k)), k = 1..m, from the FP64 Gram matrix of the
+    TT-vectors or lazy sums A (tt_cond), and that Gram matrix."""
+    m = len(A)
+    ctx = _ctx(_device_of(A[0]))
+    hs = [_SumHolder(a) for a in A]
+    xs = (_Sum * m)(*[h.s for h in hs])
+    out = (C.c_double * m)()
+    G = (C.c_double * (m * m))()
+    ctx.ensure_ws(64 << 20)
+    ctx.call_with_ws(lambda: ctx.lib.tt_cond(ctx.h, m, xs, out, G))
     return np.array(out[:]), np.array(G[:]).reshape(m, m)
 
 

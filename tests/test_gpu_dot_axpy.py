@@ -14,7 +14,10 @@ def rand(seed, ns, ranks, scale=1.0):
     return synth.random_tt(synth.rng(seed), ns, ranks, np.float64, scale)
 
 
-@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+# FP32 cores are widened exactly and every product and sum of the dot is FP64,
+# so FP32 inputs meet the FP64 oracle (run on the same values upcast) at the
+# FP64 level too.
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-12)])
 def test_dot_pairs_and_sums(dtype, tol):
     tt = need_gpu()
     npdt = np.float64 if dtype == torch.float64 else np.float32
@@ -90,3 +93,24 @@ def test_norm_of_lazy_sums(dtype, tol):
     # zero tensor
     z = [np.zeros((1, 4, 2)), np.zeros((2, 4, 1))]
     assert tt.norm(dev_tt([c.astype(npdt) for c in z], dtype)) == 0.0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_dot_tiles_and_split_reductions(dtype):
+    """Ranks spanning several 16 x 16 matrix-core tiles with ragged edges, rank one
+    against rank 40, and a long second product (r n = 33 * 64) that the kernel
+    splits over waves: FP64 accumulation against the oracle in both dtypes."""
+    tt = need_gpu()
+    npdt = np.float64 if dtype == torch.float64 else np.float32
+    up = lambda v: [c.astype(np.float64) for c in v]
+    cases = [([9, 64, 5], [1, 33, 17, 1], [1, 40, 3, 1]),
+             ([16, 3, 17, 5], [1, 1, 1, 1, 1], [1, 40, 21, 6, 1]),
+             ([50, 50], [1, 19, 1], [1, 47, 1])]
+    for i, (ns, rx, ry) in enumerate(cases):
+        x = [c.astype(npdt) for c in rand(60 + i, ns, rx)]
+        y = [c.astype(npdt) for c in rand(70 + i, ns, ry)]
+        ref = oracle.tt_dot(up(x), up(y))
+        got = tt.dot(dev_tt(x, dtype), dev_tt(y, dtype))
+        assert abs(got - ref) <= 1e-12 * oracle.tt_norm(up(x)) * oracle.tt_norm(up(y)), (ns, got, ref)
+        # <x, x> is ||x||^2 to FP64 accuracy
+        assert abs(tt.dot(dev_tt(x, dtype), dev_tt(x, dtype)) / oracle.tt_norm(up(x)) ** 2 - 1.0) <= 1e-12

@@ -153,3 +153,22 @@ def test_conditioned_inputs_have_prescribed_gram():
     G = A.T @ A
     assert np.allclose(G, M, atol=1e-9)
     assert np.linalg.cond(G) == pytest.approx(1e6, rel=1e-3)
+
+
+def test_cond_curve_pins():
+    """kappa(A_k): 1 on orthonormal columns, max/min scale on orthogonal scaled
+    columns, sqrt(cond(Gram)) on the conditioned inputs (their Gram matrix is
+    the prescribed correlation matrix)."""
+    g = synth.rng(43)
+    ns = (3, 4, 3)
+    Qd, _ = np.linalg.qr(g.standard_normal((36, 5)))
+    A = [oracle.tt_svd(Qd[:, i].reshape(ns), 0.0)[0] for i in range(5)]
+    assert np.allclose(oracle.cond_curve(A), 1.0, atol=1e-12)
+    scales = [1.0, 0.5, 4.0, 1e-3, 2.0]
+    B = [oracle.tt_svd(scales[i] * Qd[:, i].reshape(ns), 0.0)[0] for i in range(5)]
+    want = [max(scales[:k]) / min(scales[:k]) for k in range(1, 6)]
+    assert np.allclose(oracle.cond_curve(B), want, rtol=1e-10)
+    X, C, M = conditioned_inputs(44, 8, 3, 4, 2, 1e6)
+    kap = oracle.cond_curve(X)
+    assert abs(kap[-1] / math.sqrt(1e6) - 1.0) < 1e-6
+    assert np.all(np.diff(kap) >= -1e-9 * kap[1:])   # adding columns never lowers kappa
