@@ -249,6 +249,22 @@ tt_status tt_loo(tt_ctx* ctx, int32_t m, const tt_vec* q, double* loo, double* g
  * HOST m*m row-major or NULL.  Errors: TT_EINVAL (shapes), TT_ECAPACITY. */
 tt_status tt_cond(tt_ctx* ctx, int32_t m, const tt_sum* a, double* kappa, double* gram);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): <x, y> of two TT-vectors x and y
+ * (same d, n and dtype; plain TT-vectors, not lazy sums) with the contraction
+ * of tt_dot (FP64 products and sums for either dtype), written to the DEVICE
+ * double *out.  No context: one kernel launch on `stream` (a hipStream_t of the
+ * current device, NULL for the default stream); the call neither allocates
+ * nor synchronises, so *out is valid once the stream reaches that point.
+ * Scratch: a fixed 16 MiB device array inside the library, one per device,
+ * held from the first call on that device until the process ends; a pair needs
+ * (2 max_k rx_k ry_k rounded up to 32) + max_k rx_k n_k ry_{k+1} doubles of it.
+ * Every call on a device shares that device's array, so calls that overlap on
+ * one device (other streams, other threads) race; calls ordered on one stream
+ * do not.  Errors: TT_EINVAL (shapes, null pointers, capacity below the packed
+ * size), TT_ECAPACITY (the pair needs more than the 16 MiB), TT_EDEVICE. */
+tt_status tt_dot_noalloc(void* stream, const tt_vec* x, const tt_vec* y, double* out);
+
 /* ---------------------------------------------------------------------------
  * Serving engine: continuous batching of orthogonalization requests.
  *

@@ -22,7 +22,7 @@ HIP_FLAGS = [
     "-Wall", "-Wno-unused-result", "-Wno-unused-function",
 ]
 
-SOURCES = ["qr.hip", "svd.hip", "gemm.hip", "misc.hip", "round.cpp", "api.cpp"]
+SOURCES = ["qr.hip", "svd.hip", "gemm.hip", "misc.hip", "noalloc.hip", "round.cpp", "api.cpp"]
 
 
 def _hipcc() -> str:
