@@ -192,6 +192,20 @@ tt_status tt_orthogonalize(tt_ctx* ctx, tt_scheme scheme, int32_t m, const tt_su
                            int64_t rank_guard, tt_vec* q, double* R, double* loo,
                            tt_ortho_stats* stats);
 
+/* Output capacities of tt_orthogonalize for the m inputs a (Section 3: the ranks
+ * of the sum a scheme rounds bound the ranks of its result, and every rank is
+ * capped by min(prod n_{<=k}, prod n_{>k}) and by rank_guard when > 0):
+ * upper bounds of the bond ranks of each q_i -- CGS/MGS rank(a_i) + sum_{j<i}
+ * bound(q_j); CGS2/MGS2 min(that, caps) + sum_{j<i} bound(q_j) (the second pass
+ * rounds the first pass's result plus the basis); Gram sum_{k<=i} rank(a_k);
+ * Householder 1 + sum_{l<=i} bound(u_l) with bound(u_l) = rank(a_l) +
+ * sum_{j<l} bound(u_j) + l + 1.  ranks (HOST [m*(d+1)], nullable) receives the
+ * bounds of q_i at ranks[i*(d+1) + k]; sizes (HOST [m], nullable) the packed
+ * element counts, i.e. the capacity each q[i] needs.  Host-only: reads only the
+ * shapes (the data pointers may be NULL).  Errors: TT_EINVAL. */
+tt_status tt_orthogonalize_capacity(int32_t scheme, int32_t m, const tt_sum* a, int64_t rank_guard, int64_t* ranks,
+                                    int64_t* sizes);
+
 /* Randomized rounding of a lazy sum (the cheaper rounding of sums that the
  * paper cites for output ranks far below those of the sum):
  * Randomize-then-Orthogonalize with the Gaussian sketch TT-vector `sketch`

@@ -1179,6 +1179,70 @@ tt_status tt_loo(tt_ctx* c, int32_t m, const tt_vec* q, double* loo, double* gra
   return loo_from_gram(c, Gq, m, loo);
 }
 
+tt_status tt_orthogonalize_capacity(int32_t scheme, int32_t m, const tt_sum* a, int64_t rank_guard, int64_t* ranks,
+                                    int64_t* sizes) {
+  if (scheme < TT_CGS || scheme > TT_HOUSEHOLDER || m < 1 || !a) return TT_EINVAL;
+  const tt_vec* s0 = (a[0].ncomp >= 1 && a[0].comp) ? &a[0].comp[0] : nullptr;
+  if (!s0 || s0->d < 1 || s0->d > TT_MAXD) return TT_EINVAL;
+  const int d = s0->d;
+  for (int i = 0; i < m; ++i) {
+    if (a[i].ncomp < 1 || !a[i].comp) return TT_EINVAL;
+    for (int c = 0; c < a[i].ncomp; ++c) {
+      const tt_vec& v = a[i].comp[c];
+      if (v.d != d || v.r[0] != 1 || v.r[d] != 1) return TT_EINVAL;
+      for (int k = 0; k < d; ++k)
+        if (v.n[k] != s0->n[k] || v.n[k] < 1 || v.r[k] < 1) return TT_EINVAL;
+    }
+  }
+  int64_t caps[TT_MAXD + 1];
+  rank_caps(*s0, caps);
+  auto capped = [&](int64_t* b) {
+    for (int k = 0; k <= d; ++k) {
+      int64_t v = std::min(b[k], caps[k]);
+      if (rank_guard > 0) v = std::min(v, rank_guard);
+      b[k] = (k == 0 || k == d) ? 1 : v;
+    }
+  };
+  // S[k]: sum of the bounds of q_0..q_{i-1}; acc[k]: Gram's running sum of input
+  // ranks; U[k]: sum of the bounds of the Householder vectors u_0..u_i.
+  std::vector<int64_t> S(d + 1, 0), acc(d + 1, 0), U(d + 1, 0);
+  for (int i = 0; i < m; ++i) {
+    int64_t ra[TT_MAXD + 1], b[TT_MAXD + 1];
+    for (int k = 0; k <= d; ++k) {
+      ra[k] = 0;
+      for (int c = 0; c < a[i].ncomp; ++c) ra[k] += a[i].comp[c].r[k];
+    }
+    if (scheme == TT_GRAM) {
+      // q_i rounds sum_{k<=i} R^{-1}(k, i) a_k
+      for (int k = 0; k <= d; ++k) b[k] = (acc[k] += ra[k]);
+    } else if (scheme == TT_HOUSEHOLDER) {
+      // rounded w = a~_i (a_i plus earlier reflections), then w and i canonical
+      // terms, then u_i = that plus one; q_i = e_i reflected by u_0..u_i
+      int64_t bw[TT_MAXD + 1], b1[TT_MAXD + 1], u[TT_MAXD + 1];
+      for (int k = 0; k <= d; ++k) bw[k] = ra[k] + U[k];
+      capped(bw);
+      for (int k = 0; k <= d; ++k) b1[k] = bw[k] + i;
+      capped(b1);
+      for (int k = 0; k <= d; ++k) u[k] = b1[k] + 1;
+      capped(u);
+      for (int k = 0; k <= d; ++k) b[k] = 1 + (U[k] += u[k]);
+    } else if (scheme == TT_CGS2 || scheme == TT_MGS2) {
+      // second pass: the rounded first-pass vector (at most min(R1, caps)) plus the basis
+      for (int k = 0; k <= d; ++k) b[k] = std::min(ra[k] + S[k], caps[k]) + S[k];
+    } else {
+      for (int k = 0; k <= d; ++k) b[k] = ra[k] + S[k];
+    }
+    capped(b);
+    int64_t sz = 0;
+    for (int k = 0; k < d; ++k) sz += b[k] * s0->n[k] * b[k + 1];
+    if (ranks)
+      for (int k = 0; k <= d; ++k) ranks[(size_t)i * (d + 1) + k] = b[k];
+    if (sizes) sizes[i] = sz;
+    for (int k = 0; k <= d; ++k) S[k] += b[k];
+  }
+  return TT_OK;
+}
+
 tt_status tt_cond(tt_ctx* c, int32_t m, const tt_sum* a, double* kappa, double* gram) {
   if (!c || m < 1 || !a || !kappa) return fail(c, TT_EINVAL, "cond: bad arguments");
   tt_status s;

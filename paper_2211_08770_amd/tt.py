@@ -111,6 +111,9 @@ def _load():
         lib.tt_orthogonalize.restype = C.c_int
         lib.tt_loo.argtypes = [P, C.c_int32, C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.tt_loo.restype = C.c_int
+        lib.tt_orthogonalize_capacity.argtypes = [C.c_int32, C.c_int32, C.POINTER(_Sum), C.c_int64,
+                                                  C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        lib.tt_orthogonalize_capacity.restype = C.c_int
         lib.tt_cond.argtypes = [P, C.c_int32, C.POINTER(_Sum), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.tt_cond.restype = C.c_int
         lib.tt_round_randomized.argtypes = [P, C.POINTER(_Sum), C.POINTER(_Vec), C.c_double, C.POINTER(_Vec)]
@@ -435,36 +438,29 @@ def round_batched(xs, deltas, max_ranks=None):
 
 
 def q_rank_bounds(scheme: str, ra, ns, rank_guard: int = 0):
-    """Upper bounds of the bond ranks of every q_i an orthogonalization returns (output capacity).
+    """Upper bounds of the bond ranks of every q_i an orthogonalization returns
+    (its output capacity), from tt_orthogonalize_capacity of the C ABI.
 
-    ra[i][k]: summed component ranks of input i at bond k.  Bounds: the rank caps of the mode
-    sizes, the pre-round ranks (Gram: sum_{k<=i} rank(a_k); the Gram-Schmidt schemes:
-    rank(a_i) + sum_{j<i} bound(q_j), which also bounds their second pass; Householder:
-    1 + sum_{l<=i} bound(u_l) with u_l <= a_l + sum_{j<l} u_j + l canonical terms + 1) and the
-    rank guard.
+    ra[i][k]: summed component ranks of input i at bond k; ns: mode sizes.
     """
-    d = len(ns)
-    caps = [1]
-    for k in range(1, d):
-        caps.append(min(int(np.prod(ns[:k], dtype=object)), int(np.prod(ns[k:], dtype=object))))
-    caps.append(1)
-
-    def capped(b):
-        return [1 if k in (0, d) else min(b[k], caps[k], rank_guard if rank_guard > 0 else b[k]) for k in range(d + 1)]
-    bounds, acc, ubounds = [], [0] * (d + 1), []
-    for i in range(len(ra)):
-        if scheme == "gram":
-            acc = [acc[k] + ra[i][k] for k in range(d + 1)]
-            b = list(acc)
-        elif scheme == "householder":
-            bw = capped([ra[i][k] + sum(u[k] for u in ubounds) for k in range(d + 1)])
-            b1 = capped([bw[k] + i for k in range(d + 1)])
-            ubounds.append(capped([b1[k] + 1 for k in range(d + 1)]))
-            b = [1 + sum(u[k] for u in ubounds) for k in range(d + 1)]
-        else:
-            b = [ra[i][k] + sum(bb[k] for bb in bounds) for k in range(d + 1)]
-        bounds.append(capped(b))
-    return bounds
+    lib = _load()
+    d, m = len(ns), len(ra)
+    vecs = (_Vec * m)()
+    one = (C.c_double * 1)(1.0)
+    sums = (_Sum * m)()
+    for i in range(m):
+        v = vecs[i]
+        v.d, v.dtype = d, _F64
+        for k in range(d):
+            v.n[k] = int(ns[k])
+        for k in range(d + 1):
+            v.r[k] = 1 if k in (0, d) else int(ra[i][k])   # summed ranks: the boundary bonds count components
+        sums[i] = _Sum(1, one, C.cast(C.byref(vecs, i * C.sizeof(_Vec)), C.POINTER(_Vec)))
+    out = (C.c_int64 * (m * (d + 1)))()
+    st = lib.tt_orthogonalize_capacity(SCHEMES[scheme], m, sums, int(rank_guard), out, None)
+    if st != 0:
+        raise TTError(st, "orthogonalize capacity: bad shapes")
+    return [[int(out[i * (d + 1) + k]) for k in range(d + 1)] for i in range(m)]
 
 
 def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: bool = True, q_capacity=None,

@@ -111,8 +111,10 @@ def test_loo_matches_dense_two_norm():
 
 @pytest.mark.parametrize("scheme", oracle.SCHEMES)
 def test_loo_bounds_with_delta_in_place_of_u(scheme):
-    # Table 1 (TT column): LOO = O(delta kappa^2) for CGS/Gram/MGS as printed,
-    # O(delta) for CGS2/MGS2.  Checked only where delta * kappa^p <= 0.1.
+    # Table 1 (TT column) with the reading of the text for MGS: LOO = O(delta
+    # kappa^2) for CGS/Gram, O(delta kappa) for MGS (Table 1 prints kappa^2 for it
+    # while the text says it follows kappa), O(delta) for CGS2/MGS2.  Checked only
+    # where delta * kappa^p <= 0.1.
     delta = 1e-8
     X, C, M = conditioned_inputs(47, 6, 3, 4, 2, 1e4)
     kappa_g = np.linalg.cond(M)
@@ -120,7 +122,7 @@ def test_loo_bounds_with_delta_in_place_of_u(scheme):
     loo = oracle.loo_curve(res.Q)
     for k in range(1, 7):
         kap = math.sqrt(np.linalg.cond(M[:k, :k]))
-        p = {"cgs": 2, "gram": 2, "mgs": 2, "cgs2": 0, "mgs2": 0}[scheme]
+        p = {"cgs": 2, "gram": 2, "mgs": 1, "cgs2": 0, "mgs2": 0}[scheme]
         if delta * kap ** p <= 0.1:
             assert loo[k - 1] <= 10 * k * delta * max(1.0, kap ** p) + 1e-13, (scheme, k)
     assert kappa_g == pytest.approx(1e4, rel=1e-6)
