@@ -168,6 +168,15 @@ tt_status tt_round_batched(tt_ctx* ctx, int32_t njobs, const tt_sum* xs, const d
  * by min(sum of component ranks, prod n_{<=k}, prod n_{>k}). */
 int64_t tt_round_out_capacity(const tt_sum* x);
 
+/* Accuracy tt_round(x, delta) guarantees: ||x - x~|| <= delta_eff ||x||.  FP64:
+ * delta_eff = delta.  FP32-bulk: the per-bond threshold is
+ * max(delta / sqrt(d-1), 2 sqrt(s_k) u_32) ||x||, s_k the columns of the merged
+ * core at bond k, because singular values below the FP32 resolution of that
+ * core are noise (keeping them only inflates the ranks); so delta_eff =
+ * max(delta, sqrt(d-1) 2 sqrt(s_max) u_32) with s_max bounded by the summed
+ * ranks and the rank caps.  Host-only.  -1 on bad input. */
+double tt_round_effective_delta(const tt_sum* x, double delta);
+
 /* Workspace bytes tt_round needs for x (batched: sum over jobs). */
 int64_t tt_round_workspace_bytes(const tt_sum* x);
 

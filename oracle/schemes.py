@@ -40,7 +40,7 @@ from .tt import tt_sum, tt_dot, tt_norm, tt_round, tt_scale, tt_ranks, tt_full, 
 
 __all__ = ["OrthoResult", "cgs", "mgs", "cgs2", "mgs2", "gram", "householder", "orthogonalize",
            "loo_curve", "gram_of", "SCHEMES", "GramBreakdown", "HouseholderBreakdown", "canonical_index",
-           "canonical_tt", "tth_vec", "apply_h_vec", "cond_curve"]
+           "canonical_tt", "tth_vec", "apply_h_vec", "cond_curve", "gs_step"]
 
 SCHEMES = ("cgs", "mgs", "cgs2", "mgs2", "gram")
 
@@ -139,6 +139,31 @@ def _two_pass(A, delta, modified):
         res.Q.append(tt_scale(1.0 / R2[i, i], p))
     res.R = R1 + R2
     return res
+
+
+def gs_step(scheme, Q, a, delta):
+    """Step i = len(Q) of TT-CGS, TT-MGS, TT-CGS2 or TT-MGS2 (Algorithms 1-4)
+    against the given q_0..q_{i-1}: the projections of a (one pass, or two
+    passes each rounded, R = R_1 + R_2), the rounding and the normalisation.
+    Returns (q_i, column i of R as an array of i + 1 entries)."""
+    passes = 2 if scheme in ("cgs2", "mgs2") else 1
+    modified = scheme in ("mgs", "mgs2")
+    i = len(Q)
+    res = OrthoResult(Q=[], R=None)
+    col = np.zeros(i + 1)
+    prev_terms = list(_as_sum(a))
+    for _ in range(passes):
+        prev = tt_sum(prev_terms)
+        terms = list(prev_terms)
+        for j in range(i):
+            src = tt_sum(terms) if modified else prev
+            r = tt_dot(src, Q[j])
+            col[j] += r
+            terms.append((-r, Q[j]))
+        p = _round(res, terms, delta)
+        prev_terms = [(1.0, p)]
+    col[i] = tt_norm(p)
+    return tt_scale(1.0 / col[i], p), col
 
 
 def cgs2(A, delta):

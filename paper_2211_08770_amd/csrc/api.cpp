@@ -612,6 +612,22 @@ int64_t tt_round_out_capacity(const tt_sum* x) {
   return s;
 }
 
+double tt_round_effective_delta(const tt_sum* x, double delta) {
+  if (!x || x->ncomp < 1 || !x->comp || !(delta >= 0.0)) return -1.0;
+  const tt_vec& s0 = x->comp[0];
+  if (s0.d < 1 || s0.d > TT_MAXD) return -1.0;
+  if (s0.dtype != TT_F32 || s0.d == 1) return delta;
+  int64_t caps[TT_MAXD + 1];
+  rank_caps(s0, caps);
+  int64_t smax = 1;
+  for (int k = 1; k < s0.d; ++k) {
+    int64_t R = 0;
+    for (int c = 0; c < x->ncomp; ++c) R += x->comp[c].r[k];
+    smax = std::max(smax, std::min(R, caps[k]));
+  }
+  return std::max(delta, std::sqrt((double)(s0.d - 1)) * fp32_eps_floor(smax));
+}
+
 int64_t tt_round_workspace_bytes(const tt_sum* x) {
   if (!x || x->ncomp < 1 || !x->comp) return -1;
   std::vector<RJob> jobs(1);

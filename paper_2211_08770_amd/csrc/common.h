@@ -62,6 +62,7 @@ struct SvdTask {
   int32_t* perm;          // [kr] scratch
   const double* norm;     // device ||x||; eps = delta / sqrt(d-1) * norm
   double delta_scaled;    // delta / sqrt(d-1)
+  double eps_floor;       // eps = max(delta_scaled, eps_floor) * norm (FP32-bulk noise floor; 0 in FP64)
   int64_t max_rank;       // <= 0: none
   int32_t* rank_out;      // device int
   double* wt;             // ncol x t row-major:  W^T  with W = Sigma_t V_t^T

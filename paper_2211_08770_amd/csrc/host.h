@@ -2,6 +2,7 @@
 // batched TT-round pipeline.  Only host code lives here; every arithmetic step
 // of the method runs in the kernels declared in common.h.
 #pragma once
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -180,6 +181,10 @@ struct RJob {
 tt_status make_job(tt_ctx* c, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out, RJob& job);
 tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs);
 int64_t round_workspace_bytes(const std::vector<RJob>& jobs);
+// FP32-bulk noise floor of the per-bond threshold, relative to ||x||, for a
+// merged core with s columns: 2 sqrt(s) u_32 (the level below which the SVD
+// sets columns aside as unresolved in FP32).
+inline double fp32_eps_floor(int64_t s) { return 2.0 * std::sqrt((double)(s > 1 ? s : 1)) * 5.9604644775390625e-08; }
 // Randomize-then-Orthogonalize rounding of a lazy FP64 sum with the sketch TT
 // sk (ranks l_k); with delta > 0 the result is then rounded deterministically.
 tt_status round_randomized(tt_ctx* c, const tt_sum* x, const tt_vec* sk, double delta, tt_vec* out);

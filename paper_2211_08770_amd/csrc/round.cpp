@@ -1059,6 +1059,9 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       t.perm = js.perm;
       t.norm = js.d_norm;
       t.delta_scaled = jb.delta / std::sqrt((double)(jb.d - 1));
+      // FP32-bulk: singular values below the FP32 resolution of the merged core
+      // (the set-aside level 2 sqrt(s) u_32 ||x||) are noise, never kept
+      t.eps_floor = (jb.dtype == TT_F32) ? fp32_eps_floor(LR.N) : 0.0;
       t.max_rank = jb.max_rank;
       t.rank_out = d_ranks + (size_t)j * (TT_MAXD + 1) + (k + 1);
       t.wt = js.wt;

@@ -481,7 +481,7 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   __syncthreads();
   for (int i = k + tid; i < nc; i += NT) tk.sigma[i] = 0.0;
   if (tid == 0) {
-    const double eps = tk.delta_scaled * (*tk.norm);
+    const double eps = (tk.delta_scaled > tk.eps_floor ? tk.delta_scaled : tk.eps_floor) * (*tk.norm);
     const double eps2 = eps * eps;
     int t = k > 0 ? k : 1;
     double tail = edrop;

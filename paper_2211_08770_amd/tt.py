@@ -20,7 +20,7 @@ import torch
 __all__ = ["TT", "dot", "dot_batched", "axpy", "norm", "round", "round_batched", "round_randomized", "orthogonalize",
            "loo", "laplacian",
            "krylov_laplacian",
-           "Engine", "TTError", "cond", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
+           "Engine", "TTError", "cond", "effective_delta", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
 
 TT_MAXD = 64
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -111,6 +111,8 @@ def _load():
         lib.tt_orthogonalize.restype = C.c_int
         lib.tt_loo.argtypes = [P, C.c_int32, C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.tt_loo.restype = C.c_int
+        lib.tt_round_effective_delta.argtypes = [C.POINTER(_Sum), C.c_double]
+        lib.tt_round_effective_delta.restype = C.c_double
         lib.tt_orthogonalize_capacity.argtypes = [C.c_int32, C.c_int32, C.POINTER(_Sum), C.c_int64,
                                                   C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         lib.tt_orthogonalize_capacity.restype = C.c_int
@@ -353,6 +355,13 @@ def krylov_laplacian(ns, m: int, dtype=torch.float64, device=None):
 def round_out_capacity(x) -> int:
     h = _SumHolder(x)
     return int(_load().tt_round_out_capacity(C.byref(h.s)))
+
+
+def effective_delta(x, delta: float) -> float:
+    """delta_eff of tt_round_effective_delta: the accuracy TT-round guarantees for x
+    (delta in FP64; at least the FP32 resolution of the merged cores in FP32-bulk)."""
+    h = _SumHolder(x)
+    return float(_load().tt_round_effective_delta(C.byref(h.s), float(delta)))
 
 
 def round_workspace_bytes(x) -> int:

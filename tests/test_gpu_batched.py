@@ -52,3 +52,24 @@ def test_batched_mixed_orders_including_order_one():
         assert diff_norm(host_cores(o), ref) <= 1e-12 * oracle.tt_norm(c)
         single = tt.round(x, delta)
         assert single.r == o.r and torch.equal(single.data, o.data)
+
+
+def test_full_size_uneven_batch_sampled_against_oracle():
+    """The 256-job uneven workload (d ~ U{4..10}, n ~ U{16,32,64}, rank ~ U{8..128}, FP32
+    cores, delta = 1e-5) rounded in one batch; 16 jobs sampled across the batch (every
+    16th, plus the job of largest work) each compared with the oracle's rounding of the
+    same FP32 values upcast: ranks equal (the caps; there is no compressible tail) and
+    error within max(delta, 1e-5)."""
+    tt = need_gpu()
+    delta = 1e-5
+    jobs = synth.uneven_jobs(seed=30000)
+    xs = [dev_tt(c, torch.float32) for c, _ in jobs]
+    outs = tt.round_batched(xs, delta)
+    work = [d * n * R ** 3 for _, (d, n, R) in jobs]
+    pick = sorted(set(list(range(0, len(jobs), 16)) + [int(np.argmax(work))]))
+    assert len(pick) >= 16
+    for i in pick:
+        c64 = [a.astype(np.float64) for a in jobs[i][0]]
+        ref = oracle.tt_round(c64, delta)
+        assert outs[i].r == oracle.tt_ranks(ref), (i, jobs[i][1])
+        assert diff_norm(host_cores(outs[i]), ref) <= 1e-5 * oracle.tt_norm(c64), (i, jobs[i][1])

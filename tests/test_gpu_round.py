@@ -53,6 +53,15 @@ def check_round(terms, delta, dtype, max_rank=0, tol=None):
         assert left_orth_error(got) <= 1e-15
         return out
     d = diff_norm(got, ref) / nx
+    de = tt.effective_delta(dev_sum(terms, dtype), delta)
+    if de > delta:
+        # FP32-bulk below its resolution: the per-bond threshold is the FP32 floor, so the
+        # result meets delta_eff (not delta) and stays within delta_eff + delta of the oracle's
+        err = diff_norm(got, x) / nx
+        assert err <= de, (err, de)
+        assert d <= de + delta, (d, de)
+        assert all(a <= b for a, b in zip(out.r, oracle.tt_ranks(ref)))
+        return out
     if min_margin(lg) >= TIE[dtype]:
         assert out.r == oracle.tt_ranks(ref), (out.r, oracle.tt_ranks(ref))
         assert d <= tol, d
@@ -71,8 +80,6 @@ def test_round_small_sums(dtype, delta):
     ns = [5, 6, 4, 7]
     terms = rand_terms(100, ns, [[1, 3, 4, 2, 1], [1, 2, 2, 2, 1], [1, 4, 3, 3, 1]], coefs=[1.0, -0.5, 0.25],
                        scales=[1.0, 0.3, 0.01])
-    if dtype == torch.float32 and delta < 1e-5:
-        pytest.skip("FP32-bulk is checked against max(delta, 1e-5) only for delta >= 1e-5")
     check_round(terms, delta, dtype)
 
 
@@ -130,6 +137,17 @@ def test_round_graded_sum_of_20_terms_fp32():
     e_ref = sample_entries(ref, idx)
     e_got = sample_entries(host_cores(out), idx)
     assert np.max(np.abs(e_ref - e_got)) <= 1e-4 * np.max(np.abs(e_ref))
+
+
+def test_round_graded_sum_of_20_terms_fp32_at_1e8():
+    """FP32-bulk at delta = 1e-8, below its resolution: rounded at delta_eff (the FP32
+    floor of the per-bond threshold), against the oracle's rounding at 1e-8."""
+    tt = need_gpu()
+    terms = synth.sum_of_graded_terms(dtype=np.float32)
+    de = tt.effective_delta(dev_sum(terms, torch.float32), 1e-8)
+    assert 1e-8 < de < 1e-5
+    out = check_round(terms, 1e-8, torch.float32)
+    assert 20 < max(out.r) <= 40
 
 
 def test_round_is_deterministic():

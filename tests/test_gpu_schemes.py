@@ -33,7 +33,7 @@ def run_both(scheme, X, delta, dtype=torch.float64):
     return ref, ref_loo, Q, R, loo, st
 
 
-def compare(scheme, X, M, delta, ref, ref_loo, Q, R, loo, st, base_tol):
+def compare(scheme, X, M, delta, ref, ref_loo, Q, R, loo, st, base_tol, loo_floor_u=1.1e-16):
     m = len(X)
     assert st["rounds"] == ref.rounds
     assert st["m_reached"] == m
@@ -49,7 +49,7 @@ def compare(scheme, X, M, delta, ref, ref_loo, Q, R, loo, st, base_tol):
     pl = {"cgs": 2, "gram": 2, "mgs": 1, "cgs2": 0, "mgs2": 0}[scheme]
     for k in range(1, m + 1):
         kap = math.sqrt(np.linalg.cond(M[:k, :k]))
-        fl = 100 * k * 1.1e-16 * max(1.0, kap ** pl)
+        fl = 100 * k * loo_floor_u * max(1.0, kap ** pl)
         a, b = max(loo[k - 1], fl), max(ref_loo[k - 1], fl)
         assert a <= 2 * b and b <= 2 * a, (scheme, k, loo[k - 1], ref_loo[k - 1])
 
@@ -66,6 +66,21 @@ def test_mgs_twenty_vectors_order4_gram_condition_1e6():
     X, C, M = conditioned_inputs(10000, 20, 4, 8, 3, 1e6)
     ref, ref_loo, Q, R, loo, st = run_both("mgs", X, 1e-6)
     compare("mgs", X, M, 1e-6, ref, ref_loo, Q, R, loo, st, 1e-9)
+
+
+@pytest.mark.parametrize("scheme", ["cgs", "mgs", "cgs2", "mgs2", "gram"])
+def test_fp32_bulk_schemes_twenty_vectors_order4(scheme):
+    """The five schemes in FP32-bulk on the 20-vector order-4 workload (cond(Gram) = 1e6,
+    delta = 1e-6) stored in FP32, against the oracle on the same values upcast:
+    R and q within max(delta, 1e-5) kappa^p, LOO within 2x above the FP32 level."""
+    X, C, M = conditioned_inputs(10000, 20, 4, 8, 3, 1e6, dtype=np.float32)
+    X64 = [[(a, [c.astype(np.float64) for c in x]) for a, x in s] for s in X]
+    ref = oracle.orthogonalize(scheme, X64, 1e-6)
+    ref_loo = oracle.loo_curve(ref.Q)
+    tt = need_gpu()
+    A = [dev_sum(s, torch.float32) for s in X]
+    Q, R, loo, st = tt.orthogonalize(scheme, A, 1e-6)
+    compare(scheme, X, M, 1e-6, ref, ref_loo, Q, R, loo, st, 1e-5, loo_floor_u=6e-8)
 
 
 def test_gram_reports_not_spd():
@@ -136,7 +151,7 @@ def test_config2_fp64_prefix_under_rank_guard(scheme, delta):
     Q, R, _, st = tt.orthogonalize(scheme, A, delta, rank_guard=guard, with_loo=False, partial_on_guard=True)
     assert st.get("guard") and 1 <= st["m_reached"] < 50
     assert st["max_pre_rank"] > guard
-    k = min(st["m_reached"], 4)
+    k = st["m_reached"]
     ref = oracle.orthogonalize(scheme, X[:k], delta)
     for i in range(k):
         kap = math.sqrt(np.linalg.cond(M[: i + 1, : i + 1]))
@@ -144,3 +159,27 @@ def test_config2_fp64_prefix_under_rank_guard(scheme, delta):
         assert np.allclose(R[: i + 1, i], ref.R[: i + 1, i], rtol=0, atol=tol * max(1.0, np.abs(ref.R[:, i]).max()))
         qd = diff_norm(host_cores(Q[i]), ref.Q[i]) / oracle.tt_norm(ref.Q[i])
         assert qd <= max(tol, 2 * delta), (scheme, i, qd)
+
+
+@pytest.mark.parametrize("delta", [1e-3, 1e-5, 1e-7])
+def test_config2_cgs2_fp32_bulk_prefix_under_rank_guard(delta):
+    """FP32-bulk CGS2 on the 50 order-6 vectors (cond(Gram) = 1e10) stored in FP32, under
+    the rank guard: every completed step against the oracle on the same values upcast,
+    within max(delta, 1e-5) kappa(A_k)."""
+    tt = need_gpu()
+    X, C, M = conditioned_inputs(20000, 50, 6, 64, 8, 1e10, dtype=np.float32)
+    A = [dev_sum(s, torch.float32) for s in X]
+    Q, R, _, st = tt.orthogonalize("cgs2", A, delta, rank_guard=384, with_loo=False, partial_on_guard=True)
+    assert st.get("guard") and 1 <= st["m_reached"] < 50
+    k = st["m_reached"]
+    X64 = [[(a, [c.astype(np.float64) for c in x]) for a, x in s] for s in X[:k]]
+    ref = oracle.orthogonalize("cgs2", X64, delta)
+    base = max(delta, 1e-5)
+    for i in range(k):
+        kap = math.sqrt(np.linalg.cond(M[: i + 1, : i + 1]))
+        tol = base * max(1.0, kap)
+        if tol > 1e-2:
+            break
+        assert np.allclose(R[: i + 1, i], ref.R[: i + 1, i], rtol=0, atol=tol * max(1.0, np.abs(ref.R[:, i]).max())), (i,)
+        qd = diff_norm(host_cores(Q[i]), ref.Q[i]) / oracle.tt_norm(ref.Q[i])
+        assert qd <= tol, (i, qd, tol)

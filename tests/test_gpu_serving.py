@@ -113,3 +113,28 @@ def test_serving_trace_keeps_bases_orthonormal(dtype, tol):
         assert loo[-1] <= tol * len(s.basis), (loo[-1], len(s.basis))
         # every basis vector keeps the solver's rank (the rounding compresses the projections back)
         assert all(max(q.r) <= s.spec["r"] for q in s.basis)
+
+
+def test_fp32_requests_at_stated_workload_against_oracle_step():
+    """MGS2 requests of the serving workload (solvers with d ~ U{5..8}, n ~ U{32,64,128},
+    rank ~ U{4..9}, 10-39 resident basis vectors; FP32-bulk, delta = 1e-6) against the
+    oracle's MGS2 step on the same FP32 values upcast: q by difference norm and the R
+    column within max(delta, 1e-5) (the basis is orthonormal and w well separated from
+    its span, so kappa is about one)."""
+    tt = need_gpu()
+    import oracle
+    from gpu_util import host_cores, diff_norm
+    from paper_2211_08770_amd import serve
+    solvers, g = serve.make_solvers(3, seed=40401, dtype=torch.float32)
+    eng = tt.Engine()
+    for k, s in enumerate(solvers):
+        first = synth.serving_request(synth.rng(41000 + k), s.spec, len(s.basis))
+        wc = synth.serving_vector(None, s.spec, first)
+        w = tt.TT.from_cores(wc, device="cuda", dtype=torch.float32)
+        status, q, r, _ = _run_alone(eng, "mgs2", s.basis, w, 1e-6, basis_gram=s.gram)
+        assert status == "TT_OK"
+        basis64 = [host_cores(b) for b in s.basis]
+        qref, cref = oracle.gs_step("mgs2", basis64, [c.astype(np.float64) for c in wc], 1e-6)
+        nw = oracle.tt_norm([c.astype(np.float64) for c in wc])
+        assert np.abs(r - cref).max() <= 1e-5 * nw, (k, s.spec["d"], s.spec["n"], np.abs(r - cref).max())
+        assert diff_norm(host_cores(q), qref) <= 1e-5, (k, diff_norm(host_cores(q), qref))

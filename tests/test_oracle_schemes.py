@@ -174,3 +174,15 @@ def test_cond_curve_pins():
     kap = oracle.cond_curve(X)
     assert abs(kap[-1] / math.sqrt(1e6) - 1.0) < 1e-6
     assert np.all(np.diff(kap) >= -1e-9 * kap[1:])   # adding columns never lowers kappa
+
+
+@pytest.mark.parametrize("scheme", ["cgs", "mgs", "cgs2", "mgs2"])
+def test_gs_step_reproduces_the_full_scheme(scheme):
+    """One Gram-Schmidt step against the scheme's own earlier q_j gives the same q_i and
+    column i of R as the full run (the step of Algorithms 1-4, R(i,i) = ||p|| of the last pass)."""
+    X, C, M = conditioned_inputs(51, 5, 3, 4, 2, 1e4)
+    res = oracle.orthogonalize(scheme, X, 1e-6)
+    for i in range(5):
+        q, col = oracle.gs_step(scheme, res.Q[:i], X[i], 1e-6)
+        assert np.array_equal(col, res.R[: i + 1, i])
+        assert all(np.array_equal(a, b) for a, b in zip(q, res.Q[i]))
