@@ -83,6 +83,11 @@ typedef struct tt_ortho_stats {
   int32_t m_reached;          /* vectors completed before any error                      */
   int32_t max_pre_rank;       /* largest bond rank of a vector before rounding           */
   int32_t max_post_rank;      /* largest bond rank of a vector after rounding            */
+  int64_t* q_pre_size;        /* caller HOST array [m] or NULL: packed size (elements) of
+                                 the lazy sum whose rounding gave q_i, i.e. the TT storage
+                                 before that compression; with the packed size of q_i it
+                                 gives the compression gain of Section 2 (a ratio of the
+                                 compression ratios before and after rounding)             */
 } tt_ortho_stats;
 
 typedef struct tt_ctx tt_ctx;

@@ -1038,6 +1038,7 @@ tt_status ortho_householder(tt_ctx* c, int m, const tt_sum* a, double delta, int
     make_job(c, &qsums[i], delta, 0, &q[i], jobs[i]);
     const int64_t pre = max_bond(jobs[i].R, d);
     st.max_pre_rank = (int32_t)std::max<int64_t>(st.max_pre_rank, pre);
+    if (st.q_pre_size) st.q_pre_size[i] = packed_size(a[0].comp[0], jobs[i].R);
     if (rank_guard > 0 && pre > rank_guard)
       return fail(c, TT_EGUARD, "pre-round rank " + std::to_string(pre) + " of q exceeds the guard");
   }
@@ -1306,6 +1307,7 @@ tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum*
   }
   tt_ortho_stats st;
   std::memset(&st, 0, sizeof(st));
+  st.q_pre_size = stats ? stats->q_pre_size : nullptr;
   CallScope scope(c);
   const size_t mark = c->ws_off;
   struct Mark {
@@ -1378,6 +1380,7 @@ tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum*
       make_job(c, &sums[i], delta, 0, &q[i], jobs[i]);
       const int64_t pre = max_bond(jobs[i].R, d);
       st.max_pre_rank = (int32_t)std::max<int64_t>(st.max_pre_rank, pre);
+      if (st.q_pre_size) st.q_pre_size[i] = packed_size(a[0].comp[0], jobs[i].R);
       if (rank_guard > 0 && pre > rank_guard) {
         jobs.resize(i);
         st.m_reached = i;
@@ -1450,6 +1453,7 @@ tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum*
                                              std::to_string(i)));
       }
       tt_vec* dest = &q[i];
+      if (st.q_pre_size && pass + 1 == passes) st.q_pre_size[i] = packed_size(a[0].comp[0], probe.R);
       if (pass + 1 < passes) {
         // first pass of CGS2/MGS2: keep the rounded p_1 in the workspace
         p1 = q[i];

@@ -59,13 +59,16 @@ def make_solvers(nsolvers=64, seed=40000, device="cuda", dtype=torch.float32, **
 
 
 def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget_bytes=8 << 30,
-              max_inflight=64, engine=None):
+              max_inflight=64, engine=None, keep_sample=0):
     """Replay nreq Poisson arrivals at `qps` (requests/s) over the solvers.
 
     Returns a dict with p50/p99 latency (ms), throughput (requests/s),
     admitted/rejected counts, the high-water mark of the device memory the
     loop holds (bases plus in-flight requests) and the engine steps taken.
+    With keep_sample > 0, "sample" holds host copies (float64) of the basis,
+    w, q and the R column of that many requests that completed, for checks.
     """
+    kept = []
     eng = engine or tt.Engine()
     arrivals = np.cumsum(g.exponential(1.0 / qps, size=nreq))
     owners = g.integers(0, len(solvers), size=nreq)
@@ -109,6 +112,7 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
             out = eng.step()
             steps += 1
             tnow = time.perf_counter() - t0
+            inflight_w = {rid: inflight[rid][3] for rid in out}
             for rid, (status, q, r, grow) in out.items():
                 i, s, fp, _ = inflight.pop(rid)
                 held -= fp
@@ -116,6 +120,8 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
                 done += 1
                 lat.append(tnow - reqs[i][0])
                 if status == "TT_OK":
+                    if len(kept) < keep_sample:
+                        kept.append((list(s.basis), inflight_w[rid], q, r))
                     before = s.nbytes()
                     s.append(q, grow)
                     held += s.nbytes() - before
@@ -123,7 +129,9 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
             time.sleep(max(0.0, min(reqs[nxt][0] - (time.perf_counter() - t0), 0.01)))
     wall = time.perf_counter() - t0
     lat_ms = np.array(lat) * 1e3
-    return {"qps_offered": qps, "requests": nreq, "completed": done, "rejected": rejected,
+    host = lambda t: [c.astype(np.float64) for c in t.numpy_cores()]
+    sample = [([host(b) for b in basis], host(w), host(q), np.array(r)) for basis, w, q, r in kept]
+    return {"sample": sample, "qps_offered": qps, "requests": nreq, "completed": done, "rejected": rejected,
             "p50_ms": float(np.percentile(lat_ms, 50)) if len(lat_ms) else None,
             "p99_ms": float(np.percentile(lat_ms, 99)) if len(lat_ms) else None,
             "throughput_rps": done / wall, "wall_s": wall, "engine_steps": steps,

@@ -49,7 +49,7 @@ class _Sum(C.Structure):
 
 class _Stats(C.Structure):
     _fields_ = [("rounds", C.c_int32), ("m_reached", C.c_int32), ("max_pre_rank", C.c_int32),
-                ("max_post_rank", C.c_int32)]
+                ("max_post_rank", C.c_int32), ("q_pre_size", C.POINTER(C.c_int64))]
 
 
 class _Request(C.Structure):
@@ -496,6 +496,8 @@ def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: b
     R = (C.c_double * (m * m))()
     L = (C.c_double * m)()
     stats = _Stats()
+    pre_size = (C.c_int64 * m)()
+    stats.q_pre_size = C.cast(pre_size, C.POINTER(C.c_int64))
     ctx.ensure_ws(256 << 20)
     call = lambda: ctx.lib.tt_orthogonalize(ctx.h, SCHEMES[scheme], m, sums, float(delta), int(rank_guard), vq, R,
                                             L if with_loo else None, C.byref(stats))
@@ -520,7 +522,9 @@ def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: b
     Q = [_finish_out(q, vq[i]) for i, q in enumerate(Q)]
     Rm = np.array(R[:], dtype=np.float64).reshape(m, m).T.copy()   # column-major -> R[j, i]
     st = {"rounds": stats.rounds, "m_reached": stats.m_reached, "max_pre_rank": stats.max_pre_rank,
-          "max_post_rank": stats.max_post_rank}
+          "max_post_rank": stats.max_post_rank,
+          # compression gain of q_i (Section 2): storage of the rounded lazy sum over that of q_i
+          "gain": [int(pre_size[i]) / max(q.size(), 1) for i, q in enumerate(Q)]}
     return Q, Rm, (np.array(L[:]) if with_loo else None), st
 
 

@@ -59,6 +59,13 @@ def test_schemes_small(scheme):
     X, C, M = conditioned_inputs(500, 6, 3, 5, 2, 1e4)
     ref, ref_loo, Q, R, loo, st = run_both(scheme, X, 1e-8)
     compare(scheme, X, M, 1e-8, ref, ref_loo, Q, R, loo, st, 1e-10)
+    # compression gain of each q_i (Section 2): storage of the sum rounded last into q_i over q_i's
+    per = 2 if scheme in ("cgs2", "mgs2") else 1
+    ns = [5, 5, 5]
+    size = lambda r: sum(r[k] * ns[k] * r[k + 1] for k in range(3))
+    for i, q in enumerate(ref.Q):
+        want = size(ref.pre_ranks[per * i + per - 1]) / size(oracle.tt_ranks(q))
+        assert st["gain"][i] == pytest.approx(want, rel=1e-12), (scheme, i)
 
 
 def test_mgs_twenty_vectors_order4_gram_condition_1e6():
