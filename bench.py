@@ -88,16 +88,16 @@ def roofline_of(prof, bulk_fp32=True):
     algorithmic flops over its summed launch durations, against the MFMA peak of its precision."""
     name, p = max(prof.items(), key=lambda kv: kv[1]["ms"])
     achieved = p["flops"] / (p["ms"] * 1e-3) / 1e12 if p["ms"] > 0 else 0.0
-    # FP32-bulk leaves are factored and applied on the FP32 MFMA (157.3 TF/s); tree nodes and the SVD are
-    # FP64 (78.6 TF/s).  The apply kind mixes leaf and node tiles: it is priced at the FP32 peak, so its
-    # fraction is a lower bound.  An FP64 workload runs every kind on the FP64 units.
-    # The Jacobi SVD, the component GEMMs and the TT dots run on the vector ALU ("alu"; the
-    # component GEMMs are FP32 in an FP32-bulk workload), the tile QR kernels on MFMA.
-    alu = name in ("svd_jacobi", "contraction_gemm", "tt_dot", "other")
+    # FP32-bulk leaves are factored and applied on the FP32 MFMA (157.3 TF/s) and the component GEMMs
+    # run there too; tree nodes are FP64 (78.6 TF/s) and the TT dots use the FP64 MFMA for either
+    # dtype.  The apply kind mixes leaf and node tiles: it is priced at the FP32 peak, so its fraction
+    # is a lower bound.  An FP64 workload runs every kind on the FP64 units.  The Jacobi SVD runs on
+    # the vector ALU ("alu", FP64).
+    alu = name in ("svd_jacobi", "other")
     if alu:
-        peak = PEAK["fp32_vector"] if (bulk_fp32 and name == "contraction_gemm") else PEAK["fp64_vector"]
+        peak = PEAK["fp64_vector"]
     else:
-        fp32_kinds = ("qr_factor_leaf", "qr_apply") if bulk_fp32 else ()
+        fp32_kinds = ("qr_factor_leaf", "qr_apply", "contraction_gemm") if bulk_fp32 else ()
         peak = PEAK["fp32_mfma"] if name in fp32_kinds else PEAK["fp64_mfma"]
     return {"bound": "alu" if alu else "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 5), "traffic": None, "kernel": name,
