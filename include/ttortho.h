@@ -169,6 +169,26 @@ tt_status tt_round(tt_ctx* ctx, const tt_sum* x, double delta, int64_t max_rank,
 tt_status tt_round_batched(tt_ctx* ctx, int32_t njobs, const tt_sum* xs, const double* deltas,
                            const int64_t* max_ranks, tt_vec* outs, tt_status* job_status);
 
+/* tt_round_batched without waiting: every left-to-right step is planned at the
+ * rank bounds min(t_{k-1} n_{k-1}, s_k, max_rank) (rows and columns beyond the
+ * rank the device chooses are zero), the result cores are formed at those bound
+ * shapes in the workspace and compacted into outs[j] on the device at the ranks
+ * it chose, so no step waits for the host (the synchronous call reads every rank
+ * back to plan the next step at it).  Same results as tt_round_batched where the
+ * output ranks equal the bounds (bitwise); otherwise equal up to rounding, at the
+ * cost of the padded rows.  The call returns once all work is enqueued on the
+ * context's stream; ranks (HOST pinned int32 [njobs * (TT_MAXD + 1)]: the ranks
+ * of job j at ranks[j * (TT_MAXD + 1) + k], k = 0..d), job_status (HOST pinned
+ * int32 [njobs]: TT_OK, or TT_ECAPACITY when outs[j] cannot hold the result) and
+ * norms (HOST pinned double [njobs] or NULL: ||x_j||) are filled by copies on the
+ * stream: read them, and outs[j].data, after synchronising that stream.  outs[j].r
+ * is not written.  The workspace and the inputs must stay untouched until then;
+ * the next call on the context waits for this one.  Argument errors are returned
+ * before anything is enqueued; the per-launch profiler must be off. */
+tt_status tt_round_batched_async(tt_ctx* ctx, int32_t njobs, const tt_sum* xs, const double* deltas,
+                                 const int64_t* max_ranks, tt_vec* outs, int32_t* ranks, int32_t* job_status,
+                                 double* norms);
+
 /* Upper bound on the packed size (elements) of TT-round(x): ranks are capped
  * by min(sum of component ranks, prod n_{<=k}, prod n_{>k}). */
 int64_t tt_round_out_capacity(const tt_sum* x);

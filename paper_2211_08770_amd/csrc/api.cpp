@@ -157,17 +157,32 @@ namespace {
 
 // Resets the per-call arenas once the stream has drained (every entry point
 // synchronises before returning, so nothing in flight refers to them).
+// Wait for the last asynchronous call of the context (its copies may still read
+// the staging arenas and its kernels the workspace).
+void wait_async(tt_ctx* c) {
+  if (c->async_pending) {
+    (void)hipEventSynchronize(c->async_done);
+    c->async_pending = false;
+  }
+}
+
 struct CallScope {
   tt_ctx* c;
+  bool async = false;   // leave the work in flight: record async_done instead of draining the streams
   explicit CallScope(tt_ctx* ctx) : c(ctx) {
     c->err.clear();
     (void)hipSetDevice(c->device);
+    wait_async(c);
   }
   ~CallScope() {
-    if (c->side) (void)hipStreamSynchronize(c->side);
-    (void)hipStreamSynchronize(c->stream);
+    if (async && c->async_done && hipEventRecord(c->async_done, c->stream) == hipSuccess) {
+      c->async_pending = true;
+    } else {
+      if (c->side) (void)hipStreamSynchronize(c->side);
+      (void)hipStreamSynchronize(c->stream);
+      prof_collect(c);
+    }
     c->ev_used = 0;
-    prof_collect(c);
     c->dev.reset();
     c->pin.reset();
   }
@@ -453,6 +468,7 @@ void tt_ctx_destroy(tt_ctx* c) {
   prof_collect(c);
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->async_done) (void)hipEventDestroy(c->async_done);
   c->dev.release();
   c->pin.release();
   delete c;
@@ -461,6 +477,8 @@ void tt_ctx_destroy(tt_ctx* c) {
 tt_status tt_ctx_set_workspace(tt_ctx* c, void* ws, size_t bytes) {
   if (!c) return TT_EINVAL;
   if (ws && ((uintptr_t)ws & 255)) return fail(c, TT_EINVAL, "workspace must be 256-byte aligned");
+  (void)hipSetDevice(c->device);
+  wait_async(c);   // an asynchronous rounding may still use the old workspace
   c->ws = (char*)ws;
   c->ws_bytes = ws ? bytes : 0;
   c->ws_off = 0;
@@ -660,6 +678,40 @@ tt_status tt_round_batched(tt_ctx* c, int32_t njobs, const tt_sum* xs, const dou
   }
   if (first != TT_OK && c->err.empty()) c->err = "one or more jobs failed (see job_status)";
   return first;
+}
+
+tt_status tt_round_batched_async(tt_ctx* c, int32_t njobs, const tt_sum* xs, const double* deltas,
+                                 const int64_t* max_ranks, tt_vec* outs, int32_t* ranks, int32_t* job_status,
+                                 double* norms) {
+  if (!c || njobs < 0 || (njobs > 0 && (!xs || !deltas || !outs || !ranks || !job_status)))
+    return fail(c, TT_EINVAL, "round async: bad arguments");
+  if (njobs == 0) return TT_OK;
+  if (c->prof) return fail(c, TT_EINVAL, "round async: the per-launch profiler needs the synchronous calls");
+  tt_status s;
+  for (int j = 0; j < njobs; ++j) {
+    if ((s = check_sum(c, &xs[j], "x")) != TT_OK) return s;
+    if ((s = check_vec(c, &outs[j], "out", false)) != TT_OK) return s;
+    if (!same_shape(xs[j].comp[0], outs[j])) return fail(c, TT_EINVAL, "round: out shape differs from x");
+    if (!(deltas[j] >= 0.0) || !std::isfinite(deltas[j])) return fail(c, TT_EINVAL, "round: delta must be >= 0");
+    if (xs[j].comp[0].dtype != xs[0].comp[0].dtype) return fail(c, TT_EINVAL, "round: mixed dtypes in a batch");
+  }
+  CallScope scope(c);
+  if (!c->async_done && hipEventCreateWithFlags(&c->async_done, hipEventDisableTiming) != hipSuccess)
+    return fail(c, TT_EDEVICE, "event");
+  std::vector<RJob> jobs(njobs);
+  for (int j = 0; j < njobs; ++j)
+    make_job(c, &xs[j], deltas[j], max_ranks ? max_ranks[j] : 0, &outs[j], jobs[j]);
+  // every output must hold the bound-shaped result: the compaction checks the exact size on the device
+  RoundMode mode;
+  mode.bound_plan = true;
+  mode.async = true;
+  mode.ranks = ranks;
+  mode.status = job_status;
+  mode.norms = norms;
+  s = round_jobs(c, jobs, mode);
+  if (s != TT_OK) return s;
+  scope.async = true;
+  return TT_OK;
 }
 
 tt_status tt_norm(tt_ctx* c, const tt_sum* x, double* out) {

@@ -67,6 +67,7 @@ struct SvdTask {
   int32_t* rank_out;      // device int
   double* wt;             // ncol x t row-major:  W^T  with W = Sigma_t V_t^T
   double* ur;             // kr x t row-major:  left factor fed to Q application
+  int32_t t_ld;           // > 0: wt and ur have t_ld columns (a bound of the rank), zero beyond t
   int32_t* info;          // device int: sweeps used (diagnostic)
 };
 
@@ -190,6 +191,21 @@ struct CoefTask {
   int32_t modified;
 };
 hipError_t launch_fill_pattern(int dtype, void* x, int64_t n, hipStream_t s);
+// Cores of a rounding planned at rank bounds tb_k, held at their bound shapes in a staging
+// buffer, copied into the packed result at the ranks the device chose (one workgroup per job).
+// geo: [d] n_k, [d+1] tb_k, [d] staging offsets.  ranks[1..d-1] are read; ranks[0] and
+// ranks[d] are set to 1.  status is set to TT_ECAPACITY (-3) when the result exceeds capacity.
+struct CompactTask {
+  const void* staging;
+  void* out;
+  int64_t capacity;
+  const int64_t* geo;
+  int32_t* ranks;
+  int32_t* status;
+  int32_t d;
+  int32_t active;         // 0: only ranks[0] = ranks[d] = 1 (order one or a failed job)
+};
+hipError_t launch_compact(int dtype, const CompactTask* d_tasks, int ntasks, hipStream_t s);
 hipError_t launch_coef_batched(const CoefTask* d_tasks, int ntasks, hipStream_t s);
 
 hipError_t launch_mgs_correct(const double* dots, const double* Gq, int ldg, int i, double* r, double* neg,

@@ -55,6 +55,8 @@ struct tt_ctx {
   // profiler: HIP events around each launch on this context's stream
   bool prof = false;
   bool autotune = false;       // time candidate TSQR tree shapes for unseen shapes
+  hipEvent_t async_done = nullptr;   // end of the last asynchronous call on this context
+  bool async_pending = false;        // the next call waits for it before reusing any buffer
   std::vector<tto::ProfRec> prof_open;
   std::vector<hipEvent_t> prof_pool;
   double prof_ms[tto::PK_COUNT] = {0};
@@ -179,7 +181,22 @@ struct RJob {
 };
 
 tt_status make_job(tt_ctx* c, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out, RJob& job);
-tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs);
+// How a batch of roundings is sequenced.  By default the host reads the rank the
+// device chose after every left-to-right step and plans the next step at that
+// rank.  With bound_plan every step is planned at the rank bounds (the data
+// beyond the chosen rank is zero), the cores are formed at their bound shapes in
+// a staging area and compacted on the device at the end, so nothing waits for the
+// host until the final read-back; with async even that read-back is left to
+// copies into the caller's pinned arrays and the call returns once everything
+// is enqueued.
+struct RoundMode {
+  bool bound_plan = false;
+  bool async = false;
+  int32_t* ranks = nullptr;    // async: caller pinned [njobs * (TT_MAXD + 1)]
+  int32_t* status = nullptr;   // async: caller pinned [njobs]
+  double* norms = nullptr;     // async: caller pinned [njobs] or null
+};
+tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode = RoundMode());
 int64_t round_workspace_bytes(const std::vector<RJob>& jobs);
 // FP32-bulk noise floor of the per-bond threshold, relative to ||x||, for a
 // merged core with s columns: 2 sqrt(s) u_32 (the level below which the SVD

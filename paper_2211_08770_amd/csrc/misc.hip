@@ -374,7 +374,69 @@ __global__ void k_tril(const double* __restrict__ L, int m, double* __restrict__
   out[e] = (j <= i) ? L[e] : 0.0;
 }
 
+template <typename T>
+__global__ __launch_bounds__(NT) void k_compact(const CompactTask* __restrict__ tasks) {
+  constexpr int U = 8;   // elements per thread and chunk
+  const CompactTask tk = tasks[blockIdx.x];
+  const int d = tk.d;
+  if (threadIdx.x == 0) {
+    tk.ranks[0] = 1;
+    tk.ranks[d] = 1;
+  }
+  if (!tk.active) return;
+  const int64_t* n = tk.geo;
+  const int64_t* tb = tk.geo + d;
+  const int64_t* so = tk.geo + 2 * d + 1;
+  const gptr<const T> src = glb((const T*)tk.staging);
+  const gptr<T> dst = glb((T*)tk.out);
+  const bool in_place = tk.staging == tk.out;
+  // every thread walks the same offsets.  Element e of core k moves from so_k + row tb_{k+1} + b
+  // to off_k + row t_{k+1} + b (row = a n_k + i): never to a higher address, and in the order of
+  // the sources, so a chunk is read completely before it is written and no write reaches a
+  // source that is still to be read (off_k <= so_k, t <= tb).
+  int64_t off = 0;
+  for (int k = 0; k < d; ++k) {
+    const int64_t t0 = k == 0 ? 1 : tk.ranks[k], t1 = k + 1 == d ? 1 : tk.ranks[k + 1];
+    const int64_t nk = n[k], sz = t0 * nk * t1;
+    if (t0 > tb[k] || t1 > tb[k + 1]) {   // a rank above its bound: never read past the core
+      if (threadIdx.x == 0) *tk.status = -7;
+      return;
+    }
+    if (off + sz > tk.capacity) {
+      if (threadIdx.x == 0) *tk.status = -3;
+      return;
+    }
+    if (!(in_place && off == so[k] && t0 == tb[k] && t1 == tb[k + 1])) {   // else already in place
+      const int32_t w = (int32_t)t1, wb = (int32_t)tb[k + 1];
+      for (int64_t base = 0; base < sz; base += (int64_t)U * NT) {
+        T v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          const int64_t e = base + j * NT + threadIdx.x;
+          const int32_t row = (int32_t)(e / w), b = (int32_t)(e - (int64_t)row * w);
+          v[j] = e < sz ? src[so[k] + (int64_t)row * wb + b] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+          const int64_t e = base + j * NT + threadIdx.x;
+          if (e < sz) dst[off + e] = v[j];
+        }
+        __syncthreads();
+      }
+    }
+    off += sz;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_compact(int dtype, const CompactTask* d_tasks, int ntasks, hipStream_t s) {
+  if (ntasks <= 0) return hipSuccess;
+  if (dtype == 0) hipLaunchKernelGGL(k_compact<double>, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+  else hipLaunchKernelGGL(k_compact<float>, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+  return hipGetLastError();
+}
 
 hipError_t launch_axpy(int dtype, const AxpyTask* d_tasks, int ntasks, int64_t max_elems, hipStream_t s) {
   if (ntasks <= 0) return hipSuccess;

@@ -312,6 +312,9 @@ struct JobState {
   double* eye = nullptr;
   char* qx_block = nullptr;
   size_t qx_cap = 0;
+  // planning at rank bounds: the result's cores at their bound shapes (core k at stg_off[k])
+  char* stage = nullptr;
+  int64_t stg_off[TT_MAXD] = {0};
 };
 
 // Bytes a tree plan of any M' x N matrix with M' <= M needs, whatever shape the
@@ -355,7 +358,7 @@ size_t tree_apply_bytes(int64_t M, int64_t N, int dtype, int64_t tcols) {
 }
 
 // plan buffers of one job (workspace carving); returns false on unsupported shape
-bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why) {
+bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why, bool bound_plan = false) {
   const int d = jb.d;
   const size_t elt = elt_size(jb.dtype);
   st.s[d] = 1;
@@ -428,6 +431,17 @@ bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why) {
     st.eye = (double*)ws.take((size_t)nmax * nmax * 8);
     st.qx_cap = qx_work;
     st.qx_block = (char*)ws.take(std::max<size_t>(qx_work, 256));
+  }
+  if (bound_plan) {
+    // cores at their bound shapes: in the output itself when it holds them (then only cores
+    // whose ranks fall below the bounds move), else in a workspace staging area
+    int64_t tot = 0;
+    for (int k = 0; k < d; ++k) {
+      st.stg_off[k] = tot;
+      tot += st.tb[k] * jb.n[k] * st.tb[k + 1];
+    }
+    if (jb.out && jb.out->capacity >= tot) st.stage = (char*)jb.out->data;
+    else st.stage = (char*)ws.take((size_t)std::max<int64_t>(tot, 1) * elt);
   }
   return true;
 }
@@ -643,8 +657,9 @@ int64_t round_workspace_bytes(const std::vector<RJob>& jobs) {
   return (int64_t)tmp.ws_off + 4096;
 }
 
-tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
+tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) {
   if (jobs.empty()) return TT_OK;
+  const bool bp = mode.bound_plan;
   const int dtype = jobs[0].dtype;
   for (const RJob& jb : jobs)
     if (jb.dtype != dtype) return fail(c, TT_EINVAL, "all jobs of a batch must share one dtype");
@@ -685,12 +700,25 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       if (jb.orth_only) st[j].C = ws_alloc(c, (size_t)jb.n[0] * elt);   // the materialised sum
     } else {
       std::string why;
-      if (!plan_job(c, jb, st[j], &why)) return fail(c, TT_ENOTIMPL, why);
+      if (!plan_job(c, jb, st[j], &why, bp && !jb.orth_only)) return fail(c, TT_ENOTIMPL, why);
       int64_t b = 0;
       for (int k = 0; k < jb.d; ++k) b += st[j].tb[k] * jb.n[k] * st[j].tb[k + 1];
       need = b;
     }
     (void)need;
+  }
+  if (bp && c->autotune) {
+    // planning at the bounds knows every left-to-right shape now: tune them before any launch
+    for (int j = 0; j < nj; ++j) {
+      const RJob& jb = jobs[j];
+      for (int k = 0; k + 1 < jb.d; ++k) {
+        const int64_t M = st[j].tb[k] * jb.n[k], N = st[j].s[k + 1];
+        if (!tuned_shape(M, N, jb.dtype, nullptr)) {
+          tt_status ts = tune_tree(c, M, N, jb.dtype, nullptr);
+          if (ts != TT_OK) return ts;
+        }
+      }
+    }
   }
   if (c->ws_overflow) {
     c->required = std::max(c->required, c->ws_off);
@@ -1066,6 +1094,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       t.rank_out = d_ranks + (size_t)j * (TT_MAXD + 1) + (k + 1);
       t.wt = js.wt;
       t.ur = js.urb[k & 1];
+      t.t_ld = bp ? (int32_t)js.tb[k + 1] : 0;
       t.info = nullptr;
       sv.push_back(t);
     }
@@ -1080,34 +1109,35 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
     e = launch_svd(dsv, (int)sv.size(), s);
     prof_end(c, spr);
     if (e != hipSuccess) return hip_fail(c, e, "svd");
-    if ((e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=
-        hipSuccess)
+    if (!bp && (e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=
+                   hipSuccess)
       return hip_fail(c, e, "rank readback");
     // rk_ev marks the U factors and trees of this step as ready for the side stream
     hipEvent_t rk_ev = dep_event(c);
     if (!rk_ev) return fail(c, TT_EDEVICE, "event");
     if ((e = hipEventRecord(rk_ev, s)) != hipSuccess) return hip_fail(c, e, "event");
-    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "sync");
+    if (!bp && (e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "sync");
     // (4) output core k = Q_M [U_t; 0]
     std::vector<std::vector<ApplyLevel>> plans;
     for (int j : act) {
       RJob& jb = jobs[j];
       JobState& js = st[j];
-      const int64_t tk1 = h_ranks[(size_t)j * (TT_MAXD + 1) + (k + 1)];
+      const int64_t tk1 = bp ? js.tb[k + 1] : h_ranks[(size_t)j * (TT_MAXD + 1) + (k + 1)];
       if (tk1 < 1 || tk1 > js.tb[k + 1]) return fail(c, TT_EDEVICE, "rank out of range");
       js.t[k + 1] = tk1;
       const int64_t sz = js.t[k] * jb.n[k] * tk1;
-      if (js.out_off + sz > jb.out->capacity) {
+      if (!bp && js.out_off + sz > jb.out->capacity) {
         jb.status = TT_ECAPACITY;
         js.alive = false;
         continue;
       }
+      // at the bounds the core goes to its staging slot, compacted at the end
+      char* dst = bp ? js.stage + (size_t)js.stg_off[k] * elt : (char*)jb.out->data + (size_t)js.out_off * elt;
       Carver cv;
       cv.base = js.ap_side;
       cv.cap = js.ap_cap;
       std::vector<ApplyLevel> pl;
-      plan_apply(cv, js.lr[k & 1], js.urb[k & 1], tk1, tk1, (char*)jb.out->data + (size_t)js.out_off * elt, jb.dtype,
-                 tk1, 1, pl);
+      plan_apply(cv, js.lr[k & 1], js.urb[k & 1], tk1, tk1, dst, jb.dtype, tk1, 1, pl);
       if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "apply scratch");
       plans.push_back(std::move(pl));
       js.out_off += sz;
@@ -1120,7 +1150,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       pend.plans = std::move(plans);
       // with many jobs the side stream carries as much work as the main one and planning the
       // next step takes long: launch the output cores now
-      if (act.size() > 4) {
+      if (act.size() > 4 || bp) {
         tt_status fs = flush_out();
         if (fs != TT_OK) return fs;
       }
@@ -1141,23 +1171,89 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs) {
       if (!js.alive) continue;
       const int k = jb.d - 1;
       const int64_t sz = js.t[k] * jb.n[k];
-      if (js.out_off + sz > jb.out->capacity) {
+      if (!bp && js.out_off + sz > jb.out->capacity) {
         jb.status = TT_ECAPACITY;
         js.alive = false;
         continue;
       }
+      char* dst = bp ? js.stage + (size_t)js.stg_off[k] * elt : (char*)jb.out->data + (size_t)js.out_off * elt;
       Carver cv;
       cv.base = js.ap_block;
       cv.cap = js.ap_cap;
       std::vector<ApplyLevel> pl;
-      plan_apply(cv, js.rl[k], js.wt, js.t[k], js.t[k], (char*)jb.out->data + (size_t)js.out_off * elt, jb.dtype, 1,
-                 jb.n[k], pl);
+      plan_apply(cv, js.rl[k], js.wt, js.t[k], js.t[k], dst, jb.dtype, 1, jb.n[k], pl);
       if (cv.off > cv.cap) return fail(c, TT_ECAPACITY, "apply scratch");
       plans.push_back(std::move(pl));
       js.out_off += sz;
     }
     tt_status rs = launch_apply_plans(c, plans, dtype);
     if (rs != TT_OK) return rs;
+  }
+  if (bp) {
+    // ---------------- cores from their bound shapes into the packed results, at the device's ranks
+    std::vector<int32_t> hst(nj);
+    std::vector<int64_t> geo;
+    std::vector<size_t> goff(nj, 0);
+    for (int j = 0; j < nj; ++j) {
+      const RJob& jb = jobs[j];
+      hst[j] = (int32_t)jb.status;
+      if (jb.d < 2 || jb.orth_only || !st[j].alive) continue;
+      goff[j] = geo.size();
+      for (int k = 0; k < jb.d; ++k) geo.push_back(jb.n[k]);
+      for (int k = 0; k <= jb.d; ++k) geo.push_back(st[j].tb[k]);
+      for (int k = 0; k < jb.d; ++k) geo.push_back(st[j].stg_off[k]);
+    }
+    int32_t* d_status = (int32_t*)upload(c, hst);   // the statuses decided on the host; compaction may add TT_ECAPACITY
+    const int64_t* dgeo = geo.empty() ? nullptr : upload(c, geo);
+    if (!d_status || (!geo.empty() && !dgeo)) return fail(c, TT_ENOMEM, "compaction buffers");
+    std::vector<CompactTask> ct;
+    for (int j = 0; j < nj; ++j) {
+      const RJob& jb = jobs[j];
+      CompactTask t;
+      std::memset(&t, 0, sizeof(t));
+      t.d = jb.d;
+      t.ranks = d_ranks + (size_t)j * (TT_MAXD + 1);
+      t.status = d_status + j;
+      t.active = (jb.d >= 2 && !jb.orth_only && st[j].alive && jb.status == TT_OK) ? 1 : 0;
+      if (t.active) {
+        t.staging = st[j].stage;
+        t.out = jb.out->data;
+        t.capacity = jb.out->capacity;
+        t.geo = dgeo + goff[j];
+      }
+      ct.push_back(t);
+    }
+    const CompactTask* dct = upload(c, ct);
+    if (!dct) return fail(c, TT_ENOMEM, "task upload");
+    if ((e = launch_compact(dtype, dct, (int)ct.size(), s)) != hipSuccess) return hip_fail(c, e, "compaction");
+    if (mode.async) {
+      // results, ranks, statuses and norms reach the caller through copies on the stream
+      if ((e = hipMemcpyAsync(mode.ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=
+              hipSuccess ||
+          (e = hipMemcpyAsync(mode.status, d_status, (size_t)nj * 4, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+          (mode.norms && (e = hipMemcpyAsync(mode.norms, d_norms, (size_t)nj * 8, hipMemcpyDeviceToHost, s)) !=
+                             hipSuccess))
+        return hip_fail(c, e, "result copies");
+      return TT_OK;
+    }
+    int32_t* h_status = (int32_t*)c->pin.alloc((size_t)nj * 4);
+    if (!h_status) return fail(c, TT_ENOMEM, "small buffers");
+    if ((e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(h_status, d_status, (size_t)nj * 4, hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return hip_fail(c, e, "rank readback");
+    if ((e = hipMemcpyAsync(h_norms, d_norms, (size_t)nj * 8, hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return hip_fail(c, e, "norm readback");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "sync");
+    for (int j = 0; j < nj; ++j) {
+      RJob& jb = jobs[j];
+      jb.status = (tt_status)h_status[j];
+      if (jb.status != TT_OK) continue;
+      jb.norm = h_norms[j];
+      if (jb.orth_only) continue;
+      for (int k = 0; k <= jb.d; ++k) jb.out->r[k] = h_ranks[(size_t)j * (TT_MAXD + 1) + k];
+    }
+    return TT_OK;
   }
   // ---------------- norms back, ranks out
   if ((e = hipMemcpyAsync(h_norms, d_norms, (size_t)nj * 8, hipMemcpyDeviceToHost, s)) != hipSuccess)

@@ -515,11 +515,12 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
     }
     __syncthreads();
   }
-  // W^T: ncol x t
-  for (int64_t idx = tid; idx < (int64_t)N * t; idx += NT) {
-    const int col = (int)(idx / t), i = (int)(idx - (int64_t)col * t);
+  // W^T: ncol x t (x ld columns, zero beyond t, when a rank bound sets the layout)
+  const int ld = tk.t_ld > 0 ? tk.t_ld : t;
+  for (int64_t idx = tid; idx < (int64_t)N * ld; idx += NT) {
+    const int col = (int)(idx / ld), i = (int)(idx - (int64_t)col * ld);
     double v = 0.0;
-    if (!degenerate && i < k) {
+    if (!degenerate && i < k && i < t) {
       const int j = perm[i];
       if (tall) {
         // row i of W = Sigma_t V_t^T = U_t^T R, with U_t = (final column)/sigma
@@ -550,11 +551,13 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
     }
     tk.wt[idx] = v;
   }
-  // U_R: kr x t
-  for (int64_t idx = tid; idx < (int64_t)kr * t; idx += NT) {
-    const int row = (int)(idx / t), i = (int)(idx - (int64_t)row * t);
+  // U_R: kr x t (x ld columns, zero beyond t)
+  for (int64_t idx = tid; idx < (int64_t)kr * ld; idx += NT) {
+    const int row = (int)(idx / ld), i = (int)(idx - (int64_t)row * ld);
     double v;
-    if (degenerate || i >= k) {
+    if (i >= t) {
+      v = 0.0;
+    } else if (degenerate || i >= k) {
       v = (row == i) ? 1.0 : 0.0;
     } else {
       const int j = perm[i];

@@ -111,6 +111,10 @@ def _load():
         lib.tt_orthogonalize.restype = C.c_int
         lib.tt_loo.argtypes = [P, C.c_int32, C.POINTER(_Vec), C.POINTER(C.c_double), C.POINTER(C.c_double)]
         lib.tt_loo.restype = C.c_int
+        lib.tt_round_batched_async.argtypes = [P, C.c_int32, C.POINTER(_Sum), C.POINTER(C.c_double),
+                                               C.POINTER(C.c_int64), C.POINTER(_Vec), C.c_void_p, C.c_void_p,
+                                               C.c_void_p]
+        lib.tt_round_batched_async.restype = C.c_int
         lib.tt_round_effective_delta.argtypes = [C.POINTER(_Sum), C.c_double]
         lib.tt_round_effective_delta.restype = C.c_double
         lib.tt_orthogonalize_capacity.argtypes = [C.c_int32, C.c_int32, C.POINTER(_Sum), C.c_int64,
@@ -427,8 +431,16 @@ def round(x, delta: float, max_rank: int = 0, return_norm: bool = False):
     return (out, nrm.value) if return_norm else out
 
 
-def round_batched(xs, deltas, max_ranks=None):
-    """Independent roundings of several TTs / lazy sums in shared launches."""
+def round_batched(xs, deltas, max_ranks=None, plan="host"):
+    """Independent roundings of several TTs / lazy sums in shared launches.
+
+    plan="host": tt_round_batched (each left-to-right step planned at the rank the device
+    chose, read back by the host).  plan="bounds": tt_round_batched_async (every step planned
+    at the rank bounds, no host synchronisation until the end), then the stream is synchronised
+    and the ranks and statuses are read from pinned memory.
+    """
+    if plan == "bounds":
+        return _round_batched_bounds(xs, deltas, max_ranks)
     n = len(xs)
     hs = [_SumHolder(x) for x in xs]
     ctx = _ctx(hs[0].tts[0].data.device.index)
@@ -444,6 +456,34 @@ def round_batched(xs, deltas, max_ranks=None):
     ctx.ensure_ws(ws)
     ctx.call_with_ws(lambda: ctx.lib.tt_round_batched(ctx.h, n, sums, dl, mr, vos, st))
     return [_finish_out(o, vos[i]) for i, o in enumerate(outs)]
+
+
+def _round_batched_bounds(xs, deltas, max_ranks=None):
+    n = len(xs)
+    hs = [_SumHolder(x) for x in xs]
+    ctx = _ctx(hs[0].tts[0].data.device.index)
+    outs = [_new_out(x) for x in xs]
+    vos = (_Vec * n)(*[o._vec() for o in outs])
+    sums = (_Sum * n)(*[h.s for h in hs])
+    if np.isscalar(deltas):
+        deltas = [deltas] * n
+    dl = (C.c_double * n)(*[float(v) for v in deltas])
+    mr = (C.c_int64 * n)(*([int(v) for v in max_ranks] if max_ranks is not None else [0] * n))
+    ranks = torch.zeros(n * (TT_MAXD + 1), dtype=torch.int32, pin_memory=True)
+    status = torch.full((n,), -99, dtype=torch.int32, pin_memory=True)
+    ws = sum(max(int(ctx.lib.tt_round_workspace_bytes(C.byref(h.s))), 0) for h in hs)
+    ctx.ensure_ws(ws)
+    ctx.call_with_ws(lambda: ctx.lib.tt_round_batched_async(ctx.h, n, sums, dl, mr, vos, C.c_void_p(ranks.data_ptr()),
+                                                             C.c_void_p(status.data_ptr()), None))
+    torch.cuda.current_stream(ctx.device).synchronize()
+    st = status.tolist()
+    rk = ranks.view(n, TT_MAXD + 1).tolist()
+    for j, o in enumerate(outs):
+        if st[j] != 0:
+            raise TTError(st[j], f"job {j} failed")
+        o.r = [int(v) for v in rk[j][: o.d + 1]]
+        o.data = o.data[: o.size()]
+    return outs
 
 
 def q_rank_bounds(scheme: str, ra, ns, rank_guard: int = 0):
