@@ -189,6 +189,19 @@ tt_status tt_round_batched_async(tt_ctx* ctx, int32_t njobs, const tt_sum* xs, c
                                  const int64_t* max_ranks, tt_vec* outs, int32_t* ranks, int32_t* job_status,
                                  double* norms);
 
+/* Graph replay of tt_round_batched_async (for loops that round new data in the same
+ * buffers): when on, the first call with a given set of arguments -- every pointer,
+ * shape, rank, coefficient, accuracy, rank cap and capacity, the workspace and the
+ * result arrays -- runs and is then captured as a HIP graph on the context's stream
+ * (which must not be the legacy default stream; there the capture is refused and the
+ * calls run directly); later calls with the same arguments launch that graph, which
+ * reads whatever the input buffers hold by then.  Each entry keeps its task
+ * descriptors in a device block of its own (a few MB); at most 16 entries, the least
+ * recently used dropped.  Off (0) drops them all.  tt_ctx_graph_count returns the
+ * number of entries that hold a graph. */
+tt_status tt_ctx_set_graphs(tt_ctx* ctx, int on);
+int32_t tt_ctx_graph_count(const tt_ctx* ctx);
+
 /* Upper bound on the packed size (elements) of TT-round(x): ranks are capped
  * by min(sum of component ranks, prod n_{<=k}, prod n_{>k}). */
 int64_t tt_round_out_capacity(const tt_sum* x);

@@ -78,7 +78,43 @@ void* ws_alloc(tt_ctx* c, size_t bytes) {
   return c->ws + off;
 }
 
+char* ReplayArena::alloc(size_t bytes) {
+  bytes = (bytes + 255) & ~(size_t)255;
+  while (cur < chunks.size() && off + bytes > chunks[cur].second) {
+    ++cur;
+    off = 0;
+  }
+  if (cur == chunks.size()) {
+    const size_t want = std::max<size_t>(bytes, chunks.empty() ? (size_t)1 << 20 : chunks.back().second * 2);
+    char* p = nullptr;
+    if (hipMalloc((void**)&p, want) != hipSuccess || !p) return nullptr;
+    chunks.push_back({p, want});
+    off = 0;
+  }
+  char* p = chunks[cur].first + off;
+  off += bytes;
+  return p;
+}
+
+void ReplayArena::release() {
+  for (auto& ch : chunks) (void)hipFree(ch.first);
+  chunks.clear();
+  rewind();
+}
+
 void* upload_bytes(tt_ctx* c, const void* src, size_t bytes) {
+  if (c->graph_arena) {
+    char* d = c->graph_arena->alloc(bytes);
+    if (!d) return nullptr;
+    if (c->graph_capturing) return d;   // the building pass put the same bytes here
+    char* h = c->pin.alloc(bytes);
+    if (!h) return nullptr;
+    std::memcpy(h, src, bytes);
+    if (hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, c->upload_stream ? c->upload_stream : c->stream) !=
+        hipSuccess)
+      return nullptr;
+    return d;
+  }
   char* d = c->dev.alloc(bytes);
   char* h = c->pin.alloc(bytes);
   if (!d || !h) return nullptr;
@@ -89,7 +125,7 @@ void* upload_bytes(tt_ctx* c, const void* src, size_t bytes) {
   return d;
 }
 
-void* dev_scratch(tt_ctx* c, size_t bytes) { return c->dev.alloc(bytes); }
+void* dev_scratch(tt_ctx* c, size_t bytes) { return c->graph_arena ? c->graph_arena->alloc(bytes) : c->dev.alloc(bytes); }
 
 static hipEvent_t prof_event(tt_ctx* c) {
   if (!c->prof_pool.empty()) {
@@ -469,6 +505,12 @@ void tt_ctx_destroy(tt_ctx* c) {
   for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   if (c->async_done) (void)hipEventDestroy(c->async_done);
+  for (GraphEntry* g : c->graph_cache) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    g->arena.release();
+    delete g;
+  }
+  c->graph_cache.clear();
   c->dev.release();
   c->pin.release();
   delete c;
@@ -698,20 +740,140 @@ tt_status tt_round_batched_async(tt_ctx* c, int32_t njobs, const tt_sum* xs, con
   CallScope scope(c);
   if (!c->async_done && hipEventCreateWithFlags(&c->async_done, hipEventDisableTiming) != hipSuccess)
     return fail(c, TT_EDEVICE, "event");
-  std::vector<RJob> jobs(njobs);
-  for (int j = 0; j < njobs; ++j)
-    make_job(c, &xs[j], deltas[j], max_ranks ? max_ranks[j] : 0, &outs[j], jobs[j]);
-  // every output must hold the bound-shaped result: the compaction checks the exact size on the device
   RoundMode mode;
   mode.bound_plan = true;
   mode.async = true;
   mode.ranks = ranks;
   mode.status = job_status;
   mode.norms = norms;
-  s = round_jobs(c, jobs, mode);
-  if (s != TT_OK) return s;
+  auto run = [&]() -> tt_status {
+    std::vector<RJob> jobs(njobs);
+    for (int j = 0; j < njobs; ++j)
+      make_job(c, &xs[j], deltas[j], max_ranks ? max_ranks[j] : 0, &outs[j], jobs[j]);
+    return round_jobs(c, jobs, mode);
+  };
+  if (!c->graphs) {
+    s = run();
+    if (s != TT_OK) return s;
+    scope.async = true;
+    return TT_OK;
+  }
+  // graph replay: the exact bytes of every argument that reaches a launch (pointers, shapes,
+  // coefficients, accuracies, capacities, workspace) name the entry
+  std::string sig;
+  auto put = [&](const void* p, size_t n) { sig.append((const char*)p, n); };
+  put(&njobs, sizeof(njobs));
+  put(&c->ws, sizeof(c->ws));
+  put(&c->ws_bytes, sizeof(c->ws_bytes));
+  put(&c->stream, sizeof(c->stream));
+  put(&ranks, sizeof(ranks));
+  put(&job_status, sizeof(job_status));
+  put(&norms, sizeof(norms));
+  for (int j = 0; j < njobs; ++j) {
+    put(&xs[j].ncomp, sizeof(int32_t));
+    for (int i = 0; i < xs[j].ncomp; ++i) {
+      const tt_vec& v = xs[j].comp[i];
+      put(&xs[j].coef[i], sizeof(double));
+      put(&v.d, sizeof(v.d));
+      put(&v.dtype, sizeof(v.dtype));
+      put(v.n, sizeof(int64_t) * v.d);
+      put(v.r, sizeof(int64_t) * (v.d + 1));
+      put(&v.data, sizeof(v.data));
+    }
+    put(&deltas[j], sizeof(double));
+    const int64_t mr = max_ranks ? max_ranks[j] : 0;
+    put(&mr, sizeof(mr));
+    put(&outs[j].data, sizeof(outs[j].data));
+    put(&outs[j].capacity, sizeof(outs[j].capacity));
+  }
+  GraphEntry* ent = nullptr;
+  for (GraphEntry* g : c->graph_cache)
+    if (g->sig == sig) ent = g;
+  ++c->graph_clock;
+  if (ent && ent->exec) {
+    ent->last_use = c->graph_clock;
+    hipError_t e = hipGraphLaunch(ent->exec, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+    scope.async = true;
+    return TT_OK;
+  }
+  if (ent) {   // not capturable: run directly
+    s = run();
+    if (s != TT_OK) return s;
+    scope.async = true;
+    return TT_OK;
+  }
+  if (c->graph_cache.size() >= 16) {   // drop the least recently used entry
+    auto it = std::min_element(c->graph_cache.begin(), c->graph_cache.end(),
+                               [](const GraphEntry* a, const GraphEntry* b) { return a->last_use < b->last_use; });
+    (void)hipStreamSynchronize(c->stream);
+    if ((*it)->exec) (void)hipGraphExecDestroy((*it)->exec);
+    (*it)->arena.release();
+    delete *it;
+    c->graph_cache.erase(it);
+  }
+  ent = new GraphEntry;
+  ent->sig = sig;
+  ent->last_use = c->graph_clock;
+  c->graph_cache.push_back(ent);
+  // pass 1: run the call, its descriptors going to the entry's block (again when it tuned
+  // tree shapes on the way: the tuning's own allocations must not shift the block's layout)
+  c->graph_arena = &ent->arena;
+  for (int pass = 0; pass < 2; ++pass) {
+    const uint64_t tuned = c->tune_count;
+    ent->arena.rewind();
+    s = run();
+    if (s != TT_OK) {
+      c->graph_arena = nullptr;
+      return s;
+    }
+    if (c->tune_count == tuned) break;
+  }
+  // pass 2: capture the same launches (the block already holds their descriptors)
+  ent->arena.rewind();
+  c->graph_capturing = true;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+  tt_status cs = TT_OK;
+  if (e == hipSuccess) {
+    const std::string keep_err = c->err;
+    cs = run();
+    hipError_t e2 = hipStreamEndCapture(c->stream, &graph);
+    if (cs == TT_OK && e2 == hipSuccess && graph) {
+      if (hipGraphInstantiate(&ent->exec, graph, nullptr, nullptr, 0) != hipSuccess) ent->exec = nullptr;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    c->err = keep_err;
+  }
+  (void)hipGetLastError();   // a failed capture leaves the entry without a graph: later calls run directly
+  c->graph_capturing = false;
+  c->graph_arena = nullptr;
   scope.async = true;
   return TT_OK;
+}
+
+tt_status tt_ctx_set_graphs(tt_ctx* c, int on) {
+  if (!c) return TT_EINVAL;
+  (void)hipSetDevice(c->device);
+  wait_async(c);
+  if (!on) {
+    (void)hipStreamSynchronize(c->stream);
+    for (GraphEntry* g : c->graph_cache) {
+      if (g->exec) (void)hipGraphExecDestroy(g->exec);
+      g->arena.release();
+      delete g;
+    }
+    c->graph_cache.clear();
+  }
+  c->graphs = on != 0;
+  return TT_OK;
+}
+
+int32_t tt_ctx_graph_count(const tt_ctx* c) {
+  if (!c) return -1;
+  int32_t n = 0;
+  for (const GraphEntry* g : c->graph_cache) n += g->exec ? 1 : 0;
+  return n;
 }
 
 tt_status tt_norm(tt_ctx* c, const tt_sum* x, double* out) {

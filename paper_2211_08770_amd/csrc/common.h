@@ -204,6 +204,7 @@ struct CompactTask {
   int32_t* status;
   int32_t d;
   int32_t active;         // 0: only ranks[0] = ranks[d] = 1 (order one or a failed job)
+  int32_t init_status;    // the job's status as the host decided it, written to *status first
 };
 hipError_t launch_compact(int dtype, const CompactTask* d_tasks, int ntasks, hipStream_t s);
 hipError_t launch_coef_batched(const CoefTask* d_tasks, int ntasks, hipStream_t s);

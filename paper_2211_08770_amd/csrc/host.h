@@ -24,6 +24,30 @@ struct Arena {
   void release();
 };
 
+// Device block of a captured graph: descriptors and small scalars of one call,
+// allocated in the same order on every pass, so that after rewind() the same
+// request sequence yields the same addresses (the capture pass then finds the
+// descriptors the first pass uploaded already in place).
+struct ReplayArena {
+  std::vector<std::pair<char*, size_t>> chunks;
+  size_t cur = 0, off = 0;
+  char* alloc(size_t bytes);
+  void rewind() {
+    cur = 0;
+    off = 0;
+  }
+  void release();
+};
+
+// A captured tt_round_batched_async call: the exact argument bytes it was taken
+// for, its descriptor block and the instantiated graph (null: not capturable).
+struct GraphEntry {
+  std::string sig;
+  ReplayArena arena;
+  hipGraphExec_t exec = nullptr;
+  uint64_t last_use = 0;
+};
+
 }  // namespace tto
 
 namespace tto {
@@ -57,6 +81,13 @@ struct tt_ctx {
   bool autotune = false;       // time candidate TSQR tree shapes for unseen shapes
   hipEvent_t async_done = nullptr;   // end of the last asynchronous call on this context
   bool async_pending = false;        // the next call waits for it before reusing any buffer
+  // graph replay of repeated asynchronous batched roundings
+  bool graphs = false;
+  std::vector<tto::GraphEntry*> graph_cache;
+  uint64_t graph_clock = 0;
+  tto::ReplayArena* graph_arena = nullptr;   // set while a call builds or captures an entry
+  bool graph_capturing = false;              // uploads find their data in place: no copies
+  uint64_t tune_count = 0;                   // tree-shape tunings run (they allocate and launch too)
   std::vector<tto::ProfRec> prof_open;
   std::vector<hipEvent_t> prof_pool;
   double prof_ms[tto::PK_COUNT] = {0};

@@ -382,6 +382,7 @@ __global__ __launch_bounds__(NT) void k_compact(const CompactTask* __restrict__ 
   if (threadIdx.x == 0) {
     tk.ranks[0] = 1;
     tk.ranks[d] = 1;
+    *tk.status = tk.init_status;
   }
   if (!tk.active) return;
   const int64_t* n = tk.geo;

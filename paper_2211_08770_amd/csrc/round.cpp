@@ -553,6 +553,7 @@ tt_status tune_tree(tt_ctx* c, int64_t M, int64_t N, int dtype, TreeShape* best_
       if (g * kc <= QR_MAXROWS) cand.push_back(TreeShape{(int32_t)b, (int32_t)g});
   }
   if (cand.empty()) return TT_OK;
+  ++c->tune_count;
   const size_t elt = elt_size(dtype);
   const size_t mark = c->ws_off;
   struct Reset {
@@ -1203,7 +1204,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       for (int k = 0; k <= jb.d; ++k) geo.push_back(st[j].tb[k]);
       for (int k = 0; k < jb.d; ++k) geo.push_back(st[j].stg_off[k]);
     }
-    int32_t* d_status = (int32_t*)upload(c, hst);   // the statuses decided on the host; compaction may add TT_ECAPACITY
+    int32_t* d_status = (int32_t*)dev_scratch(c, (size_t)nj * 4);   // written by the compaction
     const int64_t* dgeo = geo.empty() ? nullptr : upload(c, geo);
     if (!d_status || (!geo.empty() && !dgeo)) return fail(c, TT_ENOMEM, "compaction buffers");
     std::vector<CompactTask> ct;
@@ -1214,6 +1215,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       t.d = jb.d;
       t.ranks = d_ranks + (size_t)j * (TT_MAXD + 1);
       t.status = d_status + j;
+      t.init_status = hst[j];   // the status decided on the host; the compaction may add TT_ECAPACITY
       t.active = (jb.d >= 2 && !jb.orth_only && st[j].alive && jb.status == TT_OK) ? 1 : 0;
       if (t.active) {
         t.staging = st[j].stage;

@@ -20,7 +20,7 @@ import torch
 __all__ = ["TT", "dot", "dot_batched", "axpy", "norm", "round", "round_batched", "round_randomized", "orthogonalize",
            "loo", "laplacian",
            "krylov_laplacian",
-           "Engine", "TTError", "cond", "effective_delta", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
+           "Engine", "TTError", "cond", "effective_delta", "BatchRounder", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
 
 TT_MAXD = 64
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -115,6 +115,10 @@ def _load():
                                                C.POINTER(C.c_int64), C.POINTER(_Vec), C.c_void_p, C.c_void_p,
                                                C.c_void_p]
         lib.tt_round_batched_async.restype = C.c_int
+        lib.tt_ctx_set_graphs.argtypes = [P, C.c_int]
+        lib.tt_ctx_set_graphs.restype = C.c_int
+        lib.tt_ctx_graph_count.argtypes = [P]
+        lib.tt_ctx_graph_count.restype = C.c_int32
         lib.tt_round_effective_delta.argtypes = [C.POINTER(_Sum), C.c_double]
         lib.tt_round_effective_delta.restype = C.c_double
         lib.tt_orthogonalize_capacity.argtypes = [C.c_int32, C.c_int32, C.POINTER(_Sum), C.c_int64,
@@ -484,6 +488,58 @@ def _round_batched_bounds(xs, deltas, max_ranks=None):
         o.r = [int(v) for v in rk[j][: o.d + 1]]
         o.data = o.data[: o.size()]
     return outs
+
+
+class BatchRounder:
+    """Repeated roundings of same-shaped inputs that stay in the same buffers (a solver loop):
+    tt_round_batched_async on a stream of its own, with graph replay on (tt_ctx_set_graphs),
+    so the first run() is captured and later ones launch the graph.  The outputs and the pinned
+    rank/status arrays are allocated once; results() waits for the stream and returns the TTs."""
+
+    def __init__(self, xs, deltas, max_ranks=None, graphs=True):
+        self.n = n = len(xs)
+        self.hs = [_SumHolder(x) for x in xs]
+        dev = self.hs[0].tts[0].data.device
+        self.stream = torch.cuda.Stream(device=dev)
+        with torch.cuda.stream(self.stream):
+            self.ctx = _ctx(dev.index)
+        self.ctx.check(self.ctx.lib.tt_ctx_set_graphs(self.ctx.h, 1 if graphs else 0))
+        self.outs = [_new_out(x) for x in xs]
+        self.cap = [o.data for o in self.outs]
+        self.vos = (_Vec * n)(*[o._vec() for o in self.outs])
+        self.sums = (_Sum * n)(*[h.s for h in self.hs])
+        if np.isscalar(deltas):
+            deltas = [deltas] * n
+        self.dl = (C.c_double * n)(*[float(v) for v in deltas])
+        self.mr = (C.c_int64 * n)(*([int(v) for v in max_ranks] if max_ranks is not None else [0] * n))
+        self.ranks = torch.zeros(n * (TT_MAXD + 1), dtype=torch.int32, pin_memory=True)
+        self.status = torch.full((n,), -99, dtype=torch.int32, pin_memory=True)
+        ws = sum(max(int(self.ctx.lib.tt_round_workspace_bytes(C.byref(h.s))), 0) for h in self.hs)
+        self.ctx.ensure_ws(2 * ws)
+
+    def run(self):
+        """Enqueue one rounding of every input (after the work of the current stream)."""
+        self.stream.wait_stream(torch.cuda.current_stream(self.stream.device))
+        c = self.ctx
+        c.call_with_ws(lambda: c.lib.tt_round_batched_async(c.h, self.n, self.sums, self.dl, self.mr, self.vos,
+                                                            C.c_void_p(self.ranks.data_ptr()),
+                                                            C.c_void_p(self.status.data_ptr()), None))
+
+    def graph_count(self):
+        return int(self.ctx.lib.tt_ctx_graph_count(self.ctx.h))
+
+    def results(self):
+        self.stream.synchronize()
+        st = self.status.tolist()
+        rk = self.ranks.view(self.n, TT_MAXD + 1).tolist()
+        out = []
+        for j, o in enumerate(self.outs):
+            if st[j] != 0:
+                raise TTError(st[j], f"job {j} failed")
+            t = TT(self.cap[j], o.n, [int(v) for v in rk[j][: o.d + 1]])
+            t.data = t.data[: t.size()]
+            out.append(t)
+        return out
 
 
 def q_rank_bounds(scheme: str, ra, ns, rank_guard: int = 0):
