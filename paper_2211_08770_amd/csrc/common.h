@@ -16,6 +16,7 @@ namespace tto {
 constexpr int QR_NB = 16;          // panel width
 constexpr int QR_THREADS = 1024;   // 16 waves per tile
 constexpr int QR_MAXROWS = 800;    // LDS panel: QR_MAXROWS x QR_NB doubles = 100 KiB (fan-in 4 at 200 columns)
+constexpr int QR_BLOCK_COLS = 384; // columns per block of a column-blocked QR (fan-in 2, 768-row tiles)
 
 struct QrTask {
   const void* src;        // leaf: element (r, c) at src[r * src_rs + c * src_cs]
@@ -25,12 +26,17 @@ struct QrTask {
   int32_t kc0, kc_last;   // node: rows contributed by each child but the last, and by the last
   int32_t m, ncol;        // tile shape
   void* tile;             // row-major m x ncol
-  double* tau;            // [min(m, ncol)]
+  double* tau;            // [min(m, nfact)]
   void* tmat;             // [npanels][QR_NB][QR_NB] doubles: T of each panel (I - V T V^T)
+  int32_t nfact;          // columns factored (0: all); the columns beyond are carried and
+                          // updated by the reflectors (a column block of a blocked QR).  A node
+                          // then stacks the top min(m, nfact) rows of each child: triangular in
+                          // the factored columns, full in the carried ones.
 };
 
-// Apply the orthogonal factor of a factored tile:  out = Q * [X; 0].
-// X is k_in x t (double, row-major, ld = x_ld); out is m x t.
+// Apply the orthogonal factor of a factored tile:  out = Q * [X; Z].
+// X is k_in x t (double, row-major, ld = x_ld); Z holds the rows k_in..m-1 (double,
+// row-major, ld = rest_ld) or is zero when rest is null; out is m x t.
 struct ApplyTask {
   const void* tile;       // factored tile (V below the diagonal), ld = ncol
   const double* tau;
@@ -43,12 +49,15 @@ struct ApplyTask {
   double* work;           // m x t row-major scratch (tree nodes keep their result here)
   void* out;              // leaves: final destination (out dtype), strides below
   int64_t out_rs, out_cs;
-  int32_t to_out;         // 1: write to out (with cast); 0: result stays in work
+  int32_t to_out;         // 1: write to out (with cast); 2: write to out as double; 0: result stays in work
+  const double* rest;     // rows k_in..m-1 of the input (null: zero)
+  int64_t rest_ld;
 };
 
 // ---------------------------------------------------------------------------
 // One-sided Jacobi SVD of a (kr x ncol) upper-trapezoidal R factor, FP64.
 // ---------------------------------------------------------------------------
+constexpr int SVD_MAXROWS = 1024;   // rows of the R factor (columns of the Jacobi problem)
 struct SvdTask {
   const void* R;          // row-major kr x ncol, ld = r_ld (root tile of a TSQR)
   int64_t r_ld;
@@ -126,6 +135,20 @@ struct DotTask {
   void* tmp;              // scratch >= max_k rx_k * n_k * ry_{k+1} doubles
   double* out;            // result slot: coef * <x, y>
 };
+
+// Batched copy of row-major blocks between dtypes (column-blocked QR: trailing
+// rows of the tiles gathered into the next block's matrix, R factors assembled):
+//   dst[r * dst_ld + c] = (src && !(tri && c < r)) ? src[r * src_ld + c] : 0
+struct BlockCopy {
+  const void* src;
+  int64_t src_ld;
+  void* dst;
+  int64_t dst_ld;
+  int32_t rows, cols;
+  int32_t src_f32, dst_f32;
+  int32_t tri;            // 1: entries left of the diagonal written as zero
+};
+hipError_t launch_block_copy(const BlockCopy* d_tasks, int ntasks, int64_t max_rows, hipStream_t s);
 
 // Batched strided copy: dst[i] = coef * src[i] (+ dst[i] when accumulate).
 struct CopySeg {

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "../../include/ttortho.h"
@@ -156,10 +157,22 @@ struct Tree {
   int leaf_dtype = 0;                           // 0 f64, 1 f32
   std::vector<std::vector<QrTask>> lvl;         // lvl[0] = leaves
   std::vector<int64_t> leaf_row0;               // first row of each leaf
-  int kr() const;                               // rows of the root R factor
-  const void* root_R() const;                   // root tile (row-major, ld = N)
-  int root_f32() const { return lvl.size() == 1 && leaf_dtype == TT_F32 ? 1 : 0; }   // dtype of root_R
+  // Column-blocked QR, for a matrix too wide for one tree (more than QR_MAXROWS rows and
+  // more than QR_MAXROWS / 2 columns): the tiles factor the first nf columns and carry
+  // the others through their reflectors; the rows each tile leaves behind (rows
+  // min(m, nf)..m-1 of the carried columns, tiles in level order) are gathered into
+  // `rest`, (M - nf) x (N - nf) in the leaf dtype, which `next` factors in turn.  Then
+  // A = Q_1 diag(I, Q_next) [R_11 R_12; 0 R_next] with rows in that gathered order, and
+  // R is assembled in rfull (kr x N doubles, ld N).
+  int64_t nf = 0;                               // 0: an ordinary tree
+  std::shared_ptr<Tree> next;
+  void* rest = nullptr;
+  double* rfull = nullptr;
+  int kr() const;                               // rows of the R factor
+  const void* root_R() const;                   // R (row-major, ld = N; entries left of the diagonal not read)
+  int root_f32() const { return !next && lvl.size() == 1 && leaf_dtype == TT_F32 ? 1 : 0; }   // dtype of root_R
   int depth() const { return (int)lvl.size(); }
+  int64_t fk() const { return next ? nf : N; }  // columns the tiles factor
 };
 
 // Plan (and carve from `alloc`) a TSQR tree for an M x N matrix whose element

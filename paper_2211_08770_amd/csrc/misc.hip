@@ -90,6 +90,22 @@ __global__ __launch_bounds__(NT) void k_copy_segs(const CopySeg* __restrict__ se
   }
 }
 
+// One row of a block per workgroup step, the threads along the row (coalesced
+// on both sides).
+__global__ __launch_bounds__(NT) void k_block_copy(const BlockCopy* __restrict__ tasks) {
+  const BlockCopy tk = tasks[blockIdx.y];
+  for (int r = blockIdx.x; r < tk.rows; r += gridDim.x) {
+    const int64_t so = (int64_t)r * tk.src_ld, dof = (int64_t)r * tk.dst_ld;
+    for (int c = threadIdx.x; c < tk.cols; c += NT) {
+      double v = 0.0;
+      if (tk.src && !(tk.tri && c < r))
+        v = tk.src_f32 ? (double)((const float*)tk.src)[so + c] : ((const double*)tk.src)[so + c];
+      if (tk.dst_f32) ((float*)tk.dst)[dof + c] = (float)v;
+      else ((double*)tk.dst)[dof + c] = v;
+    }
+  }
+}
+
 __global__ void k_segsum(const double* __restrict__ slots, const int32_t* __restrict__ seg,
                          const int32_t* __restrict__ idx, int nout, double* __restrict__ out) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
@@ -598,6 +614,18 @@ hipError_t launch_copy_segs(int dtype, const CopySeg* d_segs, int nsegs, hipStre
     dim3 grid(16, cnt);
     if (dtype == 0) hipLaunchKernelGGL(k_copy_segs<double>, grid, dim3(NT), 0, s, d_segs + first);
     else hipLaunchKernelGGL(k_copy_segs<float>, grid, dim3(NT), 0, s, d_segs + first);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_block_copy(const BlockCopy* d_tasks, int ntasks, int64_t max_rows, hipStream_t s) {
+  if (ntasks <= 0 || max_rows <= 0) return hipSuccess;
+  const int gx = (int)(max_rows < 512 ? max_rows : 512);
+  for (int first = 0; first < ntasks; first += 65535) {
+    const int cnt = (ntasks - first) < 65535 ? (ntasks - first) : 65535;
+    hipLaunchKernelGGL(k_block_copy, dim3(gx, cnt), dim3(NT), 0, s, d_tasks + first);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

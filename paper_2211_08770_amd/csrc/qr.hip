@@ -499,6 +499,7 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   __shared__ double prm[8];
   const QrTask tk = tasks[blockIdx.x];
   const int m = tk.m, N = tk.ncol, tid = threadIdx.x;
+  const int nf = (tk.nfact > 0 && tk.nfact < N) ? tk.nfact : N;   // factored columns
   const gptr<TT> A = glb((TT*)tk.tile);
 
   // ---- fill the tile (UF loads in flight per thread: clamped addresses, masked stores;
@@ -539,7 +540,7 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
     for (int ci = 0; ci < tk.nchild; ++ci) {
       const QrTask ch = children[tk.child0 + ci];
       const gptr<const TS> ct = glb((const TS*)ch.tile);
-      const int kc = ch.m < N ? ch.m : N;
+      const int kc = ch.m < nf ? ch.m : nf;
       const int total = kc * N;
       const int d_r = NT / N, d_c = NT - d_r * N;   // (row, column) step of NT elements
       int r = tid / N, c = tid - r * N;
@@ -561,14 +562,14 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
 #pragma unroll
         for (int k = 0; k < UF; ++k)
           if (base + k * NT < total)
-            A[(int64_t)(row0 + rr[k]) * N + cc[k]] = (cc[k] >= rr[k]) ? (TT)v[k] : (TT)0;
+            A[(int64_t)(row0 + rr[k]) * N + cc[k]] = (cc[k] >= rr[k] || cc[k] >= nf) ? (TT)v[k] : (TT)0;
       }
       row0 += kc;
     }
   }
   __syncthreads();
 
-  const int kmax = m < N ? m : N;
+  const int kmax = m < nf ? m : nf;
   TT* P = (TT*)smem;                                       // NB columns x ldv rows
   double* scr = (double*)(smem + panel_bytes((int)sizeof(TT), ldv));
   for (int p0 = 0, pi = 0; p0 < kmax; p0 += NB, ++pi) {
@@ -629,7 +630,8 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
   }
 }
 
-// out = Q [X; 0] for one factored tile; Q = Q_0 Q_1 ... (panels applied last to first).
+// out = Q [X; Z] for one factored tile (Z the rest rows, zero when absent);
+// Q = Q_0 Q_1 ... (panels applied last to first).
 // Workgroup (task, y) owns the 16 output columns [16y, 16y + 16): its slice of
 // W = [X; 0] stays in registers through every panel (row block b of 16 rows
 // belongs to wave b mod 16; lane l holds rows 4s + l/16 of the block, column
@@ -662,7 +664,10 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int row = (wave + NWV * b) * NB + 4 * s + (lane >> 4);
-      Wr[b][s] = (colok && row < tk.k_in) ? X[(int64_t)row * tk.x_ld + col] : 0.0;
+      double v = 0.0;
+      if (colok && row < tk.k_in) v = X[(int64_t)row * tk.x_ld + col];
+      else if (colok && row < m && tk.rest) v = tk.rest[(int64_t)(row - tk.k_in) * tk.rest_ld + col];
+      Wr[b][s] = v;
     }
   const int np = (tk.kq + NB - 1) / NB;
   for (int pi = np - 1; pi >= 0; --pi) {
@@ -779,7 +784,8 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
     for (int s = 0; s < 4; ++s) {
       const int row = (wave + NWV * b) * NB + 4 * s + (lane >> 4);
       if (colok && row < m) {
-        if (tk.to_out) glb((TO*)tk.out)[row * tk.out_rs + col * tk.out_cs] = (TO)Wr[b][s];
+        if (tk.to_out == 2) glb((double*)tk.out)[row * tk.out_rs + col * tk.out_cs] = Wr[b][s];
+        else if (tk.to_out) glb((TO*)tk.out)[row * tk.out_rs + col * tk.out_cs] = (TO)Wr[b][s];
         else glb(tk.work)[(int64_t)row * t + col] = Wr[b][s];
       }
     }

@@ -75,11 +75,12 @@ void* Carver::take(size_t bytes) {
 }
 
 int Tree::kr() const {
+  if (next) return (int)(nf + next->kr());
   const QrTask& r = lvl.back()[0];
   return (int)std::min<int64_t>(r.m, N);
 }
 
-const void* Tree::root_R() const { return lvl.back()[0].tile; }
+const void* Tree::root_R() const { return next ? (const void*)rfull : lvl.back()[0].tile; }
 
 bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs, int64_t cs,
                      TreeShape sh, std::string* why);
@@ -99,6 +100,10 @@ bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const
   t.leaf_dtype = dtype;
   t.lvl.clear();
   t.leaf_row0.clear();
+  t.nf = 0;
+  t.next.reset();
+  t.rest = nullptr;
+  t.rfull = nullptr;
   if (M < 1 || N < 1) {
     if (why) *why = "empty QR shape";
     return false;
@@ -110,26 +115,25 @@ bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const
   if (req.leaf_rows >= std::min<int64_t>(N, M) && req.leaf_rows <= QR_MAXROWS && req.fanin >= 2 &&
       (int64_t)req.fanin * std::min<int64_t>(req.leaf_rows, N) <= QR_MAXROWS)
     sh = req;
-  int64_t b;
+  int64_t b, g = sh.fanin, fk = N;   // leaf rows, fan-in, columns the tiles factor
   if (M <= QR_MAXROWS && sh.leaf_rows >= M) {
     b = M;
+  } else if (N > QR_MAXROWS / 2) {
+    // too wide for one tree: the first column block, its trailing rows factored by `next`
+    fk = QR_BLOCK_COLS;
+    b = 2 * fk;
+    g = 2;
   } else {
-    if (N > QR_MAXROWS / 2) {
-      if (why)
-        *why = "QR of a " + std::to_string(M) + " x " + std::to_string(N) +
-               " unfolding exceeds the supported tile shape (rows > " + std::to_string(QR_MAXROWS) +
-               " needs columns <= " + std::to_string(QR_MAXROWS / 2) + ")";
-      return false;
-    }
     b = sh.leaf_rows;
   }
+  const int32_t nfact = fk < N ? (int32_t)fk : 0;
   const int64_t nleaves = (M + b - 1) / b;
   std::vector<QrTask> leaves;
   leaves.reserve(nleaves);
   for (int64_t j = 0; j < nleaves; ++j) {
     const int64_t r0 = j * b;
     const int64_t m = std::min<int64_t>(b, M - r0);
-    const int64_t k = std::min<int64_t>(m, N);
+    const int64_t k = std::min<int64_t>(m, fk);
     QrTask q;
     std::memset(&q, 0, sizeof(q));
     q.src = src ? (const char*)src + (size_t)(r0 * rs) * elt : nullptr;
@@ -137,6 +141,7 @@ bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const
     q.src_cs = cs;
     q.m = (int32_t)m;
     q.ncol = (int32_t)N;
+    q.nfact = nfact;
     q.tile = cv.take((size_t)m * N * elt);
     q.tau = (double*)cv.take((size_t)k * 8);
     q.tmat = cv.take((size_t)npanels(k) * QR_NB * QR_NB * 8);
@@ -144,29 +149,29 @@ bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const
     t.leaf_row0.push_back(r0);
   }
   t.lvl.push_back(std::move(leaves));
-  const int64_t g = sh.fanin;
   while (t.lvl.back().size() > 1) {
     const std::vector<QrTask>& prev = t.lvl.back();
     std::vector<QrTask> nodes;
     for (size_t i = 0; i < prev.size(); i += (size_t)g) {
       const int cnt = (int)std::min<size_t>((size_t)g, prev.size() - i);
       int64_t rows = 0;
-      for (int c = 0; c < cnt; ++c) rows += std::min<int64_t>(prev[i + c].m, N);
-      const int64_t k = std::min<int64_t>(rows, N);
+      for (int c = 0; c < cnt; ++c) rows += std::min<int64_t>(prev[i + c].m, fk);
+      const int64_t k = std::min<int64_t>(rows, fk);
       QrTask q;
       std::memset(&q, 0, sizeof(q));
       q.nchild = cnt;
       q.child0 = (int32_t)i;
       // every child but the last contributes the same number of R rows (the kernels rely on it)
-      q.kc0 = (int32_t)std::min<int64_t>(prev[i].m, N);
-      q.kc_last = (int32_t)std::min<int64_t>(prev[i + cnt - 1].m, N);
+      q.kc0 = (int32_t)std::min<int64_t>(prev[i].m, fk);
+      q.kc_last = (int32_t)std::min<int64_t>(prev[i + cnt - 1].m, fk);
       for (int c = 0; c + 1 < cnt; ++c)
-        if (std::min<int64_t>(prev[i + c].m, N) != q.kc0) {
+        if (std::min<int64_t>(prev[i + c].m, fk) != q.kc0) {
           if (why) *why = "internal: uneven TSQR children";
           return false;
         }
       q.m = (int32_t)rows;
       q.ncol = (int32_t)N;
+      q.nfact = nfact;
       q.tile = cv.take((size_t)rows * N * 8);
       q.tau = (double*)cv.take((size_t)k * 8);
       q.tmat = cv.take((size_t)npanels(k) * QR_NB * QR_NB * 8);
@@ -174,7 +179,30 @@ bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const
     }
     t.lvl.push_back(std::move(nodes));
   }
+  if (nfact) {
+    // the trailing block: rows left behind by the tiles, in level order, factored by an
+    // ordinary (or again blocked) tree of the default shape
+    t.nf = fk;
+    t.rest = cv.take((size_t)(M - fk) * (N - fk) * elt);
+    t.next = std::make_shared<Tree>();
+    if (!plan_tree_shape(cv, *t.next, M - fk, N - fk, dtype, t.rest, N - fk, 1, default_shape(M - fk, N - fk), why))
+      return false;
+    t.rfull = (double*)cv.take((size_t)t.kr() * N * 8);
+  }
   return true;
+}
+
+// First row of each tile's left-behind rows (rows min(m, nf)..m-1) in the trailing
+// block of a column-blocked tree: tiles in level order, leaves first.
+static std::vector<std::vector<int64_t>> rest_offsets(const Tree& t) {
+  std::vector<std::vector<int64_t>> off(t.lvl.size());
+  int64_t o = 0;
+  for (size_t l = 0; l < t.lvl.size(); ++l)
+    for (const QrTask& q : t.lvl[l]) {
+      off[l].push_back(o);
+      o += q.m - std::min<int64_t>(q.m, t.nf);
+    }
+  return off;
 }
 
 namespace {
@@ -194,7 +222,7 @@ int64_t active_rows(int64_t m, int nchild, int64_t kc0, int64_t kc_last, int64_t
 
 // algorithmic flops of a Householder QR of one tile: sum_j (4 a_j (N-j-1) + 3 a_j)
 double qr_flops(const QrTask& q) {
-  const int64_t kq = std::min<int64_t>(q.m, q.ncol);
+  const int64_t kq = std::min<int64_t>(q.m, q.nfact > 0 ? q.nfact : q.ncol);
   double f = 0.0;
   for (int64_t j = 0; j < kq; ++j) {
     const double a = (double)active_rows(q.m, q.nchild, q.kc0, q.kc_last, j);
@@ -220,17 +248,31 @@ size_t apply_work_bytes(const Tree& t, int64_t tcols) {
   size_t s = 0;
   for (const auto& l : t.lvl)
     for (const auto& q : l) s += (((size_t)q.m * tcols * 8) + 255) & ~(size_t)255;
+  if (t.next) s += ((((size_t)(t.M - t.nf) * tcols * 8) + 255) & ~(size_t)255) + apply_work_bytes(*t.next, tcols);
   return s;
 }
 
+// Column-blocked tree: Q [X_1; X_2; 0] = Q_1 [X_1; Q_next [X_2; 0]], so the plan of
+// `next` (its result Y, in the gathered row order, as double) comes first and every
+// tile of the first block then takes its left-behind rows from Y.
 void plan_apply(Carver& cv, const Tree& t, const double* X, int64_t x_ld, int64_t tcols, void* out,
                 int out_dtype, int64_t out_rs, int64_t out_cs, std::vector<ApplyLevel>& plan) {
   const int L = (int)t.lvl.size();
-  const int64_t N = t.N;
+  const int64_t N = t.fk();
+  plan.clear();
+  double* Y = nullptr;
+  std::vector<std::vector<int64_t>> roff;
+  if (t.next) {
+    Y = (double*)cv.take((size_t)(t.M - t.nf) * tcols * 8);
+    plan_apply(cv, *t.next, X ? X + t.nf * x_ld : nullptr, x_ld, tcols, Y, TT_F64, tcols, 1, plan);
+    for (auto& lv : plan)
+      for (auto& a : lv.tasks)
+        if (a.to_out) a.to_out = 2;   // Y is double whatever the final output's dtype
+    roff = rest_offsets(t);
+  }
   std::vector<std::vector<double*>> work(L);
   for (int l = 0; l < L; ++l)
     for (size_t i = 0; i < t.lvl[l].size(); ++i) work[l].push_back((double*)cv.take((size_t)t.lvl[l][i].m * tcols * 8));
-  plan.clear();
   // parent of each task and its row offset inside the parent
   std::vector<std::vector<std::pair<int, int64_t>>> parent(L);
   for (int l = 0; l + 1 < L; ++l) {
@@ -262,6 +304,10 @@ void plan_apply(Carver& cv, const Tree& t, const double* X, int64_t x_ld, int64_
       a.kc_last = q.kc_last;
       a.t = (int32_t)tcols;
       a.work = work[l][i];
+      if (Y && q.m > std::min<int64_t>(q.m, N)) {
+        a.rest = Y + roff[l][i] * tcols;
+        a.rest_ld = tcols;
+      }
       if (l == L - 1) {
         a.x = X;
         a.x_ld = x_ld;
@@ -396,8 +442,11 @@ bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why, bool bound_pl
     apmax = std::max(apmax, tree_apply_bytes(M, N, jb.dtype, st.tb[k + 1]));
     smax = std::max(smax, N);
     tmax = std::max(tmax, st.tb[k + 1]);
-    if (N > 1024) {
-      if (why) *why = "SVD of a " + std::to_string(N) + "-column R factor exceeds 1024";
+    // the SVD takes R factors of at most SVD_MAXROWS rows: planned at the rank bounds
+    // every step must stay within it; planned at the chosen ranks, each step is checked
+    // when its rank is known
+    if (bound_plan && std::min(M, N) > SVD_MAXROWS) {
+      if (why) *why = "SVD of a " + std::to_string(std::min(M, N)) + "-row R factor exceeds " + std::to_string(SVD_MAXROWS);
       return false;
     }
   }
@@ -446,7 +495,7 @@ bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why, bool bound_pl
   return true;
 }
 
-tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
+tt_status launch_levels_plain(tt_ctx* c, std::vector<Tree*>& trees) {
   // level by level from the leaves, all trees together (grouped by dtype)
   int maxL = 0;
   for (Tree* t : trees) maxL = std::max(maxL, t->depth());
@@ -487,6 +536,92 @@ tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
     }
   }
   return TT_OK;
+}
+
+tt_status launch_copies(tt_ctx* c, const std::vector<BlockCopy>& cp) {
+  if (cp.empty()) return TT_OK;
+  const BlockCopy* d = upload(c, cp);
+  if (!d) return fail(c, TT_ENOMEM, "task upload");
+  int64_t rows = 1;
+  for (const BlockCopy& b : cp) rows = std::max<int64_t>(rows, b.rows);
+  const int pr = prof_begin(c, PK_OTHER, 0.0, 0.0);
+  const hipError_t e = launch_block_copy(d, (int)cp.size(), rows, c->stream);
+  prof_end(c, pr);
+  return e == hipSuccess ? TT_OK : hip_fail(c, e, "block copy");
+}
+
+// Factorisation of trees, column-blocked ones included: the tiles of every tree level
+// by level; for blocked trees the left-behind rows gathered, the trailing blocks factored
+// the same way, and R assembled from the first block's top rows and the trailing R.
+tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
+  tt_status st = launch_levels_plain(c, trees);
+  if (st != TT_OK) return st;
+  std::vector<Tree*> blocked, nexts;
+  for (Tree* t : trees)
+    if (t->next) {
+      blocked.push_back(t);
+      nexts.push_back(t->next.get());
+    }
+  if (blocked.empty()) return TT_OK;
+  std::vector<BlockCopy> cp;
+  for (Tree* t : blocked) {
+    const std::vector<std::vector<int64_t>> off = rest_offsets(*t);
+    const int64_t nf = t->nf, wc = t->N - nf;
+    for (size_t l = 0; l < t->lvl.size(); ++l) {
+      const int tdt = l == 0 ? t->leaf_dtype : TT_F64;
+      for (size_t i = 0; i < t->lvl[l].size(); ++i) {
+        const QrTask& q = t->lvl[l][i];
+        const int64_t k = std::min<int64_t>(q.m, nf);
+        if (q.m <= k) continue;
+        BlockCopy b;
+        std::memset(&b, 0, sizeof(b));
+        b.src = (const char*)q.tile + (size_t)(k * t->N + nf) * elt_size(tdt);
+        b.src_ld = t->N;
+        b.dst = (char*)t->rest + (size_t)(off[l][i] * wc) * elt_size(t->leaf_dtype);
+        b.dst_ld = wc;
+        b.rows = (int32_t)(q.m - k);
+        b.cols = (int32_t)wc;
+        b.src_f32 = tdt == TT_F32;
+        b.dst_f32 = t->leaf_dtype == TT_F32;
+        cp.push_back(b);
+      }
+    }
+  }
+  if ((st = launch_copies(c, cp)) != TT_OK) return st;
+  if ((st = launch_levels_factor(c, nexts)) != TT_OK) return st;
+  cp.clear();
+  for (Tree* t : blocked) {
+    const QrTask& root = t->lvl.back()[0];
+    const int64_t nf = t->nf, N = t->N, k2 = t->next->kr();
+    BlockCopy b;
+    std::memset(&b, 0, sizeof(b));
+    b.src = root.tile;   // rows 0..nf-1: [R_11 R_12]
+    b.src_ld = N;
+    b.src_f32 = t->lvl.size() == 1 && t->leaf_dtype == TT_F32;
+    b.dst = t->rfull;
+    b.dst_ld = N;
+    b.rows = (int32_t)nf;
+    b.cols = (int32_t)N;
+    b.tri = 1;
+    cp.push_back(b);
+    std::memset(&b, 0, sizeof(b));   // rows nf..kr-1, columns 0..nf-1: zero
+    b.dst = t->rfull + nf * N;
+    b.dst_ld = N;
+    b.rows = (int32_t)k2;
+    b.cols = (int32_t)nf;
+    cp.push_back(b);
+    std::memset(&b, 0, sizeof(b));   // rows nf..kr-1, columns nf..N-1: R of the trailing block
+    b.src = t->next->root_R();
+    b.src_ld = t->next->N;
+    b.src_f32 = t->next->root_f32();
+    b.dst = t->rfull + nf * N + nf;
+    b.dst_ld = N;
+    b.rows = (int32_t)k2;
+    b.cols = (int32_t)(N - nf);
+    b.tri = 1;
+    cp.push_back(b);
+  }
+  return launch_copies(c, cp);
 }
 
 tt_status launch_apply_plans(tt_ctx* c, std::vector<std::vector<ApplyLevel>>& plans, int out_dtype,
@@ -1057,6 +1192,9 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       cv.cap = js.lr_cap;
       std::string why;
       const int64_t M = js.t[k] * jb.n[k], N = js.s[k + 1];
+      if (std::min(M, N) > SVD_MAXROWS)
+        return fail(c, TT_ENOTIMPL, "SVD of a " + std::to_string(std::min(M, N)) + "-row R factor exceeds " +
+                                        std::to_string(SVD_MAXROWS));
       if (c->autotune && !tuned_shape(M, N, jb.dtype, nullptr)) {
         tt_status ts = tune_tree(c, M, N, jb.dtype, nullptr);
         if (ts != TT_OK) return ts;

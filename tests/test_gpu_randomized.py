@@ -56,8 +56,8 @@ def test_randomized_exact_recovery_and_orders():
 
 def test_randomized_rounds_a_sum_beyond_the_tile_limits():
     # 50 components of rank 10 on order 4, n = 32: the unfolding of the deterministic
-    # right-to-left sweep is 1024 x 500 (more than 800 rows and 400 columns), which tt_round
-    # rejects; the sketch only ever factors (32 p) x 24 matrices.
+    # right-to-left sweep is 1024 x 500 (more than 800 rows and 400 columns: tt_round
+    # factors it in column blocks); the sketch only ever factors (32 p) x 24 matrices.
     tt = need_gpu()
     g = synth.rng(98)
     ns = [32, 32, 32, 32]
@@ -66,9 +66,6 @@ def test_randomized_rounds_a_sum_beyond_the_tile_limits():
     terms = [(a, [x[0], x[1] + 1e-9 * g.standard_normal(x[1].shape), x[2], x[3]]) for a, x in terms]
     sk = synth.random_tt(g, ns, [1, 24, 24, 24, 1])
     xs = dev_sum(terms)
-    with pytest.raises(tt.TTError) as ei:
-        tt.round(xs, 1e-6)
-    assert ei.value.status == "TT_ENOTIMPL"
     ref = oracle.tt_round_rto(terms, sk, 1e-6)
     out = tt.round_randomized(xs, dev_tt(sk), 1e-6)
     assert out.r == oracle.tt_ranks(ref)

@@ -179,3 +179,29 @@ def test_round_at_the_tile_limits():
     terms = rand_terms(321, [32, 32, 32, 32], [[1, 10, 10, 10, 1]] * 40,
                        scales=[2.0 ** -(j % 7) for j in range(40)])
     check_round(terms, 1e-6, torch.float64)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_round_column_blocked_unfoldings(dtype):
+    # 50 components of rank 10 on order 4, n = 32: the right-to-left unfoldings are
+    # 1024 x 500 and 16000 x 500 and the second left-to-right one 1024 x 500, all more
+    # than 800 rows and 400 columns: QR in column blocks (384 columns, then 116)
+    terms = rand_terms(322, [32, 32, 32, 32], [[1, 10, 10, 10, 1]] * 50,
+                       scales=[2.0 ** -(j % 7) for j in range(50)])
+    out = check_round(terms, 1e-6, dtype)
+    assert out.r[1] == 32 and out.r[2] > 300   # the left-to-right step 1 factors 1024 x 500
+
+
+def test_round_column_blocked_three_blocks():
+    # 64 components of rank 16 on order 4, n = 64, near two base TTs (so the result has low
+    # rank): the right-to-left unfoldings are 4096 x 1024 and 65536 x 1024, blocked three
+    # times (384 + 384 + 256 columns)
+    g = synth.rng(323)
+    ns = [64, 64, 64, 64]
+    base = [synth.random_tt(g, ns, [1, 16, 16, 16, 1]) for _ in range(2)]
+    terms = []
+    for j in range(64):
+        x = [c.copy() for c in base[j % 2]]
+        x[1] = x[1] + 1e-3 * g.standard_normal(x[1].shape)
+        terms.append((float(g.standard_normal()), x))
+    check_round(terms, 1e-6, torch.float64)
