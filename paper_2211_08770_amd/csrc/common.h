@@ -166,6 +166,10 @@ hipError_t launch_qr_factor(int dtype_src, int dtype_tile, const QrTask* d_tasks
                             int ntasks, int max_rows, hipStream_t s);
 hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tasks, int ntasks, int max_rows,
                            int max_t, hipStream_t s);
+// Trailing update of column blocks: tile columns out[r * out_rs + c * out_cs] (c < t,
+// r < m, tile dtype) replaced in place by Q^T times them (Q the tile's reflectors).
+hipError_t launch_qr_update(int dtype_tile, const ApplyTask* d_tasks, int ntasks, int max_rows, int max_t,
+                            hipStream_t s);
 hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s);
 hipError_t launch_gemm(int dtype, const GemmTask* d_tasks, const GemmPart* d_parts, int ntasks,
                        int max_m, int max_n, hipStream_t s);

@@ -624,8 +624,9 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
     __syncthreads();
     if (tid < NB * NB) glb((double*)tk.tmat)[(size_t)pi * NB * NB + tid] = Tm[tid];
     // ---- trailing update  A <- Q_p^T A  on the panel's rows
+    // (columns beyond nf, when carried, are updated afterwards by the UPD apply kernel)
     const int c0 = p0 + nb;
-    if (c0 < N) block_update<true, TT, TT>(A, N, rowl, c0, N, rows, P, ldv, Tm, scr);
+    if (c0 < nf) block_update<true, TT, TT>(A, N, rowl, c0, nf, rows, P, ldv, Tm, scr);
     __syncthreads();
   }
 }
@@ -639,7 +640,10 @@ __global__ __launch_bounds__(NT) void k_qr_factor(const QrTask* __restrict__ tas
 // panel is the panel's V, staged in LDS by tile row with zeros on the rows the
 // panel does not touch.  Per panel: W_p = V^T W (per-wave MFMA partials summed
 // in LDS in wave order), Y = T W_p, W -= V Y.
-template <typename TT, typename TO>
+// UPD: the trailing update of a column block instead, in place: the columns
+// out[r * out_rs + c * out_cs] (c < t, r < m, tile dtype) are replaced by
+// Q^T times them (panels first to last, Y = T^T W_p), one workgroup per 16 of them.
+template <typename TT, typename TO, bool UPD>
 __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ tasks, int ldv) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int bstart[MAXR + 1];
@@ -665,12 +669,18 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
     for (int s = 0; s < 4; ++s) {
       const int row = (wave + NWV * b) * NB + 4 * s + (lane >> 4);
       double v = 0.0;
-      if (colok && row < tk.k_in) v = X[(int64_t)row * tk.x_ld + col];
-      else if (colok && row < m && tk.rest) v = tk.rest[(int64_t)(row - tk.k_in) * tk.rest_ld + col];
+      if (UPD) {
+        if (colok && row < m) v = (double)glb((const TT*)tk.out)[(int64_t)row * tk.out_rs + (int64_t)col * tk.out_cs];
+      } else if (colok && row < tk.k_in) {
+        v = X[(int64_t)row * tk.x_ld + col];
+      } else if (colok && row < m && tk.rest) {
+        v = tk.rest[(int64_t)(row - tk.k_in) * tk.rest_ld + col];
+      }
       Wr[b][s] = v;
     }
   const int np = (tk.kq + NB - 1) / NB;
-  for (int pi = np - 1; pi >= 0; --pi) {
+  for (int it = 0; it < np; ++it) {
+    const int pi = UPD ? it : np - 1 - it;
     const int p0 = pi * NB;
     const int nb = (tk.kq - p0) < NB ? (tk.kq - p0) : NB;
     // node: first compacted row index of each child block's active rows
@@ -751,12 +761,12 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
     __syncthreads();
 #pragma unroll
     for (int v = 0; v < 4; ++v) w[v] = (TT)wsum[v * 64 + lane];
-    // Y = T W_p
+    // Y = T W_p (Q applied), Y = T^T W_p (Q^T applied)
     typename M::acc_t y = M::zero();
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int i = lane & 15, k = 4 * s + (lane >> 4);
-      y = M::mma((TT)Tm[i * NB + k], bop(w, s), y);
+      y = M::mma((TT)(UPD ? Tm[k * NB + i] : Tm[i * NB + k]), bop(w, s), y);
     }
     TT yb[4];
 #pragma unroll
@@ -784,7 +794,8 @@ __global__ __launch_bounds__(NT) void k_qr_apply(const ApplyTask* __restrict__ t
     for (int s = 0; s < 4; ++s) {
       const int row = (wave + NWV * b) * NB + 4 * s + (lane >> 4);
       if (colok && row < m) {
-        if (tk.to_out == 2) glb((double*)tk.out)[row * tk.out_rs + col * tk.out_cs] = Wr[b][s];
+        if (UPD) glb((TT*)tk.out)[(int64_t)row * tk.out_rs + (int64_t)col * tk.out_cs] = (TT)Wr[b][s];
+        else if (tk.to_out == 2) glb((double*)tk.out)[row * tk.out_rs + col * tk.out_cs] = Wr[b][s];
         else if (tk.to_out) glb((TO*)tk.out)[row * tk.out_rs + col * tk.out_cs] = (TO)Wr[b][s];
         else glb(tk.work)[(int64_t)row * t + col] = Wr[b][s];
       }
@@ -839,13 +850,26 @@ hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tas
   dim3 grid(ntasks, (max_t + NB - 1) / NB), block(NT);
   if (dtype_tile == 0) {
     const size_t sm = panel_smem(8, ldv);
-    if (dtype_out == 0) hipLaunchKernelGGL((k_qr_apply<double, double>), grid, block, sm, s, d_tasks, ldv);
-    else hipLaunchKernelGGL((k_qr_apply<double, float>), grid, block, sm, s, d_tasks, ldv);
+    if (dtype_out == 0) hipLaunchKernelGGL((k_qr_apply<double, double, false>), grid, block, sm, s, d_tasks, ldv);
+    else hipLaunchKernelGGL((k_qr_apply<double, float, false>), grid, block, sm, s, d_tasks, ldv);
   } else {
     const size_t sm = panel_smem(4, ldv);
-    if (dtype_out == 0) hipLaunchKernelGGL((k_qr_apply<float, double>), grid, block, sm, s, d_tasks, ldv);
-    else hipLaunchKernelGGL((k_qr_apply<float, float>), grid, block, sm, s, d_tasks, ldv);
+    if (dtype_out == 0) hipLaunchKernelGGL((k_qr_apply<float, double, false>), grid, block, sm, s, d_tasks, ldv);
+    else hipLaunchKernelGGL((k_qr_apply<float, float, false>), grid, block, sm, s, d_tasks, ldv);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_update(int dtype_tile, const ApplyTask* d_tasks, int ntasks, int max_rows, int max_t,
+                            hipStream_t s) {
+  if (ntasks <= 0 || max_t <= 0) return hipSuccess;
+  if (max_rows > MAXR) return hipErrorInvalidValue;
+  const int ldv = max_rows + 1;
+  dim3 grid(ntasks, (max_t + NB - 1) / NB), block(NT);
+  if (dtype_tile == 0)
+    hipLaunchKernelGGL((k_qr_apply<double, double, true>), grid, block, panel_smem(8, ldv), s, d_tasks, ldv);
+  else
+    hipLaunchKernelGGL((k_qr_apply<float, float, true>), grid, block, panel_smem(4, ldv), s, d_tasks, ldv);
   return hipGetLastError();
 }
 
@@ -864,10 +888,12 @@ hipError_t qr_kernels_init() {
   if ((e = raise_factor<double, double>(s8)) != hipSuccess) return e;
   if ((e = raise_factor<float, double>(s8)) != hipSuccess) return e;
   if ((e = raise_factor<float, float>(s4)) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_apply<double, double>, s8)) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_apply<double, float>, s8)) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_apply<float, double>, s4)) != hipSuccess) return e;
-  if ((e = raise_lds(k_qr_apply<float, float>, s4)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<double, double, false>, s8)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<double, float, false>, s8)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<float, double, false>, s4)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<float, float, false>, s4)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<double, double, true>, s8)) != hipSuccess) return e;
+  if ((e = raise_lds(k_qr_apply<float, float, true>, s4)) != hipSuccess) return e;
   return hipSuccess;
 }
 

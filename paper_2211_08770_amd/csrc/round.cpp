@@ -222,11 +222,12 @@ int64_t active_rows(int64_t m, int nchild, int64_t kc0, int64_t kc_last, int64_t
 
 // algorithmic flops of a Householder QR of one tile: sum_j (4 a_j (N-j-1) + 3 a_j)
 double qr_flops(const QrTask& q) {
-  const int64_t kq = std::min<int64_t>(q.m, q.nfact > 0 ? q.nfact : q.ncol);
+  const int64_t nf = q.nfact > 0 ? q.nfact : q.ncol;   // carried columns are counted with the update
+  const int64_t kq = std::min<int64_t>(q.m, nf);
   double f = 0.0;
   for (int64_t j = 0; j < kq; ++j) {
     const double a = (double)active_rows(q.m, q.nchild, q.kc0, q.kc_last, j);
-    f += 4.0 * a * (double)(q.ncol - j - 1) + 3.0 * a;
+    f += 4.0 * a * (double)(nf - j - 1) + 3.0 * a;
   }
   return f;
 }
@@ -244,10 +245,12 @@ struct ApplyLevel {
   std::vector<ApplyTask> tasks;
 };
 
+// Scratch of an apply plan: one m x tcols double block per tree node (a node's result is
+// its children's input); leaves write straight to the output.
 size_t apply_work_bytes(const Tree& t, int64_t tcols) {
   size_t s = 0;
-  for (const auto& l : t.lvl)
-    for (const auto& q : l) s += (((size_t)q.m * tcols * 8) + 255) & ~(size_t)255;
+  for (size_t l = 1; l < t.lvl.size(); ++l)
+    for (const auto& q : t.lvl[l]) s += (((size_t)q.m * tcols * 8) + 255) & ~(size_t)255;
   if (t.next) s += ((((size_t)(t.M - t.nf) * tcols * 8) + 255) & ~(size_t)255) + apply_work_bytes(*t.next, tcols);
   return s;
 }
@@ -272,7 +275,8 @@ void plan_apply(Carver& cv, const Tree& t, const double* X, int64_t x_ld, int64_
   }
   std::vector<std::vector<double*>> work(L);
   for (int l = 0; l < L; ++l)
-    for (size_t i = 0; i < t.lvl[l].size(); ++i) work[l].push_back((double*)cv.take((size_t)t.lvl[l][i].m * tcols * 8));
+    for (size_t i = 0; i < t.lvl[l].size(); ++i)
+      work[l].push_back(l == 0 ? nullptr : (double*)cv.take((size_t)t.lvl[l][i].m * tcols * 8));
   // parent of each task and its row offset inside the parent
   std::vector<std::vector<std::pair<int, int64_t>>> parent(L);
   for (int l = 0; l + 1 < L; ++l) {
@@ -533,6 +537,47 @@ tt_status launch_levels_plain(tt_ctx* c, std::vector<Tree*>& trees) {
         prof_end(c, pr);
         if (e != hipSuccess) return hip_fail(c, e, "qr_factor");
       }
+    }
+    // column blocks: the carried columns of this level's tiles updated by their reflectors,
+    // one workgroup per 16 columns of a tile, before the next level stacks them
+    for (int tdt = 0; tdt < 2; ++tdt) {
+      std::vector<ApplyTask> up;
+      int max_rows = 1, max_t = 0;
+      for (Tree* t : trees) {
+        if (l >= t->depth() || !t->next) continue;
+        const int tile_d = (l == 0) ? t->leaf_dtype : TT_F64;
+        if (tile_d != tdt) continue;
+        for (const QrTask& q : t->lvl[l]) {
+          ApplyTask a;
+          std::memset(&a, 0, sizeof(a));
+          a.tile = q.tile;
+          a.tau = q.tau;
+          a.tmat = q.tmat;
+          a.m = q.m;
+          a.ncol = q.ncol;
+          a.kq = (int32_t)std::min<int64_t>(q.m, q.nfact);
+          a.nchild = q.nchild;
+          a.kc0 = q.kc0;
+          a.kc_last = q.kc_last;
+          a.t = q.ncol - q.nfact;
+          a.out = (char*)q.tile + (size_t)q.nfact * elt_size(tile_d);
+          a.out_rs = q.ncol;
+          a.out_cs = 1;
+          up.push_back(a);
+          max_rows = std::max(max_rows, (int)q.m);
+          max_t = std::max(max_t, (int)a.t);
+        }
+      }
+      if (up.empty()) continue;
+      const ApplyTask* du = upload(c, up);
+      if (!du) return fail(c, TT_ENOMEM, "task upload");
+      double fl = 0.0;
+      if (c->prof)
+        for (const ApplyTask& a : up) fl += apply_flops(a);
+      const int pr = prof_begin(c, PK_QR_APPLY, fl, 0.0);
+      const hipError_t e = launch_qr_update(tdt, du, (int)up.size(), max_rows, max_t, c->stream);
+      prof_end(c, pr);
+      if (e != hipSuccess) return hip_fail(c, e, "qr_update");
     }
   }
   return TT_OK;
