@@ -57,7 +57,8 @@ struct ApplyTask {
 // ---------------------------------------------------------------------------
 // One-sided Jacobi SVD of a (kr x ncol) upper-trapezoidal R factor, FP64.
 // ---------------------------------------------------------------------------
-constexpr int SVD_MAXROWS = 1024;   // rows of the R factor (columns of the Jacobi problem)
+constexpr int SVD_SMALL_MAX = 1024;  // R factors of at most this many rows: one workgroup per SVD
+constexpr int SVD_BIG_MAX = 4096;    // above: block Jacobi over many workgroups, up to this many rows
 struct SvdTask {
   const void* R;          // row-major kr x ncol, ld = r_ld (root tile of a TSQR)
   int64_t r_ld;
@@ -78,6 +79,7 @@ struct SvdTask {
   double* ur;             // kr x t row-major:  left factor fed to Q application
   int32_t t_ld;           // > 0: wt and ur have t_ld columns (a bound of the rank), zero beyond t
   int32_t* info;          // device int: sweeps used (diagnostic)
+  int32_t* iscr;          // kr > SVD_SMALL_MAX: int scratch of kr + 64 entries
 };
 
 // ---------------------------------------------------------------------------
@@ -171,6 +173,8 @@ hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tas
 hipError_t launch_qr_update(int dtype_tile, const ApplyTask* d_tasks, int ntasks, int max_rows, int max_t,
                             hipStream_t s);
 hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s);
+// The tasks with kr > SVD_SMALL_MAX (the others are skipped): block Jacobi, several launches.
+hipError_t launch_svd_big(const SvdTask* d_tasks, int ntasks, int max_kr, hipStream_t s);
 hipError_t launch_gemm(int dtype, const GemmTask* d_tasks, const GemmPart* d_parts, int ntasks,
                        int max_m, int max_n, hipStream_t s);
 hipError_t launch_dot(int dtype, const DotTask* d_tasks, int ntasks, hipStream_t s);

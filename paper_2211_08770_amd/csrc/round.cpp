@@ -352,6 +352,7 @@ struct JobState {
   char* ap_side = nullptr;
   double *A = nullptr, *acc = nullptr, *sig = nullptr, *wt = nullptr;
   int32_t* perm = nullptr;
+  int32_t* iscr = nullptr;
   double* d_norm = nullptr;
   int64_t out_off = 0;
   bool alive = true;
@@ -446,11 +447,12 @@ bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why, bool bound_pl
     apmax = std::max(apmax, tree_apply_bytes(M, N, jb.dtype, st.tb[k + 1]));
     smax = std::max(smax, N);
     tmax = std::max(tmax, st.tb[k + 1]);
-    // the SVD takes R factors of at most SVD_MAXROWS rows: planned at the rank bounds
-    // every step must stay within it; planned at the chosen ranks, each step is checked
-    // when its rank is known
-    if (bound_plan && std::min(M, N) > SVD_MAXROWS) {
-      if (why) *why = "SVD of a " + std::to_string(std::min(M, N)) + "-row R factor exceeds " + std::to_string(SVD_MAXROWS);
+    // the SVD takes R factors of at most SVD_BIG_MAX rows (one workgroup up to
+    // SVD_SMALL_MAX); planned at the rank bounds every step stays within the one-workgroup
+    // kernel; planned at the chosen ranks, each step is checked when its rank is known
+    if (bound_plan && std::min(M, N) > SVD_SMALL_MAX) {
+      if (why)
+        *why = "SVD of a " + std::to_string(std::min(M, N)) + "-row R factor exceeds " + std::to_string(SVD_SMALL_MAX);
       return false;
     }
   }
@@ -466,6 +468,7 @@ bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why, bool bound_pl
   st.acc = (double*)ws.take((size_t)smax * smax * 8);
   st.sig = (double*)ws.take((size_t)smax * 8);
   st.perm = (int32_t*)ws.take((size_t)smax * 4);
+  st.iscr = (int32_t*)ws.take((size_t)(smax + 64) * 4);
   st.wt = (double*)ws.take((size_t)smax * tmax * 8);
   st.urb[0] = (double*)ws.take((size_t)smax * tmax * 8);
   st.urb[1] = (double*)ws.take((size_t)smax * tmax * 8);
@@ -1237,9 +1240,9 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       cv.cap = js.lr_cap;
       std::string why;
       const int64_t M = js.t[k] * jb.n[k], N = js.s[k + 1];
-      if (std::min(M, N) > SVD_MAXROWS)
+      if (std::min(M, N) > SVD_BIG_MAX)
         return fail(c, TT_ENOTIMPL, "SVD of a " + std::to_string(std::min(M, N)) + "-row R factor exceeds " +
-                                        std::to_string(SVD_MAXROWS));
+                                        std::to_string(SVD_BIG_MAX));
       if (c->autotune && !tuned_shape(M, N, jb.dtype, nullptr)) {
         tt_status ts = tune_tree(c, M, N, jb.dtype, nullptr);
         if (ts != TT_OK) return ts;
@@ -1269,6 +1272,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       t.acc = js.acc;
       t.sigma = js.sig;
       t.perm = js.perm;
+      t.iscr = js.iscr;
       t.norm = js.d_norm;
       t.delta_scaled = jb.delta / std::sqrt((double)(jb.d - 1));
       // FP32-bulk: singular values below the FP32 resolution of the merged core
@@ -1289,8 +1293,11 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       sfl += 4.0 * mx * mn * mn + 22.0 * mn * mn * mn;   // R-SVD operation count (Golub-Van Loan)
       sby += 8.0 * (double)t.kr * t.ncol;
     }
+    int max_kr = 0;
+    for (const SvdTask& t : sv) max_kr = std::max(max_kr, (int)t.kr);
     const int spr = prof_begin(c, PK_SVD, sfl, sby);
     e = launch_svd(dsv, (int)sv.size(), s);
+    if (e == hipSuccess && max_kr > SVD_SMALL_MAX) e = launch_svd_big(dsv, (int)sv.size(), max_kr, s);
     prof_end(c, spr);
     if (e != hipSuccess) return hip_fail(c, e, "svd");
     if (!bp && (e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=

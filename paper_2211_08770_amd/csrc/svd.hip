@@ -21,6 +21,7 @@
 // <= eps = delta/sqrt(d-1) * ||x|| (tail accumulated from the smallest
 // singular value), capped by max_rank.
 #include "common.h"
+#include "mfma.h"
 #include "wave.h"
 
 namespace tto {
@@ -29,7 +30,7 @@ namespace {
 
 constexpr int NT = 1024;
 constexpr int NW = NT / 64;
-constexpr int MAXC = 1024;
+constexpr int MAXC = SVD_SMALL_MAX;
 constexpr int LDS_DOUBLES = 18000;
 #ifndef JGL
 #define JGL 16
@@ -310,6 +311,7 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   __shared__ double edrop;
 
   const SvdTask tk = tasks[blockIdx.x];
+  if (tk.kr > SVD_SMALL_MAX) return;   // block Jacobi (launch_svd_big)
   const int kr = tk.kr, N = tk.ncol;
   const bool tall = (kr == N);
   const int nc = kr;
@@ -574,6 +576,323 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// R factors of more than SVD_SMALL_MAX rows: block one-sided Jacobi over many
+// workgroups.  The kr columns of A (= R or R^T as above, no deflation) are
+// split into blocks of BB; in each round of the circle schedule on the blocks
+// every disjoint pair of blocks is one workgroup, which forms the Gram matrix G
+// of its 2 BB columns on the FP64 matrix cores, diagonalises it by cyclic
+// (two-sided) Jacobi in LDS, V^T G V = diag, and rotates the columns (and J,
+// for a wide R) by V.  A pair whose columns are already orthogonal to
+// relative precision len u is left alone; a sweep in which no pair needed a
+// rotation with a cosine above sqrt(len u) ends the iteration (later rounds
+// see the per-sweep counter and return at once).  Singular values, order,
+// rank and the factors W^T, U_R then follow as in the one-workgroup kernel.
+// ---------------------------------------------------------------------------
+constexpr int BB = 32;              // columns per block
+constexpr int PW = 2 * BB;          // columns of a pair
+constexpr int GLD = PW + 1;         // padded leading dimension of G, V and the row chunk
+constexpr int BIG_SWEEPS = 24;
+constexpr size_t BIG_LDS = (size_t)3 * PW * GLD * 8;
+
+struct BigView {
+  const SvdTask* tk;
+  bool tall;
+  int kr, N, len, k;
+  __device__ double aval(int i, int j) const {
+    const int rr = tall ? i : j, cc = tall ? j : i;
+    if (tk->upper && cc < rr) return 0.0;
+    const int64_t e = (int64_t)rr * tk->r_ld + cc;
+    return tk->r_f32 ? (double)((const float*)tk->R)[e] : ((const double*)tk->R)[e];
+  }
+};
+
+__device__ inline BigView big_view(const SvdTask& tk) {
+  BigView v;
+  v.tk = &tk;
+  v.kr = tk.kr;
+  v.N = tk.ncol;
+  v.tall = (tk.kr == tk.ncol);
+  v.len = tk.ncol;   // A = R (N x N) or R^T (N x kr): columns of length N
+  v.k = tk.kr;
+  return v;
+}
+
+// A (len x k, column-major) from R, J = I (k x k) for a wide R, sweep counters zeroed.
+__global__ __launch_bounds__(NT) void k_bsvd_prep(const SvdTask* __restrict__ tasks) {
+  const SvdTask tk = tasks[blockIdx.x];
+  if (tk.kr <= SVD_SMALL_MAX) return;
+  const BigView g = big_view(tk);
+  for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)g.len * g.k;
+       idx += (int64_t)gridDim.y * NT) {
+    const int j = (int)(idx / g.len), i = (int)(idx - (int64_t)j * g.len);
+    tk.A[idx] = g.aval(i, j);
+  }
+  if (!g.tall)
+    for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)g.k * g.k;
+         idx += (int64_t)gridDim.y * NT) {
+      const int j = (int)(idx / g.k), i = (int)(idx - (int64_t)j * g.k);
+      tk.acc[idx] = (i == j) ? 1.0 : 0.0;
+    }
+  if (blockIdx.y == 0)
+    for (int i = threadIdx.x; i < BIG_SWEEPS; i += NT) tk.iscr[g.k + i] = 0;
+}
+
+// Column c (0 .. PW-1) of the pair (bp, bq): its index in A, or -1 past the last column.
+__device__ inline int pair_col(int c, int bp, int bq, int k) {
+  const int j = (c < BB) ? bp * BB + c : bq * BB + (c - BB);
+  return j < k ? j : -1;
+}
+
+// Rows [0, rows) of the pair's columns of X (column-major, ld) times V, in place,
+// 64 rows at a time through the LDS chunk.
+__device__ void rotate_rows(double* __restrict__ X, int64_t ld, int rows, const int* __restrict__ cidx,
+                            const double* __restrict__ V, double* __restrict__ Ch) {
+  typedef Mma<double> M;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rt = wave >> 2, ct = wave & 3;
+  for (int r0 = 0; r0 < rows; r0 += PW) {
+    __syncthreads();
+    for (int e = tid; e < PW * PW; e += NT) {
+      const int c = e / PW, r = e - c * PW;
+      const int j = cidx[c];
+      Ch[c * GLD + r] = (j >= 0 && r0 + r < rows) ? X[(int64_t)j * ld + r0 + r] : 0.0;
+    }
+    __syncthreads();
+    M::acc_t acc = M::zero();
+#pragma unroll 4
+    for (int k0 = 0; k0 < PW; k0 += 4) {
+      const double a = Ch[(k0 + (lane >> 4)) * GLD + rt * 16 + (lane & 15)];   // chunk[row][k]
+      const double b = V[(k0 + (lane >> 4)) * GLD + ct * 16 + (lane & 15)];    // V[k][col]
+      acc = M::mma(a, b, acc);
+    }
+    const int c = ct * 16 + (lane & 15), j = cidx[c];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = r0 + rt * 16 + M::row(lane, v);
+      if (j >= 0 && r < rows) X[(int64_t)j * ld + r] = acc[v];
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ tasks, int sweep, int round) {
+  typedef Mma<double> M;
+  extern __shared__ __align__(16) double blds[];
+  __shared__ int cidx[PW];
+  __shared__ int pq[PW / 2][2];
+  __shared__ double cs[PW / 2][2];
+  __shared__ int need, big, inner_rot;
+  const SvdTask tk = tasks[blockIdx.x];
+  if (tk.kr <= SVD_SMALL_MAX) return;
+  const BigView g = big_view(tk);
+  int* rot = tk.iscr + g.k;
+  if (sweep > 0 && rot[sweep - 1] == 0) return;   // converged
+  const int nb = (g.k + BB - 1) / BB, nbp = nb + (nb & 1);
+  const int pair = blockIdx.y;
+  if (pair >= nbp / 2 || round >= nbp - 1) return;
+  int bp, bq;
+  rr_pair(round, pair, nbp, bp, bq);
+  if (bq >= nb) return;   // paired with the empty block
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* G = blds;                  // PW x GLD
+  double* V = blds + PW * GLD;       // PW x GLD
+  double* Ch = blds + 2 * PW * GLD;  // PW x GLD
+  if (tid < PW) cidx[tid] = pair_col(tid, bp, bq, g.k);
+  if (tid == 0) {
+    need = 0;
+    big = 0;
+  }
+  __syncthreads();
+  // ---- G = A_pair^T A_pair: wave w owns the 16 x 16 tile (w / 4, w % 4)
+  {
+    const int ti = wave >> 2, tj = wave & 3;
+    const int ja = cidx[ti * 16 + (lane & 15)], jb = cidx[tj * 16 + (lane & 15)];
+    const double* Aa = tk.A + (int64_t)(ja >= 0 ? ja : 0) * g.len;
+    const double* Ab = tk.A + (int64_t)(jb >= 0 ? jb : 0) * g.len;
+    M::acc_t a0 = M::zero(), a1 = M::zero();
+    int r0 = 0;
+    for (; r0 + 8 <= g.len; r0 += 8) {
+      const int r = r0 + (lane >> 4);
+      const double x0 = ja >= 0 ? Aa[r] : 0.0, y0 = jb >= 0 ? Ab[r] : 0.0;
+      const double x1 = ja >= 0 ? Aa[r + 4] : 0.0, y1 = jb >= 0 ? Ab[r + 4] : 0.0;
+      a0 = M::mma(x0, y0, a0);
+      a1 = M::mma(x1, y1, a1);
+    }
+    for (; r0 < g.len; r0 += 4) {
+      const int r = r0 + (lane >> 4);
+      const bool ok = r < g.len;
+      const double x = (ok && ja >= 0) ? Aa[r] : 0.0, y = (ok && jb >= 0) ? Ab[r] : 0.0;
+      a0 = M::mma(x, y, a0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) G[(ti * 16 + M::row(lane, v)) * GLD + tj * 16 + (lane & 15)] = a0[v] + a1[v];
+  }
+  __syncthreads();
+  const double tol = (double)g.len * 1.1102230246251565e-16;
+  const double tol2 = tol * tol;
+  for (int e = tid; e < PW * PW; e += NT) {
+    const int i = e / PW, j = e - i * PW;
+    if (i < j) {
+      const double ga = G[i * GLD + j], al = G[i * GLD + i], be = G[j * GLD + j];
+      if (ga != 0.0 && ga * ga > tol2 * al * be) {
+        need = 1;
+        if (ga * ga > tol * al * be) big = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (!need) return;   // the whole workgroup: no barrier is reached
+  if (tid == 0 && big) atomicAdd(&rot[sweep], 1);
+  for (int e = tid; e < PW * PW; e += NT) {
+    const int i = e / PW, j = e - i * PW;
+    V[i * GLD + j] = (i == j) ? 1.0 : 0.0;
+  }
+  // ---- cyclic Jacobi on G: rounds of PW/2 disjoint pairs, G <- J^T G J, V <- V J
+  for (int isw = 0; isw < 30; ++isw) {
+    if (tid == 0) inner_rot = 0;
+    __syncthreads();
+    for (int rr = 0; rr < PW - 1; ++rr) {
+      if (tid < PW / 2) {
+        int p, q;
+        rr_pair(rr, tid, PW, p, q);
+        pq[tid][0] = p;
+        pq[tid][1] = q;
+        const double al = G[p * GLD + p], be = G[q * GLD + q], ga = G[p * GLD + q];
+        double c = 1.0, sn = 0.0;
+        if (ga != 0.0 && ga * ga > tol2 * al * be) {
+          rotation(al, be, ga, c, sn);
+          inner_rot = 1;
+        }
+        cs[tid][0] = c;
+        cs[tid][1] = sn;
+      }
+      __syncthreads();
+      for (int e = tid; e < (PW / 2) * PW; e += NT) {   // rows p, q of G
+        const int pi = e / PW, j = e - pi * PW;
+        const double c = cs[pi][0], sn = cs[pi][1];
+        if (sn != 0.0) {
+          const int p = pq[pi][0], q = pq[pi][1];
+          const double u = G[p * GLD + j], w = G[q * GLD + j];
+          G[p * GLD + j] = c * u - sn * w;
+          G[q * GLD + j] = sn * u + c * w;
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < (PW / 2) * PW; e += NT) {   // columns p, q of G and V
+        const int pi = e / PW, j = e - pi * PW;
+        const double c = cs[pi][0], sn = cs[pi][1];
+        if (sn != 0.0) {
+          const int p = pq[pi][0], q = pq[pi][1];
+          const double u = G[j * GLD + p], w = G[j * GLD + q];
+          G[j * GLD + p] = c * u - sn * w;
+          G[j * GLD + q] = sn * u + c * w;
+          const double vu = V[j * GLD + p], vw = V[j * GLD + q];
+          V[j * GLD + p] = c * vu - sn * vw;
+          V[j * GLD + q] = sn * vu + c * vw;
+        }
+      }
+      __syncthreads();
+    }
+    if (!inner_rot) break;
+  }
+  // ---- the pair's columns of A (and of J) rotated by V
+  rotate_rows(tk.A, g.len, g.len, cidx, V, Ch);
+  if (!g.tall) rotate_rows(tk.acc, g.k, g.k, cidx, V, Ch);
+}
+
+// Singular values (column norms), their order, the rank and the factors.
+__global__ __launch_bounds__(NT) void k_bsvd_finish(const SvdTask* __restrict__ tasks) {
+  __shared__ double nrm[SVD_BIG_MAX];
+  __shared__ int perm[SVD_BIG_MAX];
+  __shared__ int tsel;
+  const SvdTask tk = tasks[blockIdx.x];
+  if (tk.kr <= SVD_SMALL_MAX) return;
+  const BigView g = big_view(tk);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k = g.k, len = g.len, N = g.N, kr = g.kr;
+  const double* A = tk.A;
+  const double* J = tk.acc;
+  for (int j = wave; j < k; j += NW) {
+    const double* aj = A + (int64_t)j * len;
+    double s = 0.0;
+    for (int i = lane; i < len; i += 64) s += aj[i] * aj[i];
+    s = wave_sum(s);
+    if (lane == 0) nrm[j] = sqrt(s);
+  }
+  __syncthreads();
+  for (int j = tid; j < k; j += NT) {
+    const double sj = nrm[j];
+    int rk = 0;
+    for (int i = 0; i < k; ++i) {
+      const double si = nrm[i];
+      rk += (si > sj) || (si == sj && i < j);
+    }
+    perm[rk] = j;
+    tk.sigma[rk] = sj;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double eps = (tk.delta_scaled > tk.eps_floor ? tk.delta_scaled : tk.eps_floor) * (*tk.norm);
+    const double eps2 = eps * eps;
+    int t = k;
+    double tail = 0.0;
+    for (int i = k - 1; i >= 1; --i) {
+      tail += tk.sigma[i] * tk.sigma[i];
+      if (tail <= eps2) t = i;
+      else break;
+    }
+    if (tk.max_rank > 0 && t > tk.max_rank) t = (int)tk.max_rank;
+    if (t < 1) t = 1;
+    if (tk.sigma[0] == 0.0) t = 1;
+    tsel = t;
+    *tk.rank_out = t;
+    if (tk.info) {
+      int sw = 0;
+      while (sw < BIG_SWEEPS && tk.iscr[k + sw] != 0) ++sw;
+      *tk.info = sw + 1;
+    }
+  }
+  __syncthreads();
+  const int t = tsel;
+  const int ld = tk.t_ld > 0 ? tk.t_ld : t;
+  // W^T: ncol x t
+  for (int64_t idx = tid; idx < (int64_t)N * ld; idx += NT) {
+    const int col = (int)(idx / ld), i = (int)(idx - (int64_t)col * ld);
+    double v = 0.0;
+    if (i < t) {
+      const int j = perm[i];
+      if (g.tall) {
+        const double s = tk.sigma[i];
+        if (s > 0.0) {
+          const double* aj = A + (int64_t)j * len;
+          const int rmax = (tk.upper && col + 1 < len) ? col + 1 : len;
+          double acc = 0.0;
+          for (int row = 0; row < rmax; ++row) acc += aj[row] * g.aval(row, col);
+          v = acc / s;
+        }
+      } else {
+        v = A[(int64_t)j * len + col];
+      }
+    }
+    tk.wt[idx] = v;
+  }
+  // U_R: kr x t
+  for (int64_t idx = tid; idx < (int64_t)kr * ld; idx += NT) {
+    const int row = (int)(idx / ld), i = (int)(idx - (int64_t)row * ld);
+    double v = 0.0;
+    if (i < t) {
+      const int j = perm[i];
+      if (g.tall) {
+        const double s = tk.sigma[i];
+        v = (s > 0.0) ? A[(int64_t)j * len + row] / s : ((row == i) ? 1.0 : 0.0);
+      } else {
+        v = J[(int64_t)j * k + row];
+      }
+    }
+    tk.ur[idx] = v;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s) {
@@ -586,6 +905,29 @@ hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s) {
     ready = true;
   }
   hipLaunchKernelGGL(k_svd, dim3(ntasks), dim3(NT), LDS_DOUBLES * 8, s, d_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_big(const SvdTask* d_tasks, int ntasks, int max_kr, hipStream_t s) {
+  if (ntasks <= 0 || max_kr <= SVD_SMALL_MAX) return hipSuccess;
+  if (max_kr > SVD_BIG_MAX) return hipErrorInvalidValue;
+  static bool ready = false;
+  if (!ready) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_bsvd_round, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)BIG_LDS);
+    if (e != hipSuccess) return e;
+    ready = true;
+  }
+  hipLaunchKernelGGL(k_bsvd_prep, dim3(ntasks, 64), dim3(NT), 0, s, d_tasks);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nb = (max_kr + BB - 1) / BB, nbp = nb + (nb & 1);
+  for (int sw = 0; sw < BIG_SWEEPS; ++sw)
+    for (int r = 0; r < nbp - 1; ++r) {
+      hipLaunchKernelGGL(k_bsvd_round, dim3(ntasks, nbp / 2), dim3(NT), BIG_LDS, s, d_tasks, sw, r);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  hipLaunchKernelGGL(k_bsvd_finish, dim3(ntasks), dim3(NT), 0, s, d_tasks);
   return hipGetLastError();
 }
 

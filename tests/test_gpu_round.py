@@ -205,3 +205,20 @@ def test_round_column_blocked_three_blocks():
         x[1] = x[1] + 1e-3 * g.standard_normal(x[1].shape)
         terms.append((float(g.standard_normal()), x))
     check_round(terms, 1e-6, torch.float64)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_round_large_r_factor_block_jacobi(dtype):
+    # 80 components of rank 16 on order 4, n = 64, near two base TTs: the left-to-right
+    # step 1 factors a 2048 x 1280 matrix, and its 1280 x 1280 R factor (more than 1024
+    # rows) takes the block Jacobi SVD over many workgroups
+    g = synth.rng(324)
+    ns = [64, 64, 64, 64]
+    base = [synth.random_tt(g, ns, [1, 16, 16, 16, 1]) for _ in range(2)]
+    terms = []
+    for j in range(80):
+        x = [c.copy() for c in base[j % 2]]
+        x[1] = x[1] + 1e-3 * g.standard_normal(x[1].shape)
+        terms.append((float(g.standard_normal()), x))
+    out = check_round(terms, 1e-6, dtype)
+    assert out.r[1] == 32
