@@ -202,6 +202,14 @@ tt_status tt_round_batched_async(tt_ctx* ctx, int32_t njobs, const tt_sum* xs, c
 tt_status tt_ctx_set_graphs(tt_ctx* ctx, int on);
 int32_t tt_ctx_graph_count(const tt_ctx* ctx);
 
+/* Truncated SVD of the left-to-right sweep of TT-round (Section 2): the R factor of each
+ * step is diagonalised by one-sided Jacobi, in one workgroup when it has at most `rows`
+ * rows and by block Jacobi over many workgroups above (column blocks of 32, one
+ * workgroup per pair of blocks in each round).  Both give the singular values to working
+ * precision; the crossover is a speed setting.  rows in [32, 1024] (default 224); R
+ * factors of more than 4096 rows are not supported (TT_ENOTIMPL).  TT_EINVAL outside. */
+tt_status tt_ctx_set_svd_block_min(tt_ctx* ctx, int32_t rows);
+
 /* Upper bound on the packed size (elements) of TT-round(x): ranks are capped
  * by min(sum of component ranks, prod n_{<=k}, prod n_{>k}). */
 int64_t tt_round_out_capacity(const tt_sum* x);

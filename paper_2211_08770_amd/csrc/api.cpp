@@ -852,6 +852,13 @@ tt_status tt_round_batched_async(tt_ctx* c, int32_t njobs, const tt_sum* xs, con
   return TT_OK;
 }
 
+tt_status tt_ctx_set_svd_block_min(tt_ctx* c, int32_t rows) {
+  if (!c) return TT_EINVAL;
+  if (rows < 32 || rows > SVD_SMALL_MAX) return fail(c, TT_EINVAL, "svd block crossover must be in [32, 1024]");
+  c->svd_block_min = rows;
+  return TT_OK;
+}
+
 tt_status tt_ctx_set_graphs(tt_ctx* c, int on) {
   if (!c) return TT_EINVAL;
   (void)hipSetDevice(c->device);

@@ -59,6 +59,8 @@ struct ApplyTask {
 // ---------------------------------------------------------------------------
 constexpr int SVD_SMALL_MAX = 1024;  // R factors of at most this many rows: one workgroup per SVD
 constexpr int SVD_BIG_MAX = 4096;    // above: block Jacobi over many workgroups, up to this many rows
+constexpr int SVD_BLOCK_MIN = 224;   // default crossover: block Jacobi above this many rows (measured: the
+                                     // one-workgroup kernel is faster at 128 rows, half as fast at 256)
 struct SvdTask {
   const void* R;          // row-major kr x ncol, ld = r_ld (root tile of a TSQR)
   int64_t r_ld;
@@ -79,7 +81,8 @@ struct SvdTask {
   double* ur;             // kr x t row-major:  left factor fed to Q application
   int32_t t_ld;           // > 0: wt and ur have t_ld columns (a bound of the rank), zero beyond t
   int32_t* info;          // device int: sweeps used (diagnostic)
-  int32_t* iscr;          // kr > SVD_SMALL_MAX: int scratch of kr + 64 entries
+  int32_t block;          // 1: block Jacobi over many workgroups (launch_svd_big), 0: one workgroup (launch_svd)
+  int32_t* iscr;          // block: int scratch of kr + 64 entries
 };
 
 // ---------------------------------------------------------------------------
@@ -173,7 +176,8 @@ hipError_t launch_qr_apply(int dtype_tile, int dtype_out, const ApplyTask* d_tas
 hipError_t launch_qr_update(int dtype_tile, const ApplyTask* d_tasks, int ntasks, int max_rows, int max_t,
                             hipStream_t s);
 hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s);
-// The tasks with kr > SVD_SMALL_MAX (the others are skipped): block Jacobi, several launches.
+// The tasks with the block flag (the others are skipped): block Jacobi, several launches;
+// max_kr bounds kr over the flagged tasks.
 hipError_t launch_svd_big(const SvdTask* d_tasks, int ntasks, int max_kr, hipStream_t s);
 hipError_t launch_gemm(int dtype, const GemmTask* d_tasks, const GemmPart* d_parts, int ntasks,
                        int max_m, int max_n, hipStream_t s);

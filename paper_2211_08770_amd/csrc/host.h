@@ -89,6 +89,7 @@ struct tt_ctx {
   tto::ReplayArena* graph_arena = nullptr;   // set while a call builds or captures an entry
   bool graph_capturing = false;              // uploads find their data in place: no copies
   uint64_t tune_count = 0;                   // tree-shape tunings run (they allocate and launch too)
+  int svd_block_min = tto::SVD_BLOCK_MIN;    // R factors of more rows take the block Jacobi SVD
   std::vector<tto::ProfRec> prof_open;
   std::vector<hipEvent_t> prof_pool;
   double prof_ms[tto::PK_COUNT] = {0};

@@ -1273,6 +1273,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       t.sigma = js.sig;
       t.perm = js.perm;
       t.iscr = js.iscr;
+      t.block = (t.kr > std::min<int>(c->svd_block_min, SVD_SMALL_MAX)) ? 1 : 0;
       t.norm = js.d_norm;
       t.delta_scaled = jb.delta / std::sqrt((double)(jb.d - 1));
       // FP32-bulk: singular values below the FP32 resolution of the merged core
@@ -1294,10 +1295,11 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       sby += 8.0 * (double)t.kr * t.ncol;
     }
     int max_kr = 0;
-    for (const SvdTask& t : sv) max_kr = std::max(max_kr, (int)t.kr);
+    for (const SvdTask& t : sv)
+      if (t.block) max_kr = std::max(max_kr, (int)t.kr);
     const int spr = prof_begin(c, PK_SVD, sfl, sby);
     e = launch_svd(dsv, (int)sv.size(), s);
-    if (e == hipSuccess && max_kr > SVD_SMALL_MAX) e = launch_svd_big(dsv, (int)sv.size(), max_kr, s);
+    if (e == hipSuccess && max_kr > 0) e = launch_svd_big(dsv, (int)sv.size(), max_kr, s);
     prof_end(c, spr);
     if (e != hipSuccess) return hip_fail(c, e, "svd");
     if (!bp && (e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=

@@ -311,7 +311,7 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
   __shared__ double edrop;
 
   const SvdTask tk = tasks[blockIdx.x];
-  if (tk.kr > SVD_SMALL_MAX) return;   // block Jacobi (launch_svd_big)
+  if (tk.block) return;   // block Jacobi (launch_svd_big)
   const int kr = tk.kr, N = tk.ncol;
   const bool tall = (kr == N);
   const int nc = kr;
@@ -577,7 +577,8 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
 }
 
 // ---------------------------------------------------------------------------
-// R factors of more than SVD_SMALL_MAX rows: block one-sided Jacobi over many
+// R factors with the block flag (more than SVD_SMALL_MAX rows, or above a
+// context's crossover): block one-sided Jacobi over many
 // workgroups.  The kr columns of A (= R or R^T as above, no deflation) are
 // split into blocks of BB; in each round of the circle schedule on the blocks
 // every disjoint pair of blocks is one workgroup, which forms the Gram matrix G
@@ -585,14 +586,21 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
 // (two-sided) Jacobi in LDS, V^T G V = diag, and rotates the columns (and J,
 // for a wide R) by V.  A pair whose columns are already orthogonal to
 // relative precision len u is left alone; a sweep in which no pair needed a
-// rotation with a cosine above sqrt(len u) ends the iteration (later rounds
-// see the per-sweep counter and return at once).  Singular values, order,
+// rotation ends the iteration (later rounds see the per-sweep counter and
+// return at once).  Singular values, order,
 // rank and the factors W^T, U_R then follow as in the one-workgroup kernel.
 // ---------------------------------------------------------------------------
 constexpr int BB = 32;              // columns per block
 constexpr int PW = 2 * BB;          // columns of a pair
 constexpr int GLD = PW + 1;         // padded leading dimension of G, V and the row chunk
-constexpr int BIG_SWEEPS = 24;
+#ifndef BSVD_SWEEPS
+#define BSVD_SWEEPS 64
+#endif
+#ifndef BSVD_INNER
+#define BSVD_INNER 2
+#endif
+constexpr int BIG_SWEEPS = BSVD_SWEEPS;     // outer sweeps at most
+constexpr int INNER_SWEEPS = BSVD_INNER;    // inner sweeps per pair at most
 constexpr size_t BIG_LDS = (size_t)3 * PW * GLD * 8;
 
 struct BigView {
@@ -621,7 +629,7 @@ __device__ inline BigView big_view(const SvdTask& tk) {
 // A (len x k, column-major) from R, J = I (k x k) for a wide R, sweep counters zeroed.
 __global__ __launch_bounds__(NT) void k_bsvd_prep(const SvdTask* __restrict__ tasks) {
   const SvdTask tk = tasks[blockIdx.x];
-  if (tk.kr <= SVD_SMALL_MAX) return;
+  if (!tk.block) return;
   const BigView g = big_view(tk);
   for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)g.len * g.k;
        idx += (int64_t)gridDim.y * NT) {
@@ -681,9 +689,9 @@ __global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ t
   __shared__ int cidx[PW];
   __shared__ int pq[PW / 2][2];
   __shared__ double cs[PW / 2][2];
-  __shared__ int need, big, inner_rot;
+  __shared__ int need, inner_rot;
   const SvdTask tk = tasks[blockIdx.x];
-  if (tk.kr <= SVD_SMALL_MAX) return;
+  if (!tk.block) return;
   const BigView g = big_view(tk);
   int* rot = tk.iscr + g.k;
   if (sweep > 0 && rot[sweep - 1] == 0) return;   // converged
@@ -698,10 +706,7 @@ __global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ t
   double* V = blds + PW * GLD;       // PW x GLD
   double* Ch = blds + 2 * PW * GLD;  // PW x GLD
   if (tid < PW) cidx[tid] = pair_col(tid, bp, bq, g.k);
-  if (tid == 0) {
-    need = 0;
-    big = 0;
-  }
+  if (tid == 0) need = 0;
   __syncthreads();
   // ---- G = A_pair^T A_pair: wave w owns the 16 x 16 tile (w / 4, w % 4)
   {
@@ -734,21 +739,22 @@ __global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ t
     const int i = e / PW, j = e - i * PW;
     if (i < j) {
       const double ga = G[i * GLD + j], al = G[i * GLD + i], be = G[j * GLD + j];
-      if (ga != 0.0 && ga * ga > tol2 * al * be) {
-        need = 1;
-        if (ga * ga > tol * al * be) big = 1;
-      }
+      if (ga != 0.0 && ga * ga > tol2 * al * be) need = 1;
     }
   }
   __syncthreads();
   if (!need) return;   // the whole workgroup: no barrier is reached
-  if (tid == 0 && big) atomicAdd(&rot[sweep], 1);
+  // (with the inner sweeps capped, convergence is not quadratic: a sweep ends the
+  // iteration only when no pair needed any rotation)
+  if (tid == 0) atomicAdd(&rot[sweep], 1);
   for (int e = tid; e < PW * PW; e += NT) {
     const int i = e / PW, j = e - i * PW;
     V[i * GLD + j] = (i == j) ? 1.0 : 0.0;
   }
-  // ---- cyclic Jacobi on G: rounds of PW/2 disjoint pairs, G <- J^T G J, V <- V J
-  for (int isw = 0; isw < 30; ++isw) {
+  // ---- cyclic Jacobi on G: rounds of PW/2 disjoint pairs, G <- J^T G J, V <- V J.
+  // At most INNER_SWEEPS sweeps: the pair need not leave exactly orthogonal, since
+  // the outer sweeps go on until no pair needs a rotation.
+  for (int isw = 0; isw < INNER_SWEEPS; ++isw) {
     if (tid == 0) inner_rot = 0;
     __syncthreads();
     for (int rr = 0; rr < PW - 1; ++rr) {
@@ -800,23 +806,25 @@ __global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ t
   if (!g.tall) rotate_rows(tk.acc, g.k, g.k, cidx, V, Ch);
 }
 
-// Singular values (column norms), their order, the rank and the factors.
-__global__ __launch_bounds__(NT) void k_bsvd_finish(const SvdTask* __restrict__ tasks) {
+// Singular values (column norms), their order and the rank; the order goes to
+// iscr[0 .. k), the rank to iscr[k + BIG_SWEEPS].
+__global__ __launch_bounds__(NT) void k_bsvd_rank(const SvdTask* __restrict__ tasks) {
   __shared__ double nrm[SVD_BIG_MAX];
-  __shared__ int perm[SVD_BIG_MAX];
-  __shared__ int tsel;
   const SvdTask tk = tasks[blockIdx.x];
-  if (tk.kr <= SVD_SMALL_MAX) return;
+  if (!tk.block) return;
   const BigView g = big_view(tk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int k = g.k, len = g.len, N = g.N, kr = g.kr;
-  const double* A = tk.A;
-  const double* J = tk.acc;
+  const int k = g.k, len = g.len;
   for (int j = wave; j < k; j += NW) {
-    const double* aj = A + (int64_t)j * len;
-    double s = 0.0;
-    for (int i = lane; i < len; i += 64) s += aj[i] * aj[i];
-    s = wave_sum(s);
+    const double* aj = tk.A + (int64_t)j * len;
+    double s0 = 0.0, s1 = 0.0;
+    int i = lane;
+    for (; i + 64 < len; i += 128) {
+      s0 += aj[i] * aj[i];
+      s1 += aj[i + 64] * aj[i + 64];
+    }
+    if (i < len) s0 += aj[i] * aj[i];
+    const double s = wave_sum(s0 + s1);
     if (lane == 0) nrm[j] = sqrt(s);
   }
   __syncthreads();
@@ -827,7 +835,7 @@ __global__ __launch_bounds__(NT) void k_bsvd_finish(const SvdTask* __restrict__ 
       const double si = nrm[i];
       rk += (si > sj) || (si == sj && i < j);
     }
-    perm[rk] = j;
+    tk.iscr[rk] = j;
     tk.sigma[rk] = sj;
   }
   __syncthreads();
@@ -844,53 +852,94 @@ __global__ __launch_bounds__(NT) void k_bsvd_finish(const SvdTask* __restrict__ 
     if (tk.max_rank > 0 && t > tk.max_rank) t = (int)tk.max_rank;
     if (t < 1) t = 1;
     if (tk.sigma[0] == 0.0) t = 1;
-    tsel = t;
     *tk.rank_out = t;
+    tk.iscr[k + BIG_SWEEPS] = t;
     if (tk.info) {
       int sw = 0;
       while (sw < BIG_SWEEPS && tk.iscr[k + sw] != 0) ++sw;
       *tk.info = sw + 1;
     }
   }
-  __syncthreads();
-  const int t = tsel;
+}
+
+// U_R (kr x ld, zero beyond the rank t): the ordered final columns over sigma (square R)
+// or the ordered columns of J (wide R); for a wide R also W^T = the ordered final columns.
+__global__ __launch_bounds__(NT) void k_bsvd_copy(const SvdTask* __restrict__ tasks) {
+  const SvdTask tk = tasks[blockIdx.x];
+  if (!tk.block) return;
+  const BigView g = big_view(tk);
+  const int k = g.k, len = g.len;
+  const int t = tk.iscr[k + BIG_SWEEPS];
   const int ld = tk.t_ld > 0 ? tk.t_ld : t;
-  // W^T: ncol x t
-  for (int64_t idx = tid; idx < (int64_t)N * ld; idx += NT) {
-    const int col = (int)(idx / ld), i = (int)(idx - (int64_t)col * ld);
-    double v = 0.0;
-    if (i < t) {
-      const int j = perm[i];
-      if (g.tall) {
-        const double s = tk.sigma[i];
-        if (s > 0.0) {
-          const double* aj = A + (int64_t)j * len;
-          const int rmax = (tk.upper && col + 1 < len) ? col + 1 : len;
-          double acc = 0.0;
-          for (int row = 0; row < rmax; ++row) acc += aj[row] * g.aval(row, col);
-          v = acc / s;
-        }
-      } else {
-        v = A[(int64_t)j * len + col];
-      }
-    }
-    tk.wt[idx] = v;
-  }
-  // U_R: kr x t
-  for (int64_t idx = tid; idx < (int64_t)kr * ld; idx += NT) {
+  const int64_t stride = (int64_t)gridDim.y * NT;
+  for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)g.kr * ld; idx += stride) {
     const int row = (int)(idx / ld), i = (int)(idx - (int64_t)row * ld);
     double v = 0.0;
     if (i < t) {
-      const int j = perm[i];
+      const int j = tk.iscr[i];
       if (g.tall) {
         const double s = tk.sigma[i];
-        v = (s > 0.0) ? A[(int64_t)j * len + row] / s : ((row == i) ? 1.0 : 0.0);
+        v = (s > 0.0) ? tk.A[(int64_t)j * len + row] / s : ((row == i) ? 1.0 : 0.0);
       } else {
-        v = J[(int64_t)j * k + row];
+        v = tk.acc[(int64_t)j * k + row];
       }
     }
     tk.ur[idx] = v;
   }
+  if (!g.tall)
+    for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)g.N * ld; idx += stride) {
+      const int col = (int)(idx / ld), i = (int)(idx - (int64_t)col * ld);
+      tk.wt[idx] = (i < t) ? tk.A[(int64_t)tk.iscr[i] * len + col] : 0.0;
+    }
+}
+
+// Square R: W^T = R^T U_t (N x ld, zero beyond t), R upper triangular (entries left of
+// the diagonal read as zero), on the FP64 matrix cores: a workgroup of four waves per
+// 64 x 64 tile of W^T, K staged through LDS 16 at a time.
+__global__ __launch_bounds__(256) void k_bsvd_wt(const SvdTask* __restrict__ tasks) {
+  typedef Mma<double> M;
+  __shared__ double As[16][65];   // R^T tile: As[kk][c] = R[k0 + kk][col0 + c]
+  __shared__ double Bs[16][65];   // U tile:   Bs[kk][i] = ur[k0 + kk][i0 + i]
+  const SvdTask tk = tasks[blockIdx.z];
+  if (!tk.block || tk.kr != tk.ncol) return;
+  const int N = tk.ncol, K = tk.kr;
+  const int t = tk.iscr[K + BIG_SWEEPS];
+  const int ld = tk.t_ld > 0 ? tk.t_ld : t;
+  const int col0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
+  if (col0 >= N || i0 >= ld) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  M::acc_t acc[4] = {M::zero(), M::zero(), M::zero(), M::zero()};
+  // rows of an upper-triangular R beyond the last column of the tile are zero in its columns
+  const int kend = (tk.upper && col0 + 64 < K) ? col0 + 64 : K;
+  for (int k0 = 0; k0 < kend; k0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int kk = e >> 6, c = e & 63;
+      const int r = k0 + kk, col = col0 + c;
+      double v = 0.0;
+      if (r < K && col < N && !(tk.upper && col < r)) {
+        const int64_t off = (int64_t)r * tk.r_ld + col;
+        v = tk.r_f32 ? (double)((const float*)tk.R)[off] : ((const double*)tk.R)[off];
+      }
+      As[kk][c] = v;
+      const int ii = i0 + c;
+      Bs[kk][c] = (r < K && ii < t) ? tk.ur[(int64_t)r * ld + ii] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 16; s += 4) {
+      const double a = As[s + (lane >> 4)][16 * wave + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = M::mma(a, Bs[s + (lane >> 4)][16 * j + (lane & 15)], acc[j]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int col = col0 + 16 * wave + M::row(lane, v), i = i0 + 16 * j + (lane & 15);
+      if (col < N && i < ld) tk.wt[(int64_t)col * ld + i] = (i < t) ? acc[j][v] : 0.0;
+    }
 }
 
 }  // namespace
@@ -909,7 +958,7 @@ hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s) {
 }
 
 hipError_t launch_svd_big(const SvdTask* d_tasks, int ntasks, int max_kr, hipStream_t s) {
-  if (ntasks <= 0 || max_kr <= SVD_SMALL_MAX) return hipSuccess;
+  if (ntasks <= 0 || max_kr <= 0) return hipSuccess;
   if (max_kr > SVD_BIG_MAX) return hipErrorInvalidValue;
   static bool ready = false;
   if (!ready) {
@@ -927,7 +976,12 @@ hipError_t launch_svd_big(const SvdTask* d_tasks, int ntasks, int max_kr, hipStr
       hipLaunchKernelGGL(k_bsvd_round, dim3(ntasks, nbp / 2), dim3(NT), BIG_LDS, s, d_tasks, sw, r);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-  hipLaunchKernelGGL(k_bsvd_finish, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+  hipLaunchKernelGGL(k_bsvd_rank, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bsvd_copy, dim3(ntasks, 64), dim3(NT), 0, s, d_tasks);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const int tiles = (max_kr + 63) / 64;   // W^T is at most kr x kr (square R: N = kr, ld <= kr)
+  hipLaunchKernelGGL(k_bsvd_wt, dim3(tiles, tiles, ntasks), dim3(256), 0, s, d_tasks);
   return hipGetLastError();
 }
 

@@ -20,7 +20,7 @@ import torch
 __all__ = ["TT", "dot", "dot_batched", "axpy", "norm", "round", "round_batched", "round_randomized", "orthogonalize",
            "loo", "laplacian",
            "krylov_laplacian",
-           "Engine", "TTError", "cond", "effective_delta", "BatchRounder", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity"]
+           "Engine", "TTError", "cond", "effective_delta", "BatchRounder", "library_path", "SCHEMES", "round_workspace_bytes", "round_out_capacity", "set_svd_block_min"]
 
 TT_MAXD = 64
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -117,6 +117,8 @@ def _load():
         lib.tt_round_batched_async.restype = C.c_int
         lib.tt_ctx_set_graphs.argtypes = [P, C.c_int]
         lib.tt_ctx_set_graphs.restype = C.c_int
+        lib.tt_ctx_set_svd_block_min.argtypes = [P, C.c_int32]
+        lib.tt_ctx_set_svd_block_min.restype = C.c_int
         lib.tt_ctx_graph_count.argtypes = [P]
         lib.tt_ctx_graph_count.restype = C.c_int32
         lib.tt_round_effective_delta.argtypes = [C.POINTER(_Sum), C.c_double]
@@ -255,13 +257,16 @@ class _Ctx:
             raise TTError(st, self.lib.tt_last_error(self.h).decode())
 
     def call_with_ws(self, fn):
-        """Run fn(); grow the workspace and retry once when it reports TT_ECAPACITY."""
-        for _ in range(4):
+        """Run fn(); when it reports TT_ECAPACITY for the workspace, grow it and run fn again.
+        A call whose later steps need more than its earlier ones (ranks that grow along a
+        Gram-Schmidt run) reports only what it needed up to where it stopped, so the
+        workspace grows with headroom (1.5 times the report) to keep the reruns few."""
+        for _ in range(10):
             st = fn()
             if st == -3:
                 need = int(self.lib.tt_ctx_required_bytes(self.h))
                 if need > self.ws_bytes:
-                    self.ensure_ws(need)
+                    self.ensure_ws(need + need // 2)
                     continue
             self.check(st)
             return
@@ -393,6 +398,13 @@ def set_autotune(on: bool = True, device=None):
     """Let TT-round time candidate TSQR tree shapes for unseen QR shapes (kept for the process)."""
     ctx = _ctx(device)
     ctx.check(ctx.lib.tt_ctx_set_autotune(ctx.h, 1 if on else 0))
+
+
+def set_svd_block_min(rows: int, device=None):
+    """R factors of more than `rows` rows (32..1024) take the block Jacobi SVD over many
+    workgroups instead of the one-workgroup Jacobi (tt_ctx_set_svd_block_min)."""
+    ctx = _ctx(device)
+    ctx.check(ctx.lib.tt_ctx_set_svd_block_min(ctx.h, int(rows)))
 
 
 def tune_tsqr(rows: int, cols: int, dtype=torch.float64, device=None):
