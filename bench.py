@@ -64,6 +64,10 @@ def parse():
                    help="only the 256-job uneven batch (for profiler runs); prints its JSON object")
     p.add_argument("--randomized-only", action="store_true",
                    help="only the randomized-rounding measurement (for profiler runs); prints its JSON object")
+    p.add_argument("--serving-only", action="store_true",
+                   help="only the serving sweep (for profiler runs); prints its JSON object")
+    p.add_argument("--serving-qps", type=str, default="",
+                   help="comma-separated offered rates of the serving sweep (default 25,50,100,200)")
     return p.parse_args()
 
 
@@ -616,7 +620,7 @@ def cpu_baseline_paper_experiment(delta=1e-5):
             "sample": f"one FP64 NumPy/LAPACK call per scheme on the same experiment ({t_all:.1f} s)"}
 
 
-SERVE_DESC = ("64 solvers, d~U{5..8}, n~U{32,64,128}, solver rank~U{4..9}, basis b0~U{10..39} (restart at 40), "
+SERVE_DESC = ("64 solvers, d~U{5..8}, n~U{32,64,128}, solver rank~U{4..32}, basis b0~U{10..39} (restart at 40), "
               "MGS2 FP32-bulk, delta=1e-6, 8 GiB admission budget")
 
 
@@ -726,6 +730,12 @@ def main():
         return
     if args.batched_only:
         print(json.dumps(run_batched(tt, torch)))
+        return
+    if args.serving_only:
+        kw = {"qps_points": tuple(float(v) for v in args.serving_qps.split(","))} if args.serving_qps else {}
+        rep = run_serving(torch, nreq=args.serving_requests, **kw)
+        rep.pop("_sample")
+        print(json.dumps(rep))
         return
     pst = min(args.steps, 10)
     res32 = run_config(tt, torch, torch.float32, 1e-4, args.steps, args.warmup, profile_steps=pst)

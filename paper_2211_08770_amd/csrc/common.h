@@ -82,7 +82,7 @@ struct SvdTask {
   int32_t t_ld;           // > 0: wt and ur have t_ld columns (a bound of the rank), zero beyond t
   int32_t* info;          // device int: sweeps used (diagnostic)
   int32_t block;          // 1: block Jacobi over many workgroups (launch_svd_big), 0: one workgroup (launch_svd)
-  int32_t* iscr;          // block: int scratch of kr + 64 entries
+  int32_t* iscr;          // block: int scratch of 2 kr + 128 entries
 };
 
 // ---------------------------------------------------------------------------

@@ -468,7 +468,7 @@ bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why, bool bound_pl
   st.acc = (double*)ws.take((size_t)smax * smax * 8);
   st.sig = (double*)ws.take((size_t)smax * 8);
   st.perm = (int32_t*)ws.take((size_t)smax * 4);
-  st.iscr = (int32_t*)ws.take((size_t)(smax + 64) * 4);
+  st.iscr = (int32_t*)ws.take((size_t)(2 * smax + 128) * 4);
   st.wt = (double*)ws.take((size_t)smax * tmax * 8);
   st.urb[0] = (double*)ws.take((size_t)smax * tmax * 8);
   st.urb[1] = (double*)ws.take((size_t)smax * tmax * 8);

@@ -578,21 +578,27 @@ __global__ __launch_bounds__(NT) void k_svd(const SvdTask* __restrict__ tasks) {
 
 // ---------------------------------------------------------------------------
 // R factors with the block flag (more than SVD_SMALL_MAX rows, or above a
-// context's crossover): block one-sided Jacobi over many
-// workgroups.  The kr columns of A (= R or R^T as above, no deflation) are
-// split into blocks of BB; in each round of the circle schedule on the blocks
-// every disjoint pair of blocks is one workgroup, which forms the Gram matrix G
-// of its 2 BB columns on the FP64 matrix cores, diagonalises it by cyclic
-// (two-sided) Jacobi in LDS, V^T G V = diag, and rotates the columns (and J,
-// for a wide R) by V.  A pair whose columns are already orthogonal to
-// relative precision len u is left alone; a sweep in which no pair needed a
-// rotation ends the iteration (later rounds see the per-sweep counter and
-// return at once).  Singular values, order,
-// rank and the factors W^T, U_R then follow as in the one-workgroup kernel.
+// context's crossover): block one-sided Jacobi over many workgroups, always on
+// A = R^T (N x kr, column j = row j of R) with the rotations accumulated in J
+// (kr x kr).  Rows of R at the noise level -- the trailing rows of the R factor
+// of a matrix of low numerical rank -- are set aside first by the rule of the
+// one-workgroup kernel (their energy counts in the discarded tail), so a
+// low-rank R costs as little as its rank.  The active columns are split into
+// blocks of BB; in each round of the circle schedule on the blocks every
+// disjoint pair of blocks is one workgroup, which forms the Gram matrix G of
+// its 2 BB columns on the FP64 matrix cores, reduces its off-diagonal by at
+// most INNER_SWEEPS sweeps of cyclic (two-sided) Jacobi in LDS and rotates
+// the columns of A and J by the accumulated rotation V.  A pair whose columns
+// are orthogonal to relative precision N u is left alone; a sweep in which no
+// pair needed a rotation ends the iteration (later rounds see the per-sweep
+// counter and return at once).  Singular values, order, rank and the factors
+// W^T (the final columns of A) and U_R (columns of J) follow.
+//
+// iscr layout (2 kr + 128 ints): [0, kr) order of the singular values;
+// [kr, kr + 64) per-sweep rotation counters; kr + 64 rank; kr + 65 active
+// count; kr + 66, kr + 67 energy set aside (a double); [kr + 128, 2 kr + 128)
+// active columns in increasing order.
 // ---------------------------------------------------------------------------
-constexpr int BB = 32;              // columns per block
-constexpr int PW = 2 * BB;          // columns of a pair
-constexpr int GLD = PW + 1;         // padded leading dimension of G, V and the row chunk
 #ifndef BSVD_SWEEPS
 #define BSVD_SWEEPS 64
 #endif
@@ -601,55 +607,120 @@ constexpr int GLD = PW + 1;         // padded leading dimension of G, V and the 
 #endif
 constexpr int BIG_SWEEPS = BSVD_SWEEPS;     // outer sweeps at most
 constexpr int INNER_SWEEPS = BSVD_INNER;    // inner sweeps per pair at most
+static_assert(BIG_SWEEPS <= 64, "per-sweep counters: 64 slots");
+constexpr int BB = 32;              // columns per block
+constexpr int PW = 2 * BB;          // columns of a pair
+constexpr int GLD = PW + 1;         // padded leading dimension of G, V and the row chunk
 constexpr size_t BIG_LDS = (size_t)3 * PW * GLD * 8;
 
-struct BigView {
-  const SvdTask* tk;
-  bool tall;
-  int kr, N, len, k;
-  __device__ double aval(int i, int j) const {
-    const int rr = tall ? i : j, cc = tall ? j : i;
-    if (tk->upper && cc < rr) return 0.0;
-    const int64_t e = (int64_t)rr * tk->r_ld + cc;
-    return tk->r_f32 ? (double)((const float*)tk->R)[e] : ((const double*)tk->R)[e];
-  }
+struct BigSlots {
+  int* order;
+  int* rot;
+  int* rank;
+  int* kact;
+  int* act;
 };
 
-__device__ inline BigView big_view(const SvdTask& tk) {
-  BigView v;
-  v.tk = &tk;
-  v.kr = tk.kr;
-  v.N = tk.ncol;
-  v.tall = (tk.kr == tk.ncol);
-  v.len = tk.ncol;   // A = R (N x N) or R^T (N x kr): columns of length N
-  v.k = tk.kr;
-  return v;
+__device__ inline BigSlots big_slots(const SvdTask& tk) {
+  BigSlots b;
+  const int k = tk.kr;
+  b.order = tk.iscr;
+  b.rot = tk.iscr + k;
+  b.rank = tk.iscr + k + 64;
+  b.kact = tk.iscr + k + 65;
+  b.act = tk.iscr + k + 128;   // (kr + 66, kr + 67: the energy set aside, as the two halves of a double)
+  return b;
 }
 
-// A (len x k, column-major) from R, J = I (k x k) for a wide R, sweep counters zeroed.
+// R(i, j) with the upper-triangular mask
+__device__ inline double rval(const SvdTask& tk, int i, int j) {
+  if (tk.upper && j < i) return 0.0;
+  const int64_t e = (int64_t)i * tk.r_ld + j;
+  return tk.r_f32 ? (double)((const float*)tk.R)[e] : ((const double*)tk.R)[e];
+}
+
+// A = R^T (N x kr, column-major), J = I (kr x kr), sweep counters zeroed.
 __global__ __launch_bounds__(NT) void k_bsvd_prep(const SvdTask* __restrict__ tasks) {
   const SvdTask tk = tasks[blockIdx.x];
   if (!tk.block) return;
-  const BigView g = big_view(tk);
-  for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)g.len * g.k;
-       idx += (int64_t)gridDim.y * NT) {
-    const int j = (int)(idx / g.len), i = (int)(idx - (int64_t)j * g.len);
-    tk.A[idx] = g.aval(i, j);
+  const int N = tk.ncol, k = tk.kr;
+  const int64_t stride = (int64_t)gridDim.y * NT;
+  for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)N * k; idx += stride) {
+    const int j = (int)(idx / N), i = (int)(idx - (int64_t)j * N);
+    tk.A[idx] = rval(tk, j, i);
   }
-  if (!g.tall)
-    for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)g.k * g.k;
-         idx += (int64_t)gridDim.y * NT) {
-      const int j = (int)(idx / g.k), i = (int)(idx - (int64_t)j * g.k);
-      tk.acc[idx] = (i == j) ? 1.0 : 0.0;
-    }
-  if (blockIdx.y == 0)
-    for (int i = threadIdx.x; i < BIG_SWEEPS; i += NT) tk.iscr[g.k + i] = 0;
+  for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)k * k; idx += stride) {
+    const int j = (int)(idx / k), i = (int)(idx - (int64_t)j * k);
+    tk.acc[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  if (blockIdx.y == 0) {
+    const BigSlots b = big_slots(tk);
+    for (int i = threadIdx.x; i < 64; i += NT) b.rot[i] = 0;
+  }
 }
 
-// Column c (0 .. PW-1) of the pair (bp, bq): its index in A, or -1 past the last column.
-__device__ inline int pair_col(int c, int bp, int bq, int k) {
-  const int j = (c < BB) ? bp * BB + c : bq * BB + (c - BB);
-  return j < k ? j : -1;
+// Column norms of A, the columns set aside (the largest set of smallest columns whose
+// energy together is at most (2 sqrt(kr) u ||A||_F)^2, and zero columns), the active list.
+__global__ __launch_bounds__(NT) void k_bsvd_deflate(const SvdTask* __restrict__ tasks) {
+  __shared__ double nrm2[SVD_BIG_MAX];
+  __shared__ unsigned char on[SVD_BIG_MAX];
+  __shared__ double red[NW];
+  const SvdTask tk = tasks[blockIdx.x];
+  if (!tk.block) return;
+  const int N = tk.ncol, k = tk.kr;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = wave; j < k; j += NW) {
+    const double* aj = tk.A + (int64_t)j * N;
+    double s0 = 0.0, s1 = 0.0;
+    int i = lane;
+    for (; i + 64 < N; i += 128) {
+      s0 += aj[i] * aj[i];
+      s1 += aj[i + 64] * aj[i + 64];
+    }
+    if (i < N) s0 += aj[i] * aj[i];
+    const double s = wave_sum(s0 + s1);
+    if (lane == 0) nrm2[j] = s;
+  }
+  __syncthreads();
+  double tot = 0.0;
+  for (int j = tid; j < k; j += NT) tot += nrm2[j];
+  tot = block_sum(tot, red);
+  const double tau = 2.0 * sqrt((double)k) * tk.bulk_u;
+  const double tau2 = tau * tau * tot;
+  for (int j = tid; j < k; j += NT) {
+    const double v = nrm2[j];
+    double b[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i0 = 0; i0 < k; i0 += 8) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q;
+        const double w = nrm2[i < k ? i : 0];
+        if (i < k && (w < v || (w == v && i <= j))) b[q] += w;
+      }
+    }
+    const double below = ((b[0] + b[1]) + (b[2] + b[3])) + ((b[4] + b[5]) + (b[6] + b[7]));
+    on[j] = ((below <= tau2 && tau2 > 0.0) || v == 0.0) ? 0 : 1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const BigSlots bs = big_slots(tk);
+    int c = 0;
+    double dropped = 0.0;
+    for (int j = 0; j < k; ++j) {
+      if (on[j]) bs.act[c++] = j;
+      else dropped += nrm2[j];
+    }
+    *bs.kact = c;
+    const unsigned long long bits = __double_as_longlong(dropped);
+    tk.iscr[k + 66] = (int)(bits & 0xffffffffull);
+    tk.iscr[k + 67] = (int)(bits >> 32);
+  }
+}
+
+// Active column c (0 .. PW-1) of the pair (bp, bq): its index in A, or -1 past the last one.
+__device__ inline int pair_col(int c, int bp, int bq, int kact, const int* __restrict__ act) {
+  const int a = (c < BB) ? bp * BB + c : bq * BB + (c - BB);
+  return a < kact ? act[a] : -1;
 }
 
 // Rows [0, rows) of the pair's columns of X (column-major, ld) times V, in place,
@@ -692,40 +763,45 @@ __global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ t
   __shared__ int need, inner_rot;
   const SvdTask tk = tasks[blockIdx.x];
   if (!tk.block) return;
-  const BigView g = big_view(tk);
-  int* rot = tk.iscr + g.k;
-  if (sweep > 0 && rot[sweep - 1] == 0) return;   // converged
-  const int nb = (g.k + BB - 1) / BB, nbp = nb + (nb & 1);
+  const BigSlots bs = big_slots(tk);
+  if (sweep > 0 && bs.rot[sweep - 1] == 0) return;   // converged
+  const int N = tk.ncol, k = tk.kr, kact = *bs.kact;
+  const int nb = (kact + BB - 1) / BB, nbp = nb + (nb & 1);
   const int pair = blockIdx.y;
-  if (pair >= nbp / 2 || round >= nbp - 1) return;
+  if (nb < 2 && sweep > 0) return;   // one block: its first round orthogonalised it
+  if (pair >= (nbp > 0 ? nbp / 2 : 0) || round >= (nbp > 1 ? nbp - 1 : 1)) return;
   int bp, bq;
-  rr_pair(round, pair, nbp, bp, bq);
-  if (bq >= nb) return;   // paired with the empty block
+  if (nbp >= 2) {
+    rr_pair(round, pair, nbp, bp, bq);
+  } else {
+    bp = 0;
+    bq = 1;   // a single block (at most BB active columns) with the empty one
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* G = blds;                  // PW x GLD
   double* V = blds + PW * GLD;       // PW x GLD
   double* Ch = blds + 2 * PW * GLD;  // PW x GLD
-  if (tid < PW) cidx[tid] = pair_col(tid, bp, bq, g.k);
+  if (tid < PW) cidx[tid] = pair_col(tid, bp, bq, kact, bs.act);
   if (tid == 0) need = 0;
   __syncthreads();
   // ---- G = A_pair^T A_pair: wave w owns the 16 x 16 tile (w / 4, w % 4)
   {
     const int ti = wave >> 2, tj = wave & 3;
     const int ja = cidx[ti * 16 + (lane & 15)], jb = cidx[tj * 16 + (lane & 15)];
-    const double* Aa = tk.A + (int64_t)(ja >= 0 ? ja : 0) * g.len;
-    const double* Ab = tk.A + (int64_t)(jb >= 0 ? jb : 0) * g.len;
+    const double* Aa = tk.A + (int64_t)(ja >= 0 ? ja : 0) * N;
+    const double* Ab = tk.A + (int64_t)(jb >= 0 ? jb : 0) * N;
     M::acc_t a0 = M::zero(), a1 = M::zero();
     int r0 = 0;
-    for (; r0 + 8 <= g.len; r0 += 8) {
+    for (; r0 + 8 <= N; r0 += 8) {
       const int r = r0 + (lane >> 4);
       const double x0 = ja >= 0 ? Aa[r] : 0.0, y0 = jb >= 0 ? Ab[r] : 0.0;
       const double x1 = ja >= 0 ? Aa[r + 4] : 0.0, y1 = jb >= 0 ? Ab[r + 4] : 0.0;
       a0 = M::mma(x0, y0, a0);
       a1 = M::mma(x1, y1, a1);
     }
-    for (; r0 < g.len; r0 += 4) {
+    for (; r0 < N; r0 += 4) {
       const int r = r0 + (lane >> 4);
-      const bool ok = r < g.len;
+      const bool ok = r < N;
       const double x = (ok && ja >= 0) ? Aa[r] : 0.0, y = (ok && jb >= 0) ? Ab[r] : 0.0;
       a0 = M::mma(x, y, a0);
     }
@@ -733,7 +809,7 @@ __global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ t
     for (int v = 0; v < 4; ++v) G[(ti * 16 + M::row(lane, v)) * GLD + tj * 16 + (lane & 15)] = a0[v] + a1[v];
   }
   __syncthreads();
-  const double tol = (double)g.len * 1.1102230246251565e-16;
+  const double tol = (double)N * 1.1102230246251565e-16;
   const double tol2 = tol * tol;
   for (int e = tid; e < PW * PW; e += NT) {
     const int i = e / PW, j = e - i * PW;
@@ -746,15 +822,15 @@ __global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ t
   if (!need) return;   // the whole workgroup: no barrier is reached
   // (with the inner sweeps capped, convergence is not quadratic: a sweep ends the
   // iteration only when no pair needed any rotation)
-  if (tid == 0) atomicAdd(&rot[sweep], 1);
+  if (tid == 0) atomicAdd(&bs.rot[sweep], 1);
   for (int e = tid; e < PW * PW; e += NT) {
     const int i = e / PW, j = e - i * PW;
     V[i * GLD + j] = (i == j) ? 1.0 : 0.0;
   }
-  // ---- cyclic Jacobi on G: rounds of PW/2 disjoint pairs, G <- J^T G J, V <- V J.
-  // At most INNER_SWEEPS sweeps: the pair need not leave exactly orthogonal, since
-  // the outer sweeps go on until no pair needs a rotation.
-  for (int isw = 0; isw < INNER_SWEEPS; ++isw) {
+  // ---- cyclic Jacobi on G: rounds of PW/2 disjoint pairs, G <- J^T G J, V <- V J; a lone
+  // block (the whole active set) is diagonalised to convergence, since no later round comes
+  const int isw_max = (nb < 2) ? 40 : INNER_SWEEPS;
+  for (int isw = 0; isw < isw_max; ++isw) {
     if (tid == 0) inner_rot = 0;
     __syncthreads();
     for (int rr = 0; rr < PW - 1; ++rr) {
@@ -801,145 +877,90 @@ __global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ t
     }
     if (!inner_rot) break;
   }
-  // ---- the pair's columns of A (and of J) rotated by V
-  rotate_rows(tk.A, g.len, g.len, cidx, V, Ch);
-  if (!g.tall) rotate_rows(tk.acc, g.k, g.k, cidx, V, Ch);
+  // ---- the pair's columns of A and of J rotated by V
+  rotate_rows(tk.A, N, N, cidx, V, Ch);
+  rotate_rows(tk.acc, k, k, cidx, V, Ch);
 }
 
-// Singular values (column norms), their order and the rank; the order goes to
-// iscr[0 .. k), the rank to iscr[k + BIG_SWEEPS].
+// Singular values (norms of the active columns), their order and the rank.
 __global__ __launch_bounds__(NT) void k_bsvd_rank(const SvdTask* __restrict__ tasks) {
   __shared__ double nrm[SVD_BIG_MAX];
   const SvdTask tk = tasks[blockIdx.x];
   if (!tk.block) return;
-  const BigView g = big_view(tk);
+  const BigSlots bs = big_slots(tk);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int k = g.k, len = g.len;
-  for (int j = wave; j < k; j += NW) {
-    const double* aj = tk.A + (int64_t)j * len;
+  const int N = tk.ncol, k = tk.kr, kact = *bs.kact;
+  for (int a = wave; a < kact; a += NW) {
+    const double* aj = tk.A + (int64_t)bs.act[a] * N;
     double s0 = 0.0, s1 = 0.0;
     int i = lane;
-    for (; i + 64 < len; i += 128) {
+    for (; i + 64 < N; i += 128) {
       s0 += aj[i] * aj[i];
       s1 += aj[i + 64] * aj[i + 64];
     }
-    if (i < len) s0 += aj[i] * aj[i];
+    if (i < N) s0 += aj[i] * aj[i];
     const double s = wave_sum(s0 + s1);
-    if (lane == 0) nrm[j] = sqrt(s);
+    if (lane == 0) nrm[a] = sqrt(s);
   }
   __syncthreads();
-  for (int j = tid; j < k; j += NT) {
-    const double sj = nrm[j];
+  for (int a = tid; a < kact; a += NT) {
+    const double sa = nrm[a];
     int rk = 0;
-    for (int i = 0; i < k; ++i) {
+    for (int i = 0; i < kact; ++i) {
       const double si = nrm[i];
-      rk += (si > sj) || (si == sj && i < j);
+      rk += (si > sa) || (si == sa && i < a);
     }
-    tk.iscr[rk] = j;
-    tk.sigma[rk] = sj;
+    bs.order[rk] = bs.act[a];
+    tk.sigma[rk] = sa;
   }
   __syncthreads();
+  for (int i = kact + tid; i < k; i += NT) tk.sigma[i] = 0.0;
   if (tid == 0) {
+    const unsigned long long bits =
+        ((unsigned long long)(unsigned)tk.iscr[k + 67] << 32) | (unsigned long long)(unsigned)tk.iscr[k + 66];
+    const double edrop = __longlong_as_double((long long)bits);
     const double eps = (tk.delta_scaled > tk.eps_floor ? tk.delta_scaled : tk.eps_floor) * (*tk.norm);
     const double eps2 = eps * eps;
-    int t = k;
-    double tail = 0.0;
-    for (int i = k - 1; i >= 1; --i) {
+    int t = kact > 0 ? kact : 1;
+    double tail = edrop;
+    for (int i = kact - 1; i >= 1; --i) {
       tail += tk.sigma[i] * tk.sigma[i];
       if (tail <= eps2) t = i;
       else break;
     }
     if (tk.max_rank > 0 && t > tk.max_rank) t = (int)tk.max_rank;
     if (t < 1) t = 1;
-    if (tk.sigma[0] == 0.0) t = 1;
+    if (kact == 0 || tk.sigma[0] == 0.0) t = 1;
     *tk.rank_out = t;
-    tk.iscr[k + BIG_SWEEPS] = t;
+    *bs.rank = t;
     if (tk.info) {
       int sw = 0;
-      while (sw < BIG_SWEEPS && tk.iscr[k + sw] != 0) ++sw;
+      while (sw < BIG_SWEEPS && bs.rot[sw] != 0) ++sw;
       *tk.info = sw + 1;
     }
   }
 }
 
-// U_R (kr x ld, zero beyond the rank t): the ordered final columns over sigma (square R)
-// or the ordered columns of J (wide R); for a wide R also W^T = the ordered final columns.
+// W^T (N x ld): the ordered final columns of A (= V Sigma); U_R (kr x ld): the ordered
+// columns of J (= U); zero beyond the rank t.  No active column (R = 0): W = 0, U_R = I_t.
 __global__ __launch_bounds__(NT) void k_bsvd_copy(const SvdTask* __restrict__ tasks) {
   const SvdTask tk = tasks[blockIdx.x];
   if (!tk.block) return;
-  const BigView g = big_view(tk);
-  const int k = g.k, len = g.len;
-  const int t = tk.iscr[k + BIG_SWEEPS];
+  const BigSlots bs = big_slots(tk);
+  const int N = tk.ncol, k = tk.kr, kact = *bs.kact;
+  const int t = *bs.rank;
   const int ld = tk.t_ld > 0 ? tk.t_ld : t;
   const int64_t stride = (int64_t)gridDim.y * NT;
-  for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)g.kr * ld; idx += stride) {
+  for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)k * ld; idx += stride) {
     const int row = (int)(idx / ld), i = (int)(idx - (int64_t)row * ld);
     double v = 0.0;
-    if (i < t) {
-      const int j = tk.iscr[i];
-      if (g.tall) {
-        const double s = tk.sigma[i];
-        v = (s > 0.0) ? tk.A[(int64_t)j * len + row] / s : ((row == i) ? 1.0 : 0.0);
-      } else {
-        v = tk.acc[(int64_t)j * k + row];
-      }
-    }
+    if (i < t) v = (i < kact) ? tk.acc[(int64_t)bs.order[i] * k + row] : ((row == i) ? 1.0 : 0.0);
     tk.ur[idx] = v;
   }
-  if (!g.tall)
-    for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)g.N * ld; idx += stride) {
-      const int col = (int)(idx / ld), i = (int)(idx - (int64_t)col * ld);
-      tk.wt[idx] = (i < t) ? tk.A[(int64_t)tk.iscr[i] * len + col] : 0.0;
-    }
-}
-
-// Square R: W^T = R^T U_t (N x ld, zero beyond t), R upper triangular (entries left of
-// the diagonal read as zero), on the FP64 matrix cores: a workgroup of four waves per
-// 64 x 64 tile of W^T, K staged through LDS 16 at a time.
-__global__ __launch_bounds__(256) void k_bsvd_wt(const SvdTask* __restrict__ tasks) {
-  typedef Mma<double> M;
-  __shared__ double As[16][65];   // R^T tile: As[kk][c] = R[k0 + kk][col0 + c]
-  __shared__ double Bs[16][65];   // U tile:   Bs[kk][i] = ur[k0 + kk][i0 + i]
-  const SvdTask tk = tasks[blockIdx.z];
-  if (!tk.block || tk.kr != tk.ncol) return;
-  const int N = tk.ncol, K = tk.kr;
-  const int t = tk.iscr[K + BIG_SWEEPS];
-  const int ld = tk.t_ld > 0 ? tk.t_ld : t;
-  const int col0 = blockIdx.x * 64, i0 = blockIdx.y * 64;
-  if (col0 >= N || i0 >= ld) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  M::acc_t acc[4] = {M::zero(), M::zero(), M::zero(), M::zero()};
-  // rows of an upper-triangular R beyond the last column of the tile are zero in its columns
-  const int kend = (tk.upper && col0 + 64 < K) ? col0 + 64 : K;
-  for (int k0 = 0; k0 < kend; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = e >> 6, c = e & 63;
-      const int r = k0 + kk, col = col0 + c;
-      double v = 0.0;
-      if (r < K && col < N && !(tk.upper && col < r)) {
-        const int64_t off = (int64_t)r * tk.r_ld + col;
-        v = tk.r_f32 ? (double)((const float*)tk.R)[off] : ((const double*)tk.R)[off];
-      }
-      As[kk][c] = v;
-      const int ii = i0 + c;
-      Bs[kk][c] = (r < K && ii < t) ? tk.ur[(int64_t)r * ld + ii] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < 16; s += 4) {
-      const double a = As[s + (lane >> 4)][16 * wave + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j] = M::mma(a, Bs[s + (lane >> 4)][16 * j + (lane & 15)], acc[j]);
-    }
-    __syncthreads();
+  for (int64_t idx = blockIdx.y * (int64_t)NT + threadIdx.x; idx < (int64_t)N * ld; idx += stride) {
+    const int col = (int)(idx / ld), i = (int)(idx - (int64_t)col * ld);
+    tk.wt[idx] = (i < t && i < kact) ? tk.A[(int64_t)bs.order[i] * N + col] : 0.0;
   }
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int col = col0 + 16 * wave + M::row(lane, v), i = i0 + 16 * j + (lane & 15);
-      if (col < N && i < ld) tk.wt[(int64_t)col * ld + i] = (i < t) ? acc[j][v] : 0.0;
-    }
 }
 
 }  // namespace
@@ -970,18 +991,17 @@ hipError_t launch_svd_big(const SvdTask* d_tasks, int ntasks, int max_kr, hipStr
   hipLaunchKernelGGL(k_bsvd_prep, dim3(ntasks, 64), dim3(NT), 0, s, d_tasks);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bsvd_deflate, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const int nb = (max_kr + BB - 1) / BB, nbp = nb + (nb & 1);
   for (int sw = 0; sw < BIG_SWEEPS; ++sw)
-    for (int r = 0; r < nbp - 1; ++r) {
-      hipLaunchKernelGGL(k_bsvd_round, dim3(ntasks, nbp / 2), dim3(NT), BIG_LDS, s, d_tasks, sw, r);
+    for (int r = 0; r < (nbp > 1 ? nbp - 1 : 1); ++r) {
+      hipLaunchKernelGGL(k_bsvd_round, dim3(ntasks, nbp > 1 ? nbp / 2 : 1), dim3(NT), BIG_LDS, s, d_tasks, sw, r);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   hipLaunchKernelGGL(k_bsvd_rank, dim3(ntasks), dim3(NT), 0, s, d_tasks);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bsvd_copy, dim3(ntasks, 64), dim3(NT), 0, s, d_tasks);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int tiles = (max_kr + 63) / 64;   // W^T is at most kr x kr (square R: N = kr, ld <= kr)
-  hipLaunchKernelGGL(k_bsvd_wt, dim3(tiles, tiles, ntasks), dim3(256), 0, s, d_tasks);
   return hipGetLastError();
 }
 

@@ -102,7 +102,7 @@ def uneven_jobs(seed=30000, njobs=256, d_range=(4, 10), n_choices=(16, 32, 64),
     return jobs
 
 
-def serving_solver(g: np.random.Generator, d_range=(5, 8), n_choices=(32, 64, 128), r_range=(4, 9),
+def serving_solver(g: np.random.Generator, d_range=(5, 8), n_choices=(32, 64, 128), r_range=(4, 32),
                    b0_range=(10, 39), bmax=40, dtype=np.float32):
     """One simulated TT-GMRES solver of the serving workload.
 
