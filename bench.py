@@ -66,6 +66,10 @@ def parse():
                    help="only the randomized-rounding measurement (for profiler runs); prints its JSON object")
     p.add_argument("--serving-only", action="store_true",
                    help="only the serving sweep (for profiler runs); prints its JSON object")
+    p.add_argument("--order6-only", action="store_true",
+                   help="only the order-6 experiment of the paper's workload (for profiler runs); prints its JSON object")
+    p.add_argument("--config2-only", action="store_true",
+                   help="only the CGS2/Gram runs of the order-6, n=64 workload (for profiler runs); prints its JSON object")
     p.add_argument("--serving-qps", type=str, default="",
                    help="comma-separated offered rates of the serving sweep (default 25,50,100,200)")
     return p.parse_args()
@@ -580,8 +584,13 @@ def run_paper_experiment(tt, torch, delta=1e-5, reps=3):
                                "compression_ratio_q": round(sum(sizes) / (m * full), 4),
                                "compression_ratio_q_last": round(sizes[-1] / full, 4),
                                "compression_gain_q": [round(g, 3) for g in st["gain"]]}
-    # the order-6 experiment (n = 15, m = 35): each scheme up to a pre-round rank guard (the
-    # completed prefix), beside the oracle's run of the same experiment (stored curves)
+    out["order6"] = run_order6(tt, torch, delta)
+    return out
+
+
+def run_order6(tt, torch, delta=1e-5):
+    """The order-6 experiment (n = 15, m = 35): each scheme up to a pre-round rank guard (the
+    completed prefix), beside the oracle's run of the same experiment (stored curves)."""
     ns6, m6 = [15] * 6, 35
     A6 = tt.krylov_laplacian(ns6, m6)
     gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "order6_oracle.json")
@@ -608,11 +617,10 @@ def run_paper_experiment(tt, torch, delta=1e-5, reps=3):
                    "oracle_loo_at_m_reached": r["loo"][k - 1] if k else None,
                    "max_rank_q": max(max(q.r) for q in Q) if Q else None,
                    "oracle_max_rank_q_prefix": max(max(v) for v in r["q_ranks"][:k]) if k else None}
-    out["order6"] = {"workload": "d=6, n=15, m=35 Krylov TT-vectors, delta=1e-5, FP64; each scheme up to its "
-                                 "pre-round rank guard (CGS none, MGS/CGS2/MGS2 2048, TT-Householder 8192 on the "
-                                 "first 20 vectors); the oracle's values from its stored run of the same experiment",
-                     "schemes": o6}
-    return out
+    return {"workload": "d=6, n=15, m=35 Krylov TT-vectors, delta=1e-5, FP64; each scheme up to its "
+                        "pre-round rank guard (CGS none, MGS/CGS2/MGS2 2048, TT-Householder 8192 on the "
+                        "first 20 vectors); the oracle's values from its stored run of the same experiment",
+            "schemes": o6}
 
 
 def cpu_baseline_paper_experiment(delta=1e-5):
@@ -749,6 +757,12 @@ def main():
     if args.batched_only:
         print(json.dumps(run_batched(tt, torch)))
         return
+    if args.order6_only:
+        print(json.dumps(run_order6(tt, torch)))
+        return
+    if args.config2_only:
+        print(json.dumps(run_config2(tt, torch)))
+        return
     if args.serving_only:
         kw = {"qps_points": tuple(float(v) for v in args.serving_qps.split(","))} if args.serving_qps else {}
         rep = run_serving(torch, nreq=args.serving_requests, **kw)
@@ -805,7 +819,7 @@ def main():
                                                                          for b in (1e-3, 1e-5, 1e-7)]}
                                                               if args.config2_all else {}))
         progress("config2_guarded")
-        line["serving"] = run_serving(torch, nreq=args.serving_requests, keep_sample=0 if args.no_cpu else 4)
+        line["serving"] = run_serving(torch, nreq=args.serving_requests, keep_sample=0 if args.no_cpu else 2)
         sample = line["serving"].pop("_sample")
         progress("serving sweep")
         line["householder"] = run_householder(tt, torch)

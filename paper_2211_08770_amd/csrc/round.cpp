@@ -361,12 +361,18 @@ struct JobState {
   // contracts W_k with Q_k by a GEMM instead of applying the tree
   void* Qx[TT_MAXD] = {nullptr};
   double* eye = nullptr;
+  int64_t eye_n = 0;            // the identity is eye_n x eye_n (the widest core with an explicit Q)
   char* qx_block = nullptr;
   size_t qx_cap = 0;
   // planning at rank bounds: the result's cores at their bound shapes (core k at stg_off[k])
   char* stage = nullptr;
   int64_t stg_off[TT_MAXD] = {0};
 };
+
+#ifndef TT_QX_MAX_COLS
+#define TT_QX_MAX_COLS 256
+#endif
+constexpr int64_t QX_MAX_COLS = TT_QX_MAX_COLS;   // explicit orthogonal factors of at most this many columns
 
 // Bytes a tree plan of any M' x N matrix with M' <= M needs, whatever shape the
 // autotuner picks for it: the most storage goes to the shape with the
@@ -474,17 +480,22 @@ bool plan_job(tt_ctx* c, RJob& jb, JobState& st, std::string* why, bool bound_pl
   st.urb[1] = (double*)ws.take((size_t)smax * tmax * 8);
   st.d_norm = (double*)ws.take(64);
   // explicit Q for the right-to-left cores 2..d-1 (core 1's is needed right after the sweep,
-  // so it keeps the tree application); one identity and one apply scratch shared by them
+  // so it keeps the tree application); one identity and one apply scratch shared by them.
+  // Only for factors of at most QX_MAX_COLS columns: forming Q applies the tree to s_k
+  // columns, the left-to-right step then needs t_k <= s_k of them, so for wide factors of
+  // low truncated rank the direct application is far cheaper (and needs no M x s_k copy).
   int64_t nmax = 0;
   size_t qx_work = 0;
   for (int k = 2; k < d; ++k) {
     const int64_t M = jb.n[k] * st.s[k + 1], N = jb.R[k];
+    if (st.s[k] > QX_MAX_COLS) continue;
     st.Qx[k] = ws.take((size_t)M * st.s[k] * elt);
     nmax = std::max(nmax, N);
     qx_work = std::max(qx_work, apply_work_bytes(st.rl[k], N));
   }
   if (nmax > 0) {
     st.eye = (double*)ws.take((size_t)nmax * nmax * 8);
+    st.eye_n = nmax;
     st.qx_cap = qx_work;
     st.qx_block = (char*)ws.take(std::max<size_t>(qx_work, 256));
   }
@@ -984,14 +995,11 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
   // one identity for every job's explicit Q: the largest of the jobs' identity buffers
   double* eye = nullptr;
   int64_t eye_n = 0;
-  for (int j = 0; j < nj; ++j) {
-    int64_t nmax = 0;
-    for (int kk = 2; kk < jobs[j].d; ++kk) nmax = std::max(nmax, jobs[j].R[kk]);
-    if (st[j].eye && nmax > eye_n) {
-      eye_n = nmax;
+  for (int j = 0; j < nj; ++j)
+    if (st[j].eye && st[j].eye_n > eye_n) {   // (sized in plan_job: only cores with an explicit Q)
+      eye_n = st[j].eye_n;
       eye = st[j].eye;
     }
-  }
   if (eye && (e = launch_eye(eye, (int)eye_n, s)) != hipSuccess) return hip_fail(c, e, "eye");
   for (int step = 0; step + 1 < maxd; ++step) {
     std::vector<Tree*> trees;
