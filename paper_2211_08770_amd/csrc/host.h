@@ -165,12 +165,20 @@ struct Tree {
   // `rest`, (M - nf) x (N - nf) in the leaf dtype, which `next` factors in turn.  Then
   // A = Q_1 diag(I, Q_next) [R_11 R_12; 0 R_next] with rows in that gathered order, and
   // R is assembled in rfull (kr x N doubles, ld N).
+  // The tiles of a block hold every remaining column only while the block is factored: they
+  // live in one region that every block of the chain reuses, and once a block is done each
+  // tile's factored columns (the reflectors and R, m x nf) move to `ctile`, which the
+  // application of Q reads.  The blocks of a chain share one `rest` buffer, and a nested
+  // block writes its R in place inside the outer block's rfull (ld r_ld).
   int64_t nf = 0;                               // 0: an ordinary tree
   std::shared_ptr<Tree> next;
   void* rest = nullptr;
   double* rfull = nullptr;
+  int64_t r_ld = 0;
+  std::vector<std::vector<void*>> ctile;        // [level][tile]: m x nf, ld nf
   int kr() const;                               // rows of the R factor
-  const void* root_R() const;                   // R (row-major, ld = N; entries left of the diagonal not read)
+  const void* root_R() const;                   // R (row-major, ld = rld(); entries left of the diagonal not read)
+  int64_t rld() const { return next ? r_ld : N; }
   int root_f32() const { return !next && lvl.size() == 1 && leaf_dtype == TT_F32 ? 1 : 0; }   // dtype of root_R
   int depth() const { return (int)lvl.size(); }
   int64_t fk() const { return next ? nf : N; }  // columns the tiles factor

@@ -93,8 +93,25 @@ bool plan_tree(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void*
   return plan_tree_shape(cv, t, M, N, dtype, src, rs, cs, sh, why);
 }
 
+// The region the full-width tiles of a chain of column blocks share.
+struct WideArea {
+  char* base = nullptr;
+  size_t cap = 0;
+  bool measure = false;
+};
+
+static bool plan_tree_impl(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs,
+                           int64_t cs, TreeShape req, std::string* why, const WideArea* wide, void* shared_rest,
+                           double* rfull_in, int64_t r_ld_in);
+
 bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs, int64_t cs,
                      TreeShape req, std::string* why) {
+  return plan_tree_impl(cv, t, M, N, dtype, src, rs, cs, req, why, nullptr, nullptr, nullptr, 0);
+}
+
+static bool plan_tree_impl(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const void* src, int64_t rs,
+                           int64_t cs, TreeShape req, std::string* why, const WideArea* wide, void* shared_rest,
+                           double* rfull_in, int64_t r_ld_in) {
   t.M = M;
   t.N = N;
   t.leaf_dtype = dtype;
@@ -104,6 +121,8 @@ bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const
   t.next.reset();
   t.rest = nullptr;
   t.rfull = nullptr;
+  t.r_ld = 0;
+  t.ctile.clear();
   if (M < 1 || N < 1) {
     if (why) *why = "empty QR shape";
     return false;
@@ -142,7 +161,7 @@ bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const
     q.m = (int32_t)m;
     q.ncol = (int32_t)N;
     q.nfact = nfact;
-    q.tile = cv.take((size_t)m * N * elt);
+    if (!nfact) q.tile = cv.take((size_t)m * N * elt);   // (column blocks: below)
     q.tau = (double*)cv.take((size_t)k * 8);
     q.tmat = cv.take((size_t)npanels(k) * QR_NB * QR_NB * 8);
     leaves.push_back(q);
@@ -172,7 +191,7 @@ bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const
       q.m = (int32_t)rows;
       q.ncol = (int32_t)N;
       q.nfact = nfact;
-      q.tile = cv.take((size_t)rows * N * 8);
+      if (!nfact) q.tile = cv.take((size_t)rows * N * 8);
       q.tau = (double*)cv.take((size_t)k * 8);
       q.tmat = cv.take((size_t)npanels(k) * QR_NB * QR_NB * 8);
       nodes.push_back(q);
@@ -180,14 +199,52 @@ bool plan_tree_shape(Carver& cv, Tree& t, int64_t M, int64_t N, int dtype, const
     t.lvl.push_back(std::move(nodes));
   }
   if (nfact) {
+    // full-width tiles in the chain's shared region (the first block of a chain sizes it: the
+    // later blocks have fewer rows and columns), the factored columns of each tile kept apart
+    auto full_bytes = [&](size_t l, const QrTask& q) {
+      return (((size_t)q.m * N * (l == 0 ? elt : 8)) + 255) & ~(size_t)255;
+    };
+    WideArea wa;
+    if (wide) {
+      wa = *wide;
+    } else {
+      size_t need = 0;
+      for (size_t l = 0; l < t.lvl.size(); ++l)
+        for (const QrTask& q : t.lvl[l]) need += full_bytes(l, q);
+      wa.base = (char*)cv.take(need);
+      wa.cap = need;
+      wa.measure = cv.measure || wa.base == nullptr;
+    }
+    Carver wcv;
+    wcv.base = wa.base;
+    wcv.cap = wa.cap;
+    wcv.measure = wa.measure;
+    t.ctile.resize(t.lvl.size());
+    for (size_t l = 0; l < t.lvl.size(); ++l)
+      for (QrTask& q : t.lvl[l]) {
+        q.tile = wcv.take(full_bytes(l, q));
+        t.ctile[l].push_back(cv.take((size_t)q.m * fk * (l == 0 ? elt : 8)));
+      }
+    if (!wcv.measure && wcv.off > wcv.cap) {
+      if (why) *why = "internal: column-block tiles exceed their region";
+      return false;
+    }
     // the trailing block: rows left behind by the tiles, in level order, factored by an
     // ordinary (or again blocked) tree of the default shape
     t.nf = fk;
-    t.rest = cv.take((size_t)(M - fk) * (N - fk) * elt);
+    t.rest = shared_rest ? shared_rest : cv.take((size_t)(M - fk) * (N - fk) * elt);
+    if (wide) {   // a nested block writes its R inside the outer block's
+      t.rfull = rfull_in;
+      t.r_ld = r_ld_in;
+    } else {
+      t.rfull = (double*)cv.take((size_t)std::min(M, N) * N * 8);
+      t.r_ld = N;
+    }
     t.next = std::make_shared<Tree>();
-    if (!plan_tree_shape(cv, *t.next, M - fk, N - fk, dtype, t.rest, N - fk, 1, default_shape(M - fk, N - fk), why))
+    double* inner_r = t.rfull ? t.rfull + fk * t.r_ld + fk : nullptr;
+    if (!plan_tree_impl(cv, *t.next, M - fk, N - fk, dtype, t.rest, N - fk, 1, default_shape(M - fk, N - fk), why,
+                        &wa, t.rest, inner_r, t.r_ld))
       return false;
-    t.rfull = (double*)cv.take((size_t)t.kr() * N * 8);
   }
   return true;
 }
@@ -297,11 +354,11 @@ void plan_apply(Carver& cv, const Tree& t, const double* X, int64_t x_ld, int64_
       const QrTask& q = t.lvl[l][i];
       ApplyTask a;
       std::memset(&a, 0, sizeof(a));
-      a.tile = q.tile;
+      a.tile = t.next ? t.ctile[l][i] : q.tile;   // a column block's compact tile: m x nf
       a.tau = q.tau;
       a.tmat = q.tmat;
       a.m = q.m;
-      a.ncol = q.ncol;
+      a.ncol = t.next ? (int32_t)t.nf : q.ncol;
       a.kq = (int32_t)std::min<int64_t>(q.m, N);
       a.nchild = q.nchild;
       a.kc0 = q.kc0;
@@ -609,9 +666,11 @@ tt_status launch_copies(tt_ctx* c, const std::vector<BlockCopy>& cp) {
   return e == hipSuccess ? TT_OK : hip_fail(c, e, "block copy");
 }
 
-// Factorisation of trees, column-blocked ones included: the tiles of every tree level
-// by level; for blocked trees the left-behind rows gathered, the trailing blocks factored
-// the same way, and R assembled from the first block's top rows and the trailing R.
+// Factorisation of trees, column-blocked ones included: the tiles of every tree level by
+// level; for blocked trees then the left-behind rows gathered, the block's rows of R copied
+// out and each tile's factored columns moved to its compact tile (the shared full-width
+// region is free after that), the trailing blocks factored the same way, and the trailing
+// R copied in where the trailing block is an ordinary tree (a blocked one wrote it in place).
 tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
   tt_status st = launch_levels_plain(c, trees);
   if (st != TT_OK) return st;
@@ -625,17 +684,26 @@ tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
   std::vector<BlockCopy> cp;
   for (Tree* t : blocked) {
     const std::vector<std::vector<int64_t>> off = rest_offsets(*t);
-    const int64_t nf = t->nf, wc = t->N - nf;
+    const int64_t nf = t->nf, N = t->N, wc = N - nf, ld = t->r_ld;
     for (size_t l = 0; l < t->lvl.size(); ++l) {
       const int tdt = l == 0 ? t->leaf_dtype : TT_F64;
       for (size_t i = 0; i < t->lvl[l].size(); ++i) {
         const QrTask& q = t->lvl[l][i];
         const int64_t k = std::min<int64_t>(q.m, nf);
-        if (q.m <= k) continue;
         BlockCopy b;
         std::memset(&b, 0, sizeof(b));
-        b.src = (const char*)q.tile + (size_t)(k * t->N + nf) * elt_size(tdt);
-        b.src_ld = t->N;
+        b.src = q.tile;   // the factored columns, kept for the application of Q
+        b.src_ld = N;
+        b.dst = t->ctile[l][i];
+        b.dst_ld = nf;
+        b.rows = q.m;
+        b.cols = (int32_t)nf;
+        b.src_f32 = b.dst_f32 = tdt == TT_F32;
+        cp.push_back(b);
+        if (q.m <= k) continue;
+        std::memset(&b, 0, sizeof(b));   // the left-behind rows of the carried columns
+        b.src = (const char*)q.tile + (size_t)(k * N + nf) * elt_size(tdt);
+        b.src_ld = N;
         b.dst = (char*)t->rest + (size_t)(off[l][i] * wc) * elt_size(t->leaf_dtype);
         b.dst_ld = wc;
         b.rows = (int32_t)(q.m - k);
@@ -645,36 +713,39 @@ tt_status launch_levels_factor(tt_ctx* c, std::vector<Tree*>& trees) {
         cp.push_back(b);
       }
     }
-  }
-  if ((st = launch_copies(c, cp)) != TT_OK) return st;
-  if ((st = launch_levels_factor(c, nexts)) != TT_OK) return st;
-  cp.clear();
-  for (Tree* t : blocked) {
     const QrTask& root = t->lvl.back()[0];
-    const int64_t nf = t->nf, N = t->N, k2 = t->next->kr();
+    const int64_t k2 = std::min(t->M, N) - nf;
     BlockCopy b;
     std::memset(&b, 0, sizeof(b));
     b.src = root.tile;   // rows 0..nf-1: [R_11 R_12]
     b.src_ld = N;
     b.src_f32 = t->lvl.size() == 1 && t->leaf_dtype == TT_F32;
     b.dst = t->rfull;
-    b.dst_ld = N;
+    b.dst_ld = ld;
     b.rows = (int32_t)nf;
     b.cols = (int32_t)N;
     b.tri = 1;
     cp.push_back(b);
     std::memset(&b, 0, sizeof(b));   // rows nf..kr-1, columns 0..nf-1: zero
-    b.dst = t->rfull + nf * N;
-    b.dst_ld = N;
+    b.dst = t->rfull + nf * ld;
+    b.dst_ld = ld;
     b.rows = (int32_t)k2;
     b.cols = (int32_t)nf;
     cp.push_back(b);
+  }
+  if ((st = launch_copies(c, cp)) != TT_OK) return st;
+  if ((st = launch_levels_factor(c, nexts)) != TT_OK) return st;
+  cp.clear();
+  for (Tree* t : blocked) {
+    if (t->next->next) continue;   // a blocked trailing block wrote its R in place
+    const int64_t nf = t->nf, N = t->N, ld = t->r_ld, k2 = t->next->kr();
+    BlockCopy b;
     std::memset(&b, 0, sizeof(b));   // rows nf..kr-1, columns nf..N-1: R of the trailing block
     b.src = t->next->root_R();
-    b.src_ld = t->next->N;
+    b.src_ld = t->next->rld();
     b.src_f32 = t->next->root_f32();
-    b.dst = t->rfull + nf * N + nf;
-    b.dst_ld = N;
+    b.dst = t->rfull + nf * ld + nf;
+    b.dst_ld = ld;
     b.rows = (int32_t)k2;
     b.cols = (int32_t)(N - nf);
     b.tri = 1;
@@ -1064,7 +1135,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
           g.part0 = (int32_t)gp.size();
           g.nparts = 1;
           g.B = tr.root_R();
-          g.b_ld = tr.N;
+          g.b_ld = tr.rld();
           g.b_f32 = tr.root_f32();
           g.C = (char*)js.Y[k - 1] + (size_t)(jb.roff[ci * D + (k - 1)] * jb.n[k - 1] * js.s[k]) * elt;
           g.c_ld = js.s[k];
@@ -1086,7 +1157,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
         g.part0 = (int32_t)gp.size();
         g.nparts = (int32_t)jb.comps.size();
         g.B = tr.root_R();
-        g.b_ld = tr.N;
+        g.b_ld = tr.rld();
         g.b_f32 = tr.root_f32();
         g.C = js.C;
         g.c_ld = js.s[1];
@@ -1270,7 +1341,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       std::memset(&t, 0, sizeof(t));
       const Tree& LR = js.lr[k & 1];
       t.R = LR.root_R();
-      t.r_ld = LR.N;
+      t.r_ld = LR.rld();
       t.r_f32 = LR.root_f32();
       t.kr = LR.kr();
       t.ncol = (int32_t)LR.N;
