@@ -68,6 +68,8 @@ def parse():
                    help="only the serving sweep (for profiler runs); prints its JSON object")
     p.add_argument("--order6-only", action="store_true",
                    help="only the order-6 experiment of the paper's workload (for profiler runs); prints its JSON object")
+    p.add_argument("--order6-complete", action="store_true",
+                   help="only the order-6 experiment with every scheme run to m = 35 (several minutes)")
     p.add_argument("--config2-only", action="store_true",
                    help="only the CGS2/Gram runs of the order-6, n=64 workload (for profiler runs); prints its JSON object")
     p.add_argument("--serving-qps", type=str, default="",
@@ -550,6 +552,9 @@ def cpu_baseline_randomized(seconds=5.0):
 PAPER_SCHEMES = ["cgs", "mgs", "cgs2", "mgs2", "gram", "householder"]
 O6_CASES = {"cgs": (35, 0), "mgs": (35, 2048), "cgs2": (35, 2048), "mgs2": (35, 2048), "gram": (35, 0),
             "householder": (20, 8192)}
+# every scheme to m = 35 (pre-round ranks up to about 16000; minutes per scheme)
+O6_COMPLETE = {"cgs": (35, 0), "mgs": (35, 32768), "cgs2": (35, 32768), "mgs2": (35, 32768), "gram": (35, 0),
+               "householder": (35, 32768)}
 PAPER_DESC = ("Section 4 order-3 experiment: m=20 Krylov TT-vectors of the Dirichlet Laplacian (d=3, n=15; ones, "
               "-Delta_d, rank-one rounding, normalisation) generated on the GPU, then each scheme at delta=1e-5, FP64")
 
@@ -588,16 +593,17 @@ def run_paper_experiment(tt, torch, delta=1e-5, reps=3):
     return out
 
 
-def run_order6(tt, torch, delta=1e-5):
+def run_order6(tt, torch, delta=1e-5, complete=False):
     """The order-6 experiment (n = 15, m = 35): each scheme up to a pre-round rank guard (the
-    completed prefix), beside the oracle's run of the same experiment (stored curves)."""
+    completed prefix), beside the oracle's run of the same experiment (stored curves);
+    complete=True runs every scheme to m = 35."""
     ns6, m6 = [15] * 6, 35
     A6 = tt.krylov_laplacian(ns6, m6)
     gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "order6_oracle.json")
     with open(gold) as f:
         ref6 = json.load(f)["schemes"]
     o6 = {}
-    for sch, (mm, guard) in O6_CASES.items():
+    for sch, (mm, guard) in (O6_COMPLETE if complete else O6_CASES).items():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
@@ -617,9 +623,14 @@ def run_order6(tt, torch, delta=1e-5):
                    "oracle_loo_at_m_reached": r["loo"][k - 1] if k else None,
                    "max_rank_q": max(max(q.r) for q in Q) if Q else None,
                    "oracle_max_rank_q_prefix": max(max(v) for v in r["q_ranks"][:k]) if k else None}
-    return {"workload": "d=6, n=15, m=35 Krylov TT-vectors, delta=1e-5, FP64; each scheme up to its "
-                        "pre-round rank guard (CGS none, MGS/CGS2/MGS2 2048, TT-Householder 8192 on the "
-                        "first 20 vectors); the oracle's values from its stored run of the same experiment",
+        if complete:
+            o6[sch]["loo"] = [float(v) for v in loo6]
+            progress(f"order-6 {sch}")
+    return {"workload": "d=6, n=15, m=35 Krylov TT-vectors, delta=1e-5, FP64; " +
+                        ("every scheme to m = 35 (rank guard 32768)" if complete else
+                         "each scheme up to its pre-round rank guard (CGS none, MGS/CGS2/MGS2 2048, "
+                         "TT-Householder 8192 on the first 20 vectors)") +
+                        "; the oracle's values from its stored run of the same experiment",
             "schemes": o6}
 
 
@@ -757,8 +768,8 @@ def main():
     if args.batched_only:
         print(json.dumps(run_batched(tt, torch)))
         return
-    if args.order6_only:
-        print(json.dumps(run_order6(tt, torch)))
+    if args.order6_only or args.order6_complete:
+        print(json.dumps(run_order6(tt, torch, complete=args.order6_complete)))
         return
     if args.config2_only:
         print(json.dumps(run_config2(tt, torch)))
