@@ -68,6 +68,9 @@ def parse():
                    help="only the serving sweep (for profiler runs); prints its JSON object")
     p.add_argument("--order6-only", action="store_true",
                    help="only the order-6 experiment of the paper's workload (for profiler runs); prints its JSON object")
+    p.add_argument("--config2-guard", type=int, default=0,
+                   help="with --config2-only: the pre-round rank guard (default 1024; above it each q output is "
+                        "capped at 512 MB)")
     p.add_argument("--order6-complete", action="store_true",
                    help="only the order-6 experiment with every scheme run to m = 35 (several minutes)")
     p.add_argument("--config2-only", action="store_true",
@@ -335,12 +338,19 @@ C2_DESC = ("CGS2 and TT-Gram on m=50 TT-vectors of order 6, n=64, generating ran
            "under a pre-round rank guard of 1024 (prefix up to the guard)")
 
 
-def run_config2(tt, torch, runs=(("gram", 1e-3), ("gram", 1e-5), ("gram", 1e-7), ("cgs2", 1e-5)), reps=1):
+def run_config2(tt, torch, runs=(("gram", 1e-3), ("gram", 1e-5), ("gram", 1e-7), ("cgs2", 1e-5)), reps=1,
+                guard=None, profile=True):
     """CGS2 and Gram on the 50 order-6 vectors under the rank guard (by default Gram at
     delta 1e-3/1e-5/1e-7 and CGS2 at 1e-5; --config2-all adds CGS2 at 1e-3 and 1e-7, whose
     guarded prefixes take several seconds per call): vectors reached, time per call and per
     step (profiler off), and the dominant kernel's roofline from a separate profiled call."""
-    w = C2
+    w = dict(C2)
+    if guard:
+        w["guard"] = int(guard)
+    # above a guard of 1024 the q outputs sized for the rank bounds (up to the guard at every
+    # middle bond) would exceed the GPU's memory: each q gets 128M elements (1 GB) instead
+    # (TT-Gram's outputs past the guard are never formed and the binding sizes them so)
+    qcap = (128 << 20) if w["guard"] > 1024 else None
     A, _, _, M = conditioned_dev(tt, torch, w["seed"], w["m"], w["d"], w["n"], w["r"], w["kappa"], torch.float64)
     ctx = tt._ctx()
     ctx.lib.tt_ctx_set_profiling.argtypes = [C.c_void_p, C.c_int]
@@ -353,23 +363,30 @@ def run_config2(tt, torch, runs=(("gram", 1e-3), ("gram", 1e-5), ("gram", 1e-7),
             t0 = time.perf_counter()
             for _ in range(reps):
                 Q, R, _, st = tt.orthogonalize(sch, A, delta, rank_guard=w["guard"], with_loo=False,
-                                               partial_on_guard=True)
+                                               partial_on_guard=True, q_capacity=None if sch == "gram" else qcap)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / reps
-            ctx.lib.tt_ctx_set_profiling(ctx.h, 1)
-            tt.orthogonalize(sch, A, delta, rank_guard=w["guard"], with_loo=False, partial_on_guard=True)
-            torch.cuda.synchronize()
-            prof = profile_arrays(ctx)
-            ctx.lib.tt_ctx_set_profiling(ctx.h, 0)
+            prof = {}
+            if profile:
+                ctx.lib.tt_ctx_set_profiling(ctx.h, 1)
+                tt.orthogonalize(sch, A, delta, rank_guard=w["guard"], with_loo=False, partial_on_guard=True,
+                                 q_capacity=None if sch == "gram" else qcap)
+                torch.cuda.synchronize()
+                prof = profile_arrays(ctx)
+                ctx.lib.tt_ctx_set_profiling(ctx.h, 0)
             k = st["m_reached"]
             loo = tt.loo(Q)[0] if k > 0 else []
             out[f"{sch}_{delta:.0e}"] = {
                 "m_reached": k, "ms_per_call": round(1e3 * dt, 3), "ms_per_step": round(1e3 * dt / max(k, 1), 3),
                 "rounds": st["rounds"], "max_pre_rank": st["max_pre_rank"], "max_post_rank": st["max_post_rank"],
                 "loo_at_m_reached": float(loo[-1]) if k > 0 else None,
-                "flops": sum(v["flops"] for v in prof.values()), "bytes": sum(v["bytes"] for v in prof.values()),
-                "roofline": roofline_of(prof, bulk_fp32=False)}
-    return {"workload": C2_DESC, "runs": out}
+                "flops": sum(v["flops"] for v in prof.values()) if prof else None,
+                "bytes": sum(v["bytes"] for v in prof.values()) if prof else None,
+                "roofline": roofline_of(prof, bulk_fp32=False) if prof else None}
+            if guard:
+                progress(f"config2 {sch} {delta:.0e} (m = {k} in {dt:.1f} s)")
+    desc = C2_DESC if w["guard"] == C2["guard"] else C2_DESC.replace(f"guard of {C2['guard']}", f"guard of {w['guard']}")
+    return {"workload": desc, "runs": out}
 
 
 def cpu_baseline_config2(m_prefix=8, delta=1e-5):
@@ -772,7 +789,10 @@ def main():
         print(json.dumps(run_order6(tt, torch, complete=args.order6_complete)))
         return
     if args.config2_only:
-        print(json.dumps(run_config2(tt, torch)))
+        kw = {"runs": [(a, b) for a in ("gram", "cgs2") for b in (1e-3, 1e-5, 1e-7)]} if args.config2_all else {}
+        if args.config2_guard:
+            kw.update(guard=args.config2_guard, profile=False)
+        print(json.dumps(run_config2(tt, torch, **kw)))
         return
     if args.serving_only:
         kw = {"qps_points": tuple(float(v) for v in args.serving_qps.split(","))} if args.serving_qps else {}

@@ -1263,7 +1263,7 @@ tt_status ortho_householder(tt_ctx* c, int m, const tt_sum* a, double delta, int
     if (rank_guard > 0 && pre > rank_guard)
       return fail(c, TT_EGUARD, "pre-round rank " + std::to_string(pre) + " of q exceeds the guard");
   }
-  if ((s = round_jobs(c, jobs)) != TT_OK) return s;
+  if ((s = round_jobs_grouped(c, jobs)) != TT_OK) return s;
   for (auto& jb : jobs) {
     if (jb.status != TT_OK) return fail(c, jb.status, "householder: output capacity of q");
     st.max_post_rank = (int32_t)std::max<int64_t>(st.max_post_rank, max_bond(jb.out->r, d));
@@ -1610,7 +1610,7 @@ tt_status tt_orthogonalize(tt_ctx* c, tt_scheme scheme, int32_t m, const tt_sum*
     }
     const bool guarded = (int)jobs.size() < m;
     if (!jobs.empty()) {
-      if ((s = round_jobs(c, jobs)) != TT_OK) return finish(s);
+      if ((s = round_jobs_grouped(c, jobs)) != TT_OK) return finish(s);
       for (auto& jb : jobs) {
         if (jb.status != TT_OK) return finish(fail(c, jb.status, "gram: output capacity"));
         st.max_post_rank = (int32_t)std::max<int64_t>(st.max_post_rank, max_bond(jb.out->r, d));

@@ -907,6 +907,38 @@ tt_status tune_tree(tt_ctx* c, int64_t M, int64_t N, int dtype, TreeShape* best_
   return TT_OK;
 }
 
+tt_status round_jobs_grouped(tt_ctx* c, std::vector<RJob>& jobs) {
+  if (jobs.size() <= 1) return round_jobs(c, jobs);
+  std::vector<int64_t> need(jobs.size());
+  int64_t big = 0;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    std::vector<RJob> one(1, jobs[i]);
+    need[i] = std::max<int64_t>(round_workspace_bytes(one), 0);
+    big = std::max(big, need[i]);
+  }
+  const int64_t lim = std::max<int64_t>(big, (int64_t)1 << 30);
+  if (c->ws_off + (size_t)big > c->ws_bytes) {   // report the largest group's need at once
+    c->required = std::max(c->required, c->ws_off + (size_t)std::min<int64_t>(lim, [&] {
+      int64_t t = 0;
+      for (int64_t v : need) t += v;
+      return t;
+    }()));
+    return fail(c, TT_ECAPACITY, "workspace too small for the batched roundings: need " + std::to_string(c->required));
+  }
+  size_t i0 = 0;
+  while (i0 < jobs.size()) {
+    size_t i1 = i0;
+    int64_t sum = 0;
+    while (i1 < jobs.size() && (i1 == i0 || sum + need[i1] <= lim)) sum += need[i1++];
+    std::vector<RJob> grp(jobs.begin() + i0, jobs.begin() + i1);
+    const tt_status s = round_jobs(c, grp);
+    if (s != TT_OK) return s;
+    for (size_t k = i0; k < i1; ++k) jobs[k].status = grp[k - i0].status;
+    i0 = i1;
+  }
+  return TT_OK;
+}
+
 int64_t round_workspace_bytes(const std::vector<RJob>& jobs) {
   tt_ctx tmp;
   tmp.ws = nullptr;

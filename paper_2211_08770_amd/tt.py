@@ -596,6 +596,14 @@ def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: b
     ra = [[sum(t.r[k] for t in h.tts) for k in range(d + 1)] for h in hs]
     bounds = q_rank_bounds(scheme, ra, first.n, rank_guard)
     sizes = [sum(b[k] * first.n[k] * b[k + 1] for k in range(d)) for b in bounds]
+    if scheme == "gram" and rank_guard > 0:
+        # TT-Gram rounds q_i from the sum of a_1..a_i: its pre-round rank is known here, and a
+        # q_i past the guard is never formed (one element of output is enough for it)
+        run = [0] * (d + 1)
+        for i, r in enumerate(ra):
+            run = [x + y for x, y in zip(run, r)]
+            if max(run[1:d]) > rank_guard:
+                sizes[i] = 1
     if q_capacity is not None:
         sizes = [min(sz, int(q_capacity)) for sz in sizes]
     Q = [TT(torch.empty(max(sz, 1), dtype=first.dtype, device=first.data.device), first.n, [1] * (d + 1))
