@@ -252,8 +252,8 @@ struct RoundMode {
 tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode = RoundMode());
 int64_t round_workspace_bytes(const std::vector<RJob>& jobs);
 // round_jobs on consecutive groups of the jobs whose workspaces together stay within the
-// largest single job's (or 1 GiB): one batch for small jobs, memory bounded by the largest
-// job for large ones (the schemes' batched final roundings)
+// largest single job's (or 32 GiB): one batch for moderate jobs, memory bounded by the
+// largest job for large ones (the schemes' batched final roundings)
 tt_status round_jobs_grouped(tt_ctx* c, std::vector<RJob>& jobs);
 // FP32-bulk noise floor of the per-bond threshold, relative to ||x||, for a
 // merged core with s columns: 2 sqrt(s) u_32 (the level below which the SVD

@@ -916,7 +916,7 @@ tt_status round_jobs_grouped(tt_ctx* c, std::vector<RJob>& jobs) {
     need[i] = std::max<int64_t>(round_workspace_bytes(one), 0);
     big = std::max(big, need[i]);
   }
-  const int64_t lim = std::max<int64_t>(big, (int64_t)1 << 30);
+  const int64_t lim = std::max<int64_t>(big, (int64_t)32 << 30);
   if (c->ws_off + (size_t)big > c->ws_bytes) {   // report the largest group's need at once
     c->required = std::max(c->required, c->ws_off + (size_t)std::min<int64_t>(lim, [&] {
       int64_t t = 0;
