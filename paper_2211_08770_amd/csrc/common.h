@@ -177,7 +177,8 @@ hipError_t launch_qr_update(int dtype_tile, const ApplyTask* d_tasks, int ntasks
                             hipStream_t s);
 hipError_t launch_svd(const SvdTask* d_tasks, int ntasks, hipStream_t s);
 // The tasks with the block flag (the others are skipped): block Jacobi, several launches;
-// max_kr bounds kr over the flagged tasks.
+// max_kr bounds kr over the flagged tasks.  Every sweep's rounds are launched (sized by
+// max_kr; the rounds of a converged task return at once), so nothing waits for the host.
 hipError_t launch_svd_big(const SvdTask* d_tasks, int ntasks, int max_kr, hipStream_t s);
 hipError_t launch_gemm(int dtype, const GemmTask* d_tasks, const GemmPart* d_parts, int ntasks,
                        int max_m, int max_n, hipStream_t s);

@@ -1410,9 +1410,9 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       if (t.block) max_kr = std::max(max_kr, (int)t.kr);
     const int spr = prof_begin(c, PK_SVD, sfl, sby);
     e = launch_svd(dsv, (int)sv.size(), s);
-    if (e == hipSuccess && max_kr > 0) e = launch_svd_big(dsv, (int)sv.size(), max_kr, s);
-    prof_end(c, spr);
     if (e != hipSuccess) return hip_fail(c, e, "svd");
+    if (max_kr > 0 && (e = launch_svd_big(dsv, (int)sv.size(), max_kr, s)) != hipSuccess) return hip_fail(c, e, "svd");
+    prof_end(c, spr);
     if (!bp && (e = hipMemcpyAsync(h_ranks, d_ranks, (size_t)nj * (TT_MAXD + 1) * 4, hipMemcpyDeviceToHost, s)) !=
                    hipSuccess)
       return hip_fail(c, e, "rank readback");
