@@ -48,3 +48,18 @@ def test_blocked_workspace_grows_with_rank():
 
 def test_fp32_bulk_needs_less_workspace():
     assert 0 < ws_bytes([32] * 4, 10, 50, 1) < ws_bytes([32] * 4, 10, 50, 0)
+
+
+def test_column_blocks_keep_only_factored_columns():
+    # 100 components of rank 20 on order 6, n = 15: right-to-left unfoldings up to 30000 x 2000
+    # in FP64.  Full-width tiles for every column block would take about M N^2 / 384 elements
+    # per tree (about 10 GiB for the 30000 x 2000 one alone); with the blocks sharing one
+    # full-width region and keeping only their factored columns the whole rounding's workspace
+    # stays below 12 GiB.
+    assert 0 < ws_bytes([15] * 6, 20, 100) < 12 * 2**30
+
+
+def test_wide_svd_limit_applies_at_planning_time_only_for_bounds():
+    # The left-to-right R factors of this sum have up to 2000 rows (above the 1024-row
+    # one-workgroup kernel, below the 4096 of the block Jacobi): host planning accepts it
+    assert ws_bytes([15] * 6, 20, 100) > 0
