@@ -159,7 +159,9 @@ tt_status tt_norm(tt_ctx* ctx, const tt_sum* x, double* out);
  * discarded tail is <= the threshold (and <= max_rank when max_rank > 0).
  * Cores 0..d-2 of the result are left-orthonormal.  d = 1 copies; a zero
  * tensor yields all ranks 1 (unit-vector cores 0..d-2, zero last core).  out->r is written; norm_x (HOST, nullable)
- * receives ||x||. */
+ * receives ||x||.  Unfoldings of any width are factored (in column blocks of 384 when
+ * they have more than 800 rows and 400 columns); a left-to-right R factor of more than
+ * 4096 rows gives TT_ENOTIMPL. */
 tt_status tt_round(tt_ctx* ctx, const tt_sum* x, double delta, int64_t max_rank, tt_vec* out,
                    double* norm_x);
 
@@ -184,7 +186,9 @@ tt_status tt_round_batched(tt_ctx* ctx, int32_t njobs, const tt_sum* xs, const d
  * stream: read them, and outs[j].data, after synchronising that stream.  outs[j].r
  * is not written.  The workspace and the inputs must stay untouched until then;
  * the next call on the context waits for this one.  Argument errors are returned
- * before anything is enqueued; the per-launch profiler must be off. */
+ * before anything is enqueued; the per-launch profiler must be off.  Planned at the
+ * bounds, every left-to-right R factor must have at most 1024 rows at its bound
+ * (TT_ENOTIMPL for the call otherwise: use tt_round_batched). */
 tt_status tt_round_batched_async(tt_ctx* ctx, int32_t njobs, const tt_sum* xs, const double* deltas,
                                  const int64_t* max_ranks, tt_vec* outs, int32_t* ranks, int32_t* job_status,
                                  double* norms);
