@@ -52,7 +52,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
-    p.add_argument("--serving-requests", type=int, default=120, help="requests per offered-rate point of the serving sweep")
+    p.add_argument("--serving-requests", type=int, default=80, help="requests per offered-rate point of the serving sweep")
     p.add_argument("--config2-all", action="store_true", help="CGS2 and Gram at all three deltas of the order-6 workload")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 256 MiB device-to-device copy (reference for the HBM byte counters)")
@@ -76,7 +76,7 @@ def parse():
     p.add_argument("--config2-only", action="store_true",
                    help="only the CGS2/Gram runs of the order-6, n=64 workload (for profiler runs); prints its JSON object")
     p.add_argument("--serving-qps", type=str, default="",
-                   help="comma-separated offered rates of the serving sweep (default 25,50,100,200)")
+                   help="comma-separated offered rates of the serving sweep (default 3,6,9,15)")
     return p.parse_args()
 
 
@@ -678,7 +678,7 @@ SERVE_DESC = ("64 solvers, d~U{5..8}, n~U{32,64,128}, solver rank~U{4..32}, basi
               "MGS2 FP32-bulk, delta=1e-6, 8 GiB admission budget")
 
 
-def run_serving(torch, qps_points=(25.0, 50.0, 100.0, 200.0), nreq=500, keep_sample=0):
+def run_serving(torch, qps_points=(3.0, 6.0, 9.0, 15.0), nreq=500, keep_sample=0):
     """Poisson serving traces at several offered rates: MGS2 steps of 64 simulated TT-GMRES solvers
     against resident bases.  Per point: p50/p99 latency, throughput, engine steps; the saturation
     rate is the largest completed throughput.  keep_sample > 0 keeps that many finished requests
