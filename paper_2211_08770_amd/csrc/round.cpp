@@ -933,7 +933,10 @@ tt_status round_jobs_grouped(tt_ctx* c, std::vector<RJob>& jobs) {
     std::vector<RJob> grp(jobs.begin() + i0, jobs.begin() + i1);
     const tt_status s = round_jobs(c, grp);
     if (s != TT_OK) return s;
-    for (size_t k = i0; k < i1; ++k) jobs[k].status = grp[k - i0].status;
+    for (size_t k = i0; k < i1; ++k) {   // what round_jobs reports back in a job
+      jobs[k].status = grp[k - i0].status;
+      jobs[k].norm = grp[k - i0].norm;
+    }
     i0 = i1;
   }
   return TT_OK;

@@ -875,7 +875,9 @@ __global__ __launch_bounds__(NT) void k_bsvd_round(const SvdTask* __restrict__ t
       }
       __syncthreads();
     }
-    if (!inner_rot) break;
+    const int any = inner_rot;
+    __syncthreads();   // every wave has read the flag before thread 0 clears it for the next sweep
+    if (!any) break;
   }
   // ---- the pair's columns of A and of J rotated by V
   rotate_rows(tk.A, N, N, cidx, V, Ch);
