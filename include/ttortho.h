@@ -12,7 +12,9 @@
  * Conventions shared by every entry point
  *   - Tensor data are DEVICE pointers on the context's device; every call is
  *     ordered on the context's HIP stream and returns after that stream has
- *     completed the call's work (so host-side outputs are valid on return).
+ *     completed the call's work (so host-side outputs are valid on return),
+ *     except tt_round_batched_async and tt_dot_noalloc, which return once
+ *     their work is enqueued (their declarations say when results are valid).
  *   - A TT-vector of order d stores core k (k = 0..d-1) row-major as
  *     [r_k][n_k][r_{k+1}] at element offset sum_{j<k} r_j n_j r_{j+1};
  *     r_0 = r_d = 1.  Its left unfolding ((r_k n_k) x r_{k+1}) and its right
