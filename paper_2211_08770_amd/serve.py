@@ -48,9 +48,9 @@ class Solver:
         g[:b, :b] = self.gram
         g[b, :b] = g[:b, b] = gram_row
         g[b, b] = 1.0
-        # the result buffer is sized for the rank bounds; the basis keeps only the result's
-        # packed cores (a long trace would otherwise fill the device with bound-sized buffers)
-        self.basis.append(tt.TT(q.data[: q.size()].clone(), q.n, q.r))
+        # (a result far below its rank bounds owns a packed buffer: a long trace does not
+        # fill the device with bound-sized buffers)
+        self.basis.append(q)
         self.gram = g
 
 

@@ -388,9 +388,18 @@ def _new_out(x):
     return TT(torch.empty(cap, dtype=first.dtype, device=first.data.device), first.n, [1] * (first.d + 1))
 
 
+def _packed(data: torch.Tensor, size: int) -> torch.Tensor:
+    """The first `size` elements of an output buffer.  Output buffers are sized for the rank
+    bounds; when the result is far smaller, it gets a buffer of its own so that keeping the
+    result does not keep the bound-sized buffer alive."""
+    if data.numel() > 2 * size + (1 << 16):
+        return data[:size].clone()
+    return data[:size]
+
+
 def _finish_out(out: TT, v: _Vec):
     out.r = [int(v.r[k]) for k in range(out.d + 1)]
-    out.data = out.data[: out.size()]
+    out.data = _packed(out.data, out.size())
     return out
 
 
@@ -498,7 +507,7 @@ def _round_batched_bounds(xs, deltas, max_ranks=None):
         if st[j] != 0:
             raise TTError(st[j], f"job {j} failed")
         o.r = [int(v) for v in rk[j][: o.d + 1]]
-        o.data = o.data[: o.size()]
+        o.data = _packed(o.data, o.size())
     return outs
 
 
@@ -753,7 +762,7 @@ class Engine:
             q, qv, scratch, r, g, b, want_gram, keep, req = self.inflight.pop(ids[k])
             if sts[k] == 0:
                 q.r = [int(qv.r[i]) for i in range(q.d + 1)]
-                q.data = q.data[: q.size()]
+                q.data = _packed(q.data, q.size())
             out[ids[k]] = (_STATUS.get(sts[k], sts[k]), q, np.array(r[: b + 1]),
                            np.array(g[:b]) if want_gram else None)
         return out
