@@ -53,7 +53,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--serving-requests", type=int, default=80, help="requests per offered-rate point of the serving sweep")
-    p.add_argument("--config2-all", action="store_true", help="CGS2 and Gram at all three deltas of the order-6 workload")
+    p.add_argument("--order6-n64-all", action="store_true", help="CGS2 and Gram at all three deltas of the 50-vector order-6, n=64 workload")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only run a plain 256 MiB device-to-device copy (reference for the HBM byte counters)")
     p.add_argument("--headline-only", action="store_true",
@@ -68,12 +68,12 @@ def parse():
                    help="only the serving sweep (for profiler runs); prints its JSON object")
     p.add_argument("--order6-only", action="store_true",
                    help="only the order-6 experiment of the paper's workload (for profiler runs); prints its JSON object")
-    p.add_argument("--config2-guard", type=int, default=0,
-                   help="with --config2-only: the pre-round rank guard (default 1024; above it each q output is "
-                        "capped at 512 MB)")
+    p.add_argument("--order6-n64-guard", type=int, default=0,
+                   help="with --order6-n64-only: the pre-round rank guard (default 1024; above it each non-Gram q "
+                        "output is capped at 128M elements, 1 GB in FP64)")
     p.add_argument("--order6-complete", action="store_true",
                    help="only the order-6 experiment with every scheme run to m = 35 (several minutes)")
-    p.add_argument("--config2-only", action="store_true",
+    p.add_argument("--order6-n64-only", action="store_true",
                    help="only the CGS2/Gram runs of the order-6, n=64 workload (for profiler runs); prints its JSON object")
     p.add_argument("--serving-qps", type=str, default="",
                    help="comma-separated offered rates of the serving sweep (default 3,6,9,15)")
@@ -296,14 +296,14 @@ def oracle_conditioned(seed, m, d, n, r, kappa):
     return [[(float(cm[k, j]), [c.copy() for c in t[j]]) for j in range(k + 1)] for k in range(m)], M
 
 
-C0 = dict(seed=10000, m=20, d=4, n=8, r=3, kappa=1e6, delta=1e-6)
-C0_DESC = ("TT-MGS (Algorithm 2) of m=20 TT-vectors x_k = sum_{j<=k} c_kj t_j (private copies), t_j random rank-3 "
+MGS20 = dict(seed=10000, m=20, d=4, n=8, r=3, kappa=1e6, delta=1e-6)
+MGS20_DESC = ("TT-MGS (Algorithm 2) of m=20 TT-vectors x_k = sum_{j<=k} c_kj t_j (private copies), t_j random rank-3 "
            "TTs of order 4, n=8, cond(Gram(x)) = 1e6, delta=1e-6, FP64")
 
 
-def run_config0(tt, torch, reps=5):
+def run_mgs_m20_order4(tt, torch, reps=5):
     """The 20-vector MGS workload: per-step LOO, kappa(A_k) (tt_cond), pre/post ranks, time per call."""
-    w = C0
+    w = MGS20
     A, _, _, M = conditioned_dev(tt, torch, w["seed"], w["m"], w["d"], w["n"], w["r"], w["kappa"], torch.float64)
     Q, R, loo, st = tt.orthogonalize("mgs", A, w["delta"])
     kap, _ = tt.cond(A)
@@ -315,13 +315,13 @@ def run_config0(tt, torch, reps=5):
     dt = (time.perf_counter() - t0) / reps
     return {"ms_per_call": round(1e3 * dt, 3), "rounds": st["rounds"], "loo": [float(v) for v in loo],
             "kappa": [float(v) for v in kap], "max_pre_rank": st["max_pre_rank"],
-            "max_post_rank": st["max_post_rank"], "q_ranks": [max(q.r) for q in Q], "workload": C0_DESC}
+            "max_post_rank": st["max_post_rank"], "q_ranks": [max(q.r) for q in Q], "workload": MGS20_DESC}
 
 
-def cpu_baseline_config0(seconds=4.0):
+def cpu_baseline_mgs_m20_order4(seconds=4.0):
     """The oracle's MGS on the same workload, end to end, at all BLAS threads and at one."""
     import oracle
-    w = C0
+    w = MGS20
     X, M = oracle_conditioned(w["seed"], w["m"], w["d"], w["n"], w["r"], w["kappa"])
     out = {}
     for label, th in (("all", None), ("1", 1)):
@@ -333,18 +333,18 @@ def cpu_baseline_config0(seconds=4.0):
             "sample": f"FP64 NumPy/LAPACK MGS calls on the same workload (about {seconds:.0f} s per thread setting)"}
 
 
-C2 = dict(seed=20000, m=50, d=6, n=64, r=8, kappa=1e10, guard=1024)
-C2_DESC = ("CGS2 and TT-Gram on m=50 TT-vectors of order 6, n=64, generating ranks 8, cond(Gram(x)) = 1e10, FP64, "
+ORDER6_N64 = dict(seed=20000, m=50, d=6, n=64, r=8, kappa=1e10, guard=1024)
+ORDER6_N64_DESC = ("CGS2 and TT-Gram on m=50 TT-vectors of order 6, n=64, generating ranks 8, cond(Gram(x)) = 1e10, FP64, "
            "under a pre-round rank guard of 1024 (prefix up to the guard)")
 
 
-def run_config2(tt, torch, runs=(("gram", 1e-3), ("gram", 1e-5), ("gram", 1e-7), ("cgs2", 1e-5)), reps=1,
+def run_cgs2_gram_m50_order6(tt, torch, runs=(("gram", 1e-3), ("gram", 1e-5), ("gram", 1e-7), ("cgs2", 1e-5)), reps=1,
                 guard=None, profile=True):
     """CGS2 and Gram on the 50 order-6 vectors under the rank guard (by default Gram at
-    delta 1e-3/1e-5/1e-7 and CGS2 at 1e-5; --config2-all adds CGS2 at 1e-3 and 1e-7, whose
+    delta 1e-3/1e-5/1e-7 and CGS2 at 1e-5; --order6-n64-all adds CGS2 at 1e-3 and 1e-7, whose
     guarded prefixes take several seconds per call): vectors reached, time per call and per
     step (profiler off), and the dominant kernel's roofline from a separate profiled call."""
-    w = dict(C2)
+    w = dict(ORDER6_N64)
     if guard:
         w["guard"] = int(guard)
     # above a guard of 1024 the q outputs sized for the rank bounds (up to the guard at every
@@ -384,15 +384,15 @@ def run_config2(tt, torch, runs=(("gram", 1e-3), ("gram", 1e-5), ("gram", 1e-7),
                 "bytes": sum(v["bytes"] for v in prof.values()) if prof else None,
                 "roofline": roofline_of(prof, bulk_fp32=False) if prof else None}
             if guard:
-                progress(f"config2 {sch} {delta:.0e} (m = {k} in {dt:.1f} s)")
-    desc = C2_DESC if w["guard"] == C2["guard"] else C2_DESC.replace(f"guard of {C2['guard']}", f"guard of {w['guard']}")
+                progress(f"order-6 n=64 {sch} {delta:.0e} (m = {k} in {dt:.1f} s)")
+    desc = ORDER6_N64_DESC if w["guard"] == ORDER6_N64["guard"] else ORDER6_N64_DESC.replace(f"guard of {ORDER6_N64['guard']}", f"guard of {w['guard']}")
     return {"workload": desc, "runs": out}
 
 
-def cpu_baseline_config2(m_prefix=8, delta=1e-5):
+def cpu_baseline_cgs2_m50_order6(m_prefix=8, delta=1e-5):
     """The oracle's CGS2 on the first m_prefix vectors of the same workload: time per step."""
     import oracle
-    w = C2
+    w = ORDER6_N64
     X, M = oracle_conditioned(w["seed"], w["m"], w["d"], w["n"], w["r"], w["kappa"])
     t0 = time.perf_counter()
     res = oracle.cgs2(X[:m_prefix], delta)
@@ -788,11 +788,11 @@ def main():
     if args.order6_only or args.order6_complete:
         print(json.dumps(run_order6(tt, torch, complete=args.order6_complete)))
         return
-    if args.config2_only:
-        kw = {"runs": [(a, b) for a in ("gram", "cgs2") for b in (1e-3, 1e-5, 1e-7)]} if args.config2_all else {}
-        if args.config2_guard:
-            kw.update(guard=args.config2_guard, profile=False)
-        print(json.dumps(run_config2(tt, torch, **kw)))
+    if args.order6_n64_only:
+        kw = {"runs": [(a, b) for a in ("gram", "cgs2") for b in (1e-3, 1e-5, 1e-7)]} if args.order6_n64_all else {}
+        if args.order6_n64_guard:
+            kw.update(guard=args.order6_n64_guard, profile=False)
+        print(json.dumps(run_cgs2_gram_m50_order6(tt, torch, **kw)))
         return
     if args.serving_only:
         kw = {"qps_points": tuple(float(v) for v in args.serving_qps.split(","))} if args.serving_qps else {}
@@ -844,12 +844,12 @@ def main():
     if not args.headline_only:
         line["batched_uneven"] = run_batched(tt, torch)
         progress("batched_uneven")
-        line["config0_mgs"] = run_config0(tt, torch)
-        progress("config0_mgs")
-        line["config2_guarded"] = run_config2(tt, torch, **({"runs": [(a, b) for a in ("gram", "cgs2")
+        line["mgs_m20_order4"] = run_mgs_m20_order4(tt, torch)
+        progress("mgs_m20_order4")
+        line["cgs2_gram_m50_order6_guarded"] = run_cgs2_gram_m50_order6(tt, torch, **({"runs": [(a, b) for a in ("gram", "cgs2")
                                                                          for b in (1e-3, 1e-5, 1e-7)]}
-                                                              if args.config2_all else {}))
-        progress("config2_guarded")
+                                                              if args.order6_n64_all else {}))
+        progress("cgs2_gram_m50_order6_guarded")
         line["serving"] = run_serving(torch, nreq=args.serving_requests, keep_sample=0 if args.no_cpu else 2)
         sample = line["serving"].pop("_sample")
         progress("serving sweep")
@@ -869,10 +869,10 @@ def main():
         progress("oracle_check")
         line["batched_uneven"]["cpu_baseline"] = cpu_baseline_batched()
         progress("batched_uneven cpu_baseline")
-        line["config0_mgs"]["cpu_baseline"] = cpu_baseline_config0()
-        progress("config0_mgs cpu_baseline")
-        line["config2_guarded"]["cpu_baseline"] = cpu_baseline_config2()
-        progress("config2_guarded cpu_baseline")
+        line["mgs_m20_order4"]["cpu_baseline"] = cpu_baseline_mgs_m20_order4()
+        progress("mgs_m20_order4 cpu_baseline")
+        line["cgs2_gram_m50_order6_guarded"]["cpu_baseline"] = cpu_baseline_cgs2_m50_order6()
+        progress("cgs2_gram_m50_order6_guarded cpu_baseline")
         line["serving"]["oracle_check"] = cpu_check_serving(sample)
         progress("serving oracle_check")
         line["householder"]["cpu_baseline"] = cpu_baseline_householder()

@@ -132,7 +132,7 @@ def test_loo_entry_point_matches_oracle():
     assert np.allclose(loo, oracle.loo_curve(ref.Q), rtol=1e-8, atol=1e-14)
 
 
-def _config2_inputs():
+def _order6_n64_inputs():
     # m = 50 TT-vectors of order 6, n = 64, generating ranks 8, cond(Gram) = 1e10
     return conditioned_inputs(20000, 50, 6, 64, 8, 1e10)
 
@@ -140,7 +140,7 @@ def _config2_inputs():
 def test_gram_fp32_dots_report_singular_gram_at_condition_1e10():
     """With FP32 dots the Gram matrix at cond 1e10 is numerically singular: reported, never hidden."""
     tt = need_gpu()
-    X, C, M = _config2_inputs()
+    X, C, M = _order6_n64_inputs()
     A = [dev_sum([(a, [c.astype(np.float32) for c in x]) for a, x in s], torch.float32) for s in X]
     with pytest.raises(tt.TTError) as ei:
         tt.orthogonalize("gram", A, 1e-5, rank_guard=384)
@@ -148,11 +148,11 @@ def test_gram_fp32_dots_report_singular_gram_at_condition_1e10():
 
 
 @pytest.mark.parametrize("scheme,delta", [("gram", 1e-3), ("gram", 1e-7), ("cgs2", 1e-5)])
-def test_config2_fp64_prefix_under_rank_guard(scheme, delta):
+def test_order6_n64_fp64_prefix_under_rank_guard(scheme, delta):
     """FP64 CGS2 / Gram on 50 vectors: the run stops at the rank guard with TT_EGUARD and
     the completed prefix equals the oracle run on that prefix (step i only uses vectors <= i)."""
     tt = need_gpu()
-    X, C, M = _config2_inputs()
+    X, C, M = _order6_n64_inputs()
     A = [dev_sum(s) for s in X]
     guard = 384
     Q, R, _, st = tt.orthogonalize(scheme, A, delta, rank_guard=guard, with_loo=False, partial_on_guard=True)
@@ -169,7 +169,7 @@ def test_config2_fp64_prefix_under_rank_guard(scheme, delta):
 
 
 @pytest.mark.parametrize("delta", [1e-3, 1e-5, 1e-7])
-def test_config2_cgs2_fp32_bulk_prefix_under_rank_guard(delta):
+def test_order6_n64_cgs2_fp32_bulk_prefix_under_rank_guard(delta):
     """FP32-bulk CGS2 on the 50 order-6 vectors (cond(Gram) = 1e10) stored in FP32, under
     the rank guard: every completed step against the oracle on the same values upcast,
     within max(delta, 1e-5) kappa(A_k)."""
