@@ -1,0 +1,112 @@
+"""Host-only queries of the C ABI, without a GPU.
+
+* tt_round_out_capacity: the output buffer it sizes must hold every rounding of the sum.
+  Checked against the oracle's rounding at delta = 0, which keeps every nonzero singular
+  value (Section 2; reading 4), on random lazy sums of several orders, mode sizes and
+  ranks, including ranks above what the mode sizes allow.  Where every bond's bound is
+  reachable by generic data, the capacity is exactly the oracle's output size.
+* tt_round_effective_delta: delta itself in FP64 and for order one; in FP32-bulk at least
+  delta, and at delta = 0 the FP32 resolution of the merged cores, which grows as the square
+  root of the number of bonds and of the widest merged core (the per-bond threshold
+  2 sqrt(s) u_32 ||x|| summed over d - 1 bonds).
+
+Descriptors only: the data pointers are never dereferenced.
+"""
+import ctypes as C
+import math
+
+import pytest
+
+import oracle
+from paper_2211_08770_amd import synth, tt
+
+
+def descriptors(ns, rank_lists, dtype=0):
+    """A lazy sum of components with the given bond ranks (no device data)."""
+    d = len(ns)
+    vecs = (tt._Vec * len(rank_lists))()
+    for v, ranks in zip(vecs, rank_lists):
+        v.d, v.dtype = d, dtype
+        for k in range(d):
+            v.n[k] = ns[k]
+        for k in range(d + 1):
+            v.r[k] = ranks[k]
+        v.data = 4096   # never read by the host queries
+        v.capacity = sum(ranks[k] * ns[k] * ranks[k + 1] for k in range(d))
+    coef = (C.c_double * len(rank_lists))(*[1.0] * len(rank_lists))
+    return tt._Sum(len(rank_lists), coef, vecs), (vecs, coef)
+
+
+def lib():
+    L = tt._load()
+    L.tt_round_out_capacity.argtypes = [C.POINTER(tt._Sum)]
+    L.tt_round_out_capacity.restype = C.c_int64
+    L.tt_round_effective_delta.argtypes = [C.POINTER(tt._Sum), C.c_double]
+    L.tt_round_effective_delta.restype = C.c_double
+    return L
+
+
+CASES = [
+    ((7,), [[1, 1]]),
+    ((3, 4), [[1, 2, 1], [1, 3, 1]]),                       # summed rank 5 above the cap 3
+    ((2, 3, 2), [[1, 2, 2, 1]] * 3),                        # ranks 6 above the caps 2
+    ((4, 4, 4, 4), [[1, 2, 3, 2, 1], [1, 1, 2, 1, 1]]),      # below every cap
+    ((5, 2, 5), [[1, 3, 3, 1], [1, 4, 4, 1]]),              # 7 above both caps (5)
+    ((3, 3, 3, 3, 3), [[1, 2, 2, 2, 2, 1]] * 4),            # 8 above the caps 3 and 9 in the middle
+    ((6, 2, 6, 2), [[1, 1, 2, 2, 1], [1, 2, 1, 1, 1]]),
+    ((4, 2, 4, 4), [[1, 1, 4, 4, 1]] * 2),                  # bond 2 bound 8 unreachable (2 x 2 = 4 feed it)
+]
+
+
+@pytest.mark.parametrize("ns,rank_lists", CASES)
+def test_out_capacity_holds_the_oracle_rounding(ns, rank_lists):
+    g = synth.rng(61000 + sum(ns) + len(rank_lists))
+    terms = [(float(g.standard_normal()), synth.random_tt(g, list(ns), r)) for r in rank_lists]
+    out = oracle.tt_round(oracle.tt_sum(terms), 0.0)
+    size = sum(c.size for c in out)
+    s, keep = descriptors(ns, rank_lists)
+    cap = lib().tt_round_out_capacity(C.byref(s))
+    assert cap >= size
+    # generic data reach each bond's bound min(R_k, left modes, right modes) when the ranks on
+    # both sides of every core allow it (R_{k-1} n_k >= R_k and n_k R_{k+1} >= R_k after capping)
+    d = len(ns)
+    R = [1] + [sum(r[k] for r in rank_lists) for k in range(1, d)] + [1]
+    b = [min(R[k], math.prod(ns[:k]), math.prod(ns[k:])) for k in range(d + 1)]
+    if all(b[k - 1] * ns[k - 1] >= b[k] and ns[k] * b[k + 1] >= b[k] for k in range(1, d)):
+        assert cap == size, (cap, size, [c.shape for c in out])
+
+
+def test_out_capacity_rejects_bad_arguments():
+    assert lib().tt_round_out_capacity(None) == -1
+
+
+def test_effective_delta_fp64_and_order_one_is_delta():
+    L = lib()
+    for delta in (0.0, 1e-12, 1e-6, 0.3):
+        s, keep = descriptors((8, 8, 8), [[1, 4, 4, 1]] * 3, dtype=0)
+        assert L.tt_round_effective_delta(C.byref(s), delta) == delta
+        s1, keep1 = descriptors((50,), [[1, 1]], dtype=1)
+        assert L.tt_round_effective_delta(C.byref(s1), delta) == delta
+    s, keep = descriptors((8, 8, 8), [[1, 4, 4, 1]], dtype=0)
+    assert L.tt_round_effective_delta(C.byref(s), -1.0) < 0
+
+
+def test_effective_delta_fp32_resolution():
+    L = lib()
+    u32 = 2.0 ** -24
+
+    def eff(ns, rank_lists, delta):
+        s, keep = descriptors(ns, rank_lists, dtype=1)
+        return L.tt_round_effective_delta(C.byref(s), delta)
+
+    base = eff((32,) * 4, [[1, 10, 10, 10, 1]] * 2, 0.0)       # widest merged core: 20 columns, 3 bonds
+    assert base > 0
+    assert eff((32,) * 4, [[1, 10, 10, 10, 1]] * 8, 0.0) == pytest.approx(2 * base)     # 80 columns: x sqrt(4)
+    assert eff((32,) * 6, [[1] + [10] * 5 + [1]] * 2, 0.0) == pytest.approx(base * math.sqrt(5 / 3))
+    assert base == pytest.approx(math.sqrt(3) * 2 * math.sqrt(20) * u32)
+    # capped by the mode sizes: rank 50 summed over n = 4 modes of order 3 -> widest core 4 columns
+    assert eff((4, 4, 4), [[1, 25, 25, 1]] * 2, 0.0) == pytest.approx(math.sqrt(2) * 2 * math.sqrt(4) * u32)
+    # the resolution never lowers a larger delta
+    for delta in (1e-8, 1e-5, 1e-2):
+        e = eff((32,) * 4, [[1, 10, 10, 10, 1]] * 2, delta)
+        assert e == max(delta, base)
