@@ -110,3 +110,60 @@ def test_effective_delta_fp32_resolution():
     for delta in (1e-8, 1e-5, 1e-2):
         e = eff((32,) * 4, [[1, 10, 10, 10, 1]] * 2, delta)
         assert e == max(delta, base)
+
+
+def request(scheme, ns, basis_ranks, w_ranks):
+    """A serving request descriptor (tt_request) over descriptor-only vectors."""
+    d = len(ns)
+    basis = (tt._Vec * max(len(basis_ranks), 1))()
+    for v, ranks in zip(basis, basis_ranks):
+        v.d, v.dtype = d, 0
+        for k in range(d):
+            v.n[k] = ns[k]
+        for k in range(d + 1):
+            v.r[k] = ranks[k]
+        v.data = 4096
+        v.capacity = sum(ranks[k] * ns[k] * ranks[k + 1] for k in range(d))
+    w, keep = descriptors(ns, w_ranks)
+    req = tt._Request()
+    req.scheme = tt.SCHEMES[scheme]
+    req.b = len(basis_ranks)
+    req.basis = C.cast(basis, C.POINTER(tt._Vec))
+    req.w = w
+    req.delta = 0.0
+    return req, (basis, w, keep)
+
+
+@pytest.mark.parametrize("scheme", ["cgs", "mgs", "cgs2", "mgs2"])
+@pytest.mark.parametrize("ns,basis_ranks,w_ranks", [
+    ((5, 6, 6, 5), [[1, 2, 2, 2, 1]] * 3, [[1, 2, 3, 2, 1], [1, 1, 2, 1, 1]]),   # no cap binds in the middle
+    ((3, 4, 3), [[1, 2, 2, 1]] * 4, [[1, 3, 3, 1]]),                               # caps bind everywhere
+    ((4, 4, 4, 4, 4), [[1, 3, 4, 4, 3, 1], [1, 1, 2, 2, 1, 1]], [[1, 2, 2, 2, 2, 1]]),
+    ((9,), [[1, 1]] * 2, [[1, 1]]),
+])
+def test_request_out_capacity_holds_the_oracle_step(scheme, ns, basis_ranks, w_ranks):
+    """The q output a serving request is sized for (tt_request_out_capacity) holds the oracle's
+    Gram-Schmidt step (Algorithms 1-4 through gs_step) at delta = 0 against a basis of the
+    request's ranks; for the one-pass schemes it is exactly that size where generic data reach
+    every bound of rank(w) + sum_j rank(q_j)."""
+    g = synth.rng(62000 + len(ns) + sum(map(sum, basis_ranks)))
+    Q = []
+    for r in basis_ranks:   # a basis of the given ranks, each vector normalised
+        c = synth.random_tt(g, list(ns), r)
+        c[-1] = c[-1] / oracle.tt_norm(c)
+        Q.append(c)
+    w = [(float(g.standard_normal()), synth.random_tt(g, list(ns), r)) for r in w_ranks]
+    q, col = oracle.gs_step(scheme, Q, w, 0.0)
+    size = sum(c.size for c in q)
+    req, keep = request(scheme, ns, basis_ranks, w_ranks)
+    L = tt._load()
+    L.tt_request_out_capacity.argtypes = [C.POINTER(tt._Request)]
+    L.tt_request_out_capacity.restype = C.c_int64
+    cap = L.tt_request_out_capacity(C.byref(req))
+    assert cap >= size, (cap, size)
+    if scheme in ("cgs", "mgs"):
+        d = len(ns)
+        R = [1] + [sum(r[k] for r in w_ranks) + sum(r[k] for r in basis_ranks) for k in range(1, d)] + [1]
+        b = [min(R[k], math.prod(ns[:k]), math.prod(ns[k:])) for k in range(d + 1)]
+        if all(b[k - 1] * ns[k - 1] >= b[k] and ns[k] * b[k + 1] >= b[k] for k in range(1, d)):
+            assert cap == size, (cap, size)
