@@ -186,3 +186,20 @@ def test_gs_step_reproduces_the_full_scheme(scheme):
         q, col = oracle.gs_step(scheme, res.Q[:i], X[i], 1e-6)
         assert np.array_equal(col, res.R[: i + 1, i])
         assert all(np.array_equal(a, b) for a, b in zip(q, res.Q[i]))
+
+
+@pytest.mark.parametrize("kappa_gram", [1e10, 1e14])
+def test_gram_factors_below_the_remark_regime(kappa_gram):
+    """Section 3.2's remark puts the failure of the Cholesky factorisation of G at kappa(A)
+    above about u^{-1/2} (kappa(G) = kappa(A)^2 near 1/u).  Below it the oracle's breakdown
+    rule (a pivot at the rounding level, L_jj^2 <= m u G_jj) must not fire: at kappa(G) = 1e10
+    and 1e14 (kappa(A) = 1e5 and 1e7, under u^{-1/2} = 6.7e7) TT-Gram completes and R^T R
+    reproduces the dense Gram matrix of the vectorised inputs.  A rule at the square root of
+    the round-off, sqrt(u) G_jj, would already stop the first case."""
+    X, C, M = conditioned_inputs(53, 6, 3, 4, 2, kappa_gram)
+    res = oracle.gram(X, 1e-14)
+    A = as_dense_columns(X)
+    G = A.T @ A
+    assert np.all(np.diag(res.R) > 0) and np.allclose(np.tril(res.R, -1), 0)
+    assert np.linalg.norm(res.R.T @ res.R - G) <= 1e-12 * np.linalg.norm(G)
+    assert np.linalg.cond(G) == pytest.approx(kappa_gram, rel=1e-2)
