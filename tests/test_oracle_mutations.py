@@ -2,7 +2,8 @@
 
 Each mutant is a plausible slip (a transposed operand, a misplaced
 coefficient, a wrong threshold, a strict instead of non-strict test, the
-cancelling Householder sign, the wrong canonical index order); the same
+cancelling Householder sign, the wrong canonical index order, a Gram breakdown
+rule at the square root of the round-off); the same
 independent reference used by the pins has to reject it.  The oracle's files
 are never modified: a mutant is a separate function, swapped in for one test
 at most.
@@ -13,6 +14,7 @@ import numpy as np
 
 import oracle
 from oracle import tt_full
+from inputs import conditioned_inputs
 from paper_2211_08770_amd import synth
 
 
@@ -203,3 +205,23 @@ def test_power_sequence_pin_catches_the_missing_minus_sign():
     bad = _krylov_without_minus([n], m)
     assert all(np.allclose(tt_full(a), r, atol=1e-12) for a, r in zip(good, ref))
     assert not all(np.allclose(tt_full(a), r, atol=1e-6) for a, r in zip(bad, ref))
+
+
+def _gram_sqrt_u_rule(A):
+    """The factorisation step of TT-Gram with the breakdown rule at sqrt(u) G_jj."""
+    G = oracle.gram_of([oracle.tt_sum(a) for a in A])
+    L = np.linalg.cholesky(G)
+    u = np.finfo(np.float64).eps / 2
+    if np.any(np.diag(L) ** 2 <= math.sqrt(u) * np.diag(G)):          # slip: sqrt(u) for m u
+        raise oracle.GramBreakdown("numerically singular")
+    return L.T
+
+
+def test_remark_regime_pin_catches_a_breakdown_rule_at_sqrt_u():
+    X, C, M = conditioned_inputs(53, 6, 3, 4, 2, 1e10)     # kappa(A) = 1e5, well below u^{-1/2}
+    oracle.gram(X, 1e-14)                                  # the oracle factors it
+    try:
+        _gram_sqrt_u_rule(X)
+    except oracle.GramBreakdown:
+        return
+    raise AssertionError("the sqrt(u) rule did not fire below the remark's regime")
