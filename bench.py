@@ -846,9 +846,9 @@ def main():
         progress("batched_uneven")
         line["mgs_m20_order4"] = run_mgs_m20_order4(tt, torch)
         progress("mgs_m20_order4")
-        line["cgs2_gram_m50_order6_guarded"] = run_cgs2_gram_m50_order6(tt, torch, **({"runs": [(a, b) for a in ("gram", "cgs2")
-                                                                         for b in (1e-3, 1e-5, 1e-7)]}
-                                                              if args.order6_n64_all else {}))
+        all_runs = {"runs": [(a, b) for a in ("gram", "cgs2") for b in (1e-3, 1e-5, 1e-7)]}
+        line["cgs2_gram_m50_order6_guarded"] = run_cgs2_gram_m50_order6(
+            tt, torch, **(all_runs if args.order6_n64_all else {}))
         progress("cgs2_gram_m50_order6_guarded")
         line["serving"] = run_serving(torch, nreq=args.serving_requests, keep_sample=0 if args.no_cpu else 2)
         sample = line["serving"].pop("_sample")
