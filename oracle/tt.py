@@ -2,7 +2,8 @@
 
 This module is the reference that the HIP path is checked against. Only the
 test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
-``bench.py`` may import it; the product path never does.
+``bench.py`` (its CPU part: host timings of this oracle and checks of GPU
+results against it) may import it; the product path never does.
 
 Everything is plain NumPy in float64, written to be read against the paper
 (Coulaud, Giraud, Iannacito, "On some orthogonalization schemes in Tensor
