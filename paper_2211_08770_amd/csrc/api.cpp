@@ -441,6 +441,7 @@ tt_status dot_pairs_idx(tt_ctx* c, int npairs, const tt_sum* xs, const tt_sum* y
   }
   const int32_t* dseg = upload(c, seg);
   const int32_t* didx = out_idx ? upload(c, *out_idx) : nullptr;
+  if ((!seg.empty() && !dseg) || (out_idx && !out_idx->empty() && !didx)) return fail(c, TT_ENOMEM, "dot reduce tasks");
   hipError_t e = launch_segsum(slots, dseg, didx, npairs, out_dev, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "dot reduce");
   return TT_OK;

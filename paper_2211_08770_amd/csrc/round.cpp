@@ -1057,6 +1057,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       }
       if (g.empty()) continue;
       const CopySeg* dg = upload(c, g);
+      if (!dg) return fail(c, TT_ENOMEM, "task upload");
       if ((e = launch_copy_segs(dtype, dg, (int)g.size(), s)) != hipSuccess) return hip_fail(c, e, "copy");
     }
     std::vector<SumsqTask> nt;
@@ -1092,6 +1093,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
     }
     if (!segs.empty()) {
       const CopySeg* dg = upload(c, segs);
+      if (!dg) return fail(c, TT_ENOMEM, "task upload");
       if ((e = launch_copy_segs(dtype, dg, (int)segs.size(), s)) != hipSuccess) return hip_fail(c, e, "gather");
     }
   }
@@ -1402,6 +1404,7 @@ tt_status round_jobs(tt_ctx* c, std::vector<RJob>& jobs, const RoundMode& mode) 
       sv.push_back(t);
     }
     const SvdTask* dsv = upload(c, sv);
+    if (!sv.empty() && !dsv) return fail(c, TT_ENOMEM, "task upload");
     double sfl = 0.0, sby = 0.0;
     for (const SvdTask& t : sv) {
       const double mn = std::min(t.kr, t.ncol), mx = std::max(t.kr, t.ncol);
