@@ -158,6 +158,20 @@ def test_round_is_deterministic():
     assert a.r == b.r and torch.equal(a.data, b.data)
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_round_wide_paths_are_deterministic(dtype):
+    # the 1024 x 500 and 16000 x 500 unfoldings of 50 rank-10 components take column-blocked
+    # QR and the 500-row R factors the block Jacobi SVD (its sweep counters are atomics, its
+    # pairs run in any order): every call gives the same bits all the same
+    tt = need_gpu()
+    terms = rand_terms(322, [32, 32, 32, 32], [[1, 10, 10, 10, 1]] * 50,
+                       scales=[2.0 ** -(j % 7) for j in range(50)])
+    x = dev_sum(terms, dtype)
+    a = tt.round(x, 1e-6)
+    b = tt.round(x, 1e-6)
+    assert a.r == b.r and a.r[2] > 224 and torch.equal(a.data, b.data)
+
+
 def test_round_maximum_order():
     # d = 64, the largest order the library takes: 63 dependent steps in each sweep
     terms = rand_terms(320, [2] * 64, [[1] + [2] * 63 + [1], [1] + [1] * 63 + [1]], coefs=[1.0, -0.5])
