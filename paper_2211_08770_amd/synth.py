@@ -17,14 +17,18 @@ TT-ranks, number of vectors m, rounding accuracy delta):
     prescribed eigenvalue set (Davies-Higham, via SciPy);
   * ``mixing_coefficients`` - the lower-triangular c_kj that give the x_k a
     prescribed Gram matrix, from the Gram matrix of the t_j (computed by the
-    caller) and a correlation matrix: small dense linear algebra only.
+    caller) and a correlation matrix: small dense linear algebra only;
+  * ``serving_solver``, ``serving_vector``, ``serving_request`` - simulated
+    TT-GMRES solvers (d in [5, 8], n in {32, 64, 128}, rank in [4, 32], initial
+    basis of 10-39 vectors) and the new vectors their requests orthogonalize.
 """
 from __future__ import annotations
 
 import numpy as np
 
 __all__ = ["rng", "random_tt", "sum_of_graded_terms", "conditioned_terms",
-           "uneven_jobs", "correlation_with_spectrum", "geometric_spectrum"]
+           "uneven_jobs", "correlation_with_spectrum", "geometric_spectrum", "mixing_coefficients",
+           "serving_solver", "serving_vector", "serving_request"]
 
 
 def rng(seed: int) -> np.random.Generator:
