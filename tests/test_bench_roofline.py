@@ -30,17 +30,22 @@ def bench():
         sys.path.remove(ROOT)
 
 
-def test_recorded_traffic_is_the_calibrated_counter_sum(bench):
-    text = open(os.path.join(ROOT, "profiles", "qr_factor_leaf_graded_sum_r200_traffic.txt")).read()
-    fetch_kib, write_kib = map(float, re.search(r"FETCH_SIZE ([\d.]+) KiB, WRITE_SIZE ([\d.]+) KiB", text).groups())
-    sf, sw = map(float, re.search(r"FETCH_SIZE is scaled by (\d+\.\d+) and WRITE_SIZE by (\d+\.\d+)", text).groups())
+@pytest.mark.parametrize("kernel,workload", [("qr_factor_leaf", "graded_sum_r200"), ("qr_apply", "batched_uneven_256")])
+def test_recorded_traffic_is_the_calibrated_counter_sum(bench, kernel, workload):
+    text = open(os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")).read()
+    fetch_kib, write_kib = map(float, re.search(r"FETCH_SIZE ([\d.]+) KiB,? .*?WRITE_SIZE ([\d.]+) KiB", text).groups())
+    sf, sw = map(float, re.search(r"FETCH_SIZE (?:is )?scaled by (\d+\.\d+),? (?:and )?WRITE_SIZE by (\d+\.\d+)",
+                                  text).groups())
     stored = int(re.search(r"traffic_bytes_per_launch: (\d+)", text).group(1))
     # the averages are printed to 0.1 KiB: the product agrees to that rounding
     assert abs(1024 * (fetch_kib * sf + write_kib * sw) - stored) <= 1024 * 0.05 * (sf + sw) + 1
     src = open(os.path.join(ROOT, "paper_2211_08770_amd", "csrc", "qr.hip"), "rb").read()
     current = hashlib.sha256(src).hexdigest()[:16] in text
-    assert bench.recorded_traffic("qr_factor_leaf") == (stored if current else None)
-    assert bench.recorded_traffic("qr_apply") is None            # no summary for that kind on this workload
+    assert bench.recorded_traffic(kernel, workload) == (stored if current else None)
+
+
+def test_no_traffic_without_a_summary(bench):
+    assert bench.recorded_traffic("qr_apply") is None            # no summary for that kind on the headline
 
 
 def test_recorded_traffic_is_dropped_when_the_qr_source_changes(bench, tmp_path, monkeypatch):
