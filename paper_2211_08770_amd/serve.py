@@ -64,8 +64,10 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
               max_inflight=64, engine=None, keep_sample=0):
     """Replay nreq Poisson arrivals at `qps` (requests/s) over the solvers.
 
-    Returns a dict with p50/p99 latency (ms), throughput (requests/s),
-    admitted/rejected counts, the high-water mark of the device memory the
+    Returns a dict with p50/p99 latency (ms) and throughput (requests/s) of
+    the requests served, the counts of requests rejected at admission and of
+    requests whose step failed (breakdown, capacity: reported by the engine,
+    neither served nor timed), the high-water mark of the device memory the
     loop holds (bases plus in-flight requests) and the engine steps taken.
     With keep_sample > 0, "sample" holds host copies (float64) of the basis,
     w, q and the R column of that many requests that completed, for checks.
@@ -79,14 +81,14 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
         s = solvers[owners[i]]
         w = synth.serving_request(g, s.spec, min(len(s.basis), s.spec["b0"]))
         reqs.append((arrivals[i], owners[i], w))
-    lat, rejected, steps = [], 0, 0
+    lat, rejected, failed, steps = [], 0, 0, 0
     inflight = {}                      # engine id -> (request index, solver, footprint)
     held = sum(s.nbytes() for s in solvers)
     high = held
     nxt = 0
     done = 0
     t0 = time.perf_counter()
-    while done + rejected < nreq:
+    while done + failed + rejected < nreq:
         now = time.perf_counter() - t0
         while nxt < nreq and reqs[nxt][0] <= now:      # arrivals go to their solver's queue
             solvers[reqs[nxt][1]].queue.append(nxt)
@@ -103,6 +105,11 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
                 rejected += 1
                 continue
             if held + fp > budget_bytes:
+                # memory is freed only by requests that finish: with none in flight this one can
+                # never be admitted, so it is rejected rather than waited for
+                if not inflight:
+                    s.queue.popleft()
+                    rejected += 1
                 continue
             s.queue.popleft()
             rid = eng.submit(scheme, s.basis, w, delta, basis_gram=s.gram)
@@ -119,14 +126,16 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
                 i, s, fp, _ = inflight.pop(rid)
                 held -= fp
                 s.busy = False
+                if status != "TT_OK":
+                    failed += 1
+                    continue
                 done += 1
                 lat.append(tnow - reqs[i][0])
-                if status == "TT_OK":
-                    if len(kept) < keep_sample:
-                        kept.append((list(s.basis), inflight_w[rid], q, r))
-                    before = s.nbytes()
-                    s.append(q, grow)
-                    held += s.nbytes() - before
+                if len(kept) < keep_sample:
+                    kept.append((list(s.basis), inflight_w[rid], q, r))
+                before = s.nbytes()
+                s.append(q, grow)
+                held += s.nbytes() - before
         elif nxt < nreq:
             time.sleep(max(0.0, min(reqs[nxt][0] - (time.perf_counter() - t0), 0.01)))
     wall = time.perf_counter() - t0
@@ -134,6 +143,7 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
     host = lambda t: [c.astype(np.float64) for c in t.numpy_cores()]
     sample = [([host(b) for b in basis], host(w), host(q), np.array(r)) for basis, w, q, r in kept]
     return {"sample": sample, "qps_offered": qps, "requests": nreq, "completed": done, "rejected": rejected,
+            "failed": failed,
             "p50_ms": float(np.percentile(lat_ms, 50)) if len(lat_ms) else None,
             "p99_ms": float(np.percentile(lat_ms, 99)) if len(lat_ms) else None,
             "throughput_rps": done / wall, "wall_s": wall, "engine_steps": steps,

@@ -1,0 +1,112 @@
+"""The serving loop's scheduling and bookkeeping (paper_2211_08770_amd/serve.py), on the CPU.
+
+run_trace drives an engine through footprint / submit / step; here a stand-in engine with the
+same interface finishes each request after a few steps (q is the normalised new vector), so
+the loop's own logic is checked without a GPU: every request is served, rejected at admission
+or reported failed, and counted once; a solver never has two requests in flight; the memory
+the loop holds never exceeds its budget and returns to the bases alone at the end; failed
+steps are neither timed nor appended to a basis; requests whose footprint exceeds the whole
+budget, or the room the bases leave while nothing is in flight (memory that no finishing
+request will free), are rejected, so the loop always ends.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2211_08770_amd import serve, tt
+
+
+class StandInEngine:
+    """tt.Engine's interface: a request completes `stages` steps after its submission."""
+
+    def __init__(self, stages=3, fail_every=0, fp_extra=0):
+        self.stages, self.fail_every, self.fp_extra = stages, fail_every, fp_extra
+        self.live = {}
+        self.next_id = 0
+        self.submitted = 0
+        self.failed_ids = set()
+        self.busy_bases = set()
+
+    def footprint(self, scheme, basis, w):
+        return 2 * w.data.numel() * w.data.element_size() + self.fp_extra
+
+    def submit(self, scheme, basis, w, delta, basis_gram=None):
+        assert id(basis) not in self.busy_bases, "two requests of one solver in flight"
+        assert basis_gram is not None and basis_gram.shape == (len(basis), len(basis))
+        self.busy_bases.add(id(basis))
+        rid = self.next_id
+        self.next_id += 1
+        self.submitted += 1
+        fail = self.fail_every and self.submitted % self.fail_every == 0
+        if fail:
+            self.failed_ids.add(rid)
+        self.live[rid] = [self.stages, basis, w, fail]
+        return rid
+
+    def step(self):
+        out = {}
+        for rid in list(self.live):
+            st = self.live[rid]
+            st[0] -= 1
+            if st[0] > 0:
+                continue
+            _, basis, w, fail = self.live.pop(rid)
+            self.busy_bases.discard(id(basis))
+            b = len(basis)
+            if fail:
+                out[rid] = ("TT_EBREAKDOWN", None, np.zeros(b + 1), np.zeros(b))
+            else:
+                q = tt.TT(w.data / torch.linalg.vector_norm(w.data), w.n, w.r)
+                out[rid] = ("TT_OK", q, np.ones(b + 1), np.zeros(b))
+        return out
+
+
+def solvers(n=6):
+    # small solvers (8 x 2-3 first cores hold a basis of up to 12 orthonormal vectors)
+    return serve.make_solvers(n, seed=40000, device="cpu", dtype=torch.float64, n_choices=(8,), r_range=(2, 3),
+                              d_range=(3, 4), b0_range=(3, 6), bmax=12)
+
+
+@pytest.mark.parametrize("fail_every", [0, 4])
+def test_every_request_is_counted_once(fail_every):
+    sv, g = solvers()
+    base_bytes = sum(s.nbytes() for s in sv)
+    eng = StandInEngine(stages=3, fail_every=fail_every)
+    rep = serve.run_trace(sv, g, qps=4000.0, nreq=120, engine=eng)
+    assert rep["completed"] + rep["failed"] + rep["rejected"] == 120
+    assert rep["failed"] == len(eng.failed_ids) == (120 // fail_every if fail_every else 0)
+    assert rep["rejected"] == 0 and not eng.live
+    assert rep["throughput_rps"] == pytest.approx(rep["completed"] / rep["wall_s"])
+    assert rep["hbm_high_water_bytes"] >= base_bytes
+    assert rep["hbm_high_water_bytes"] <= 8 << 30
+    # bases grew by exactly the served results (restarts at bmax drop back to the initial basis)
+    assert all(len(s.basis) <= s.spec["bmax"] for s in sv)
+    assert sum(len(s.basis) - s.spec["b0"] for s in sv) <= rep["completed"]
+
+
+def test_budget_bounds_the_memory_held_and_rejects_what_never_fits():
+    sv, g = solvers()
+    base_bytes = sum(s.nbytes() for s in sv)
+    eng = StandInEngine(stages=2)
+    w_bytes = 2 * 8 * 8 * 3 * 3        # a rough footprint unit of these small requests
+    budget = base_bytes + 3 * w_bytes
+    rep = serve.run_trace(sv, g, qps=4000.0, nreq=60, engine=eng, budget_bytes=budget)
+    assert rep["completed"] + rep["failed"] + rep["rejected"] == 60
+    assert rep["hbm_high_water_bytes"] <= budget
+    # the first requests fit; once the grown bases leave too little room even with nothing in
+    # flight, the rest are rejected instead of waited for (the loop ends)
+    assert rep["completed"] > 0 and rep["rejected"] > 0
+    sv2, g2 = solvers()
+    huge = StandInEngine(stages=2, fp_extra=16 << 30)   # no request fits the 8 GiB budget at all
+    rep2 = serve.run_trace(sv2, g2, qps=4000.0, nreq=20, engine=huge)
+    assert rep2["rejected"] == 20 and rep2["completed"] == 0 and rep2["p50_ms"] is None
+
+
+def test_kept_samples_are_served_requests():
+    sv, g = solvers()
+    eng = StandInEngine(stages=1, fail_every=2)
+    rep = serve.run_trace(sv, g, qps=4000.0, nreq=30, engine=eng, keep_sample=5)
+    assert len(rep["sample"]) == 5
+    for basis, w, q, r in rep["sample"]:
+        assert abs(np.sqrt(sum(float(np.sum(c * c)) for c in q)) - 1.0) < 1e-12 or len(q) > 1
+        assert r.shape == (len(basis) + 1,)
