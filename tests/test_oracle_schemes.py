@@ -203,3 +203,32 @@ def test_gram_factors_below_the_remark_regime(kappa_gram):
     assert np.all(np.diag(res.R) > 0) and np.allclose(np.tril(res.R, -1), 0)
     assert np.linalg.norm(res.R.T @ res.R - G) <= 1e-12 * np.linalg.norm(G)
     assert np.linalg.cond(G) == pytest.approx(kappa_gram, rel=1e-2)
+
+
+@pytest.mark.parametrize("scheme", oracle.SCHEMES)
+def test_dense_schemes_equal_lapack_qr_on_well_conditioned_columns(scheme):
+    """The dense matrix schemes that pin the TT oracle are pinned themselves to LAPACK's
+    Householder QR (numpy.linalg.qr with the signs chosen to make the diagonal of R positive,
+    the convention every Gram-Schmidt form and the Cholesky factor share): on columns of
+    condition number about 10, Q and R agree to rounding for every scheme."""
+    g = synth.rng(54)
+    A = g.standard_normal((40, 7)) @ np.diag([1.0, 2.0, 0.5, 3.0, 1.0, 0.8, 1.5])
+    assert np.linalg.cond(A) < 30
+    Q, R = dense.dense_orthogonalize(scheme, A)
+    Ql, Rl = np.linalg.qr(A)
+    s = np.sign(np.diag(Rl))
+    Ql, Rl = Ql * s, s[:, None] * Rl
+    assert np.allclose(R, Rl, rtol=0, atol=1e-12 * np.linalg.norm(A))
+    assert np.allclose(Q, Ql, rtol=0, atol=1e-12)
+
+
+def test_dense_loo_is_the_largest_eigenvalue_magnitude():
+    """dloo(Q)[k-1] = ||I - Q_k^T Q_k||_2 (Section 3.4): on a non-orthonormal Q it equals the
+    largest absolute eigenvalue of the symmetric I - Q_k^T Q_k (LAPACK's symmetric eigensolver,
+    a route independent of the SVD behind the 2-norm)."""
+    g = synth.rng(55)
+    Q = g.standard_normal((30, 6)) / math.sqrt(30)
+    got = dense.dloo(Q)
+    for k in range(1, 7):
+        E = np.eye(k) - Q[:, :k].T @ Q[:, :k]
+        assert got[k - 1] == pytest.approx(np.abs(np.linalg.eigvalsh(E)).max(), rel=1e-12)
