@@ -139,6 +139,20 @@ def test_round_d2_is_eckart_young(delta):
     assert np.allclose(tt_full(xr), best, rtol=0, atol=1e-13 * nx)
 
 
+@pytest.mark.parametrize("cap", [1, 2, 4])
+def test_round_d2_rank_cap_is_the_best_rank_k_approximation(cap):
+    # d = 2 with delta = 0 and a rank cap k: the truncated SVD at rank k (Eckart-Young), the
+    # rank-capped rounding the paper applies to its Krylov inputs with k = 1 (Section 4)
+    g = synth.rng(13)
+    X = g.standard_normal((9, 4)) @ g.standard_normal((4, 8)) + 1e-3 * g.standard_normal((9, 8))
+    U, sig, Vt = np.linalg.svd(X, full_matrices=False)
+    x = [X.reshape(1, 9, 8), np.eye(8).reshape(8, 8, 1)]
+    xr = tt_round(x, 0.0, max_rank=cap)
+    best = (U[:, :cap] * sig[:cap]) @ Vt[:cap]
+    assert tt_ranks(xr) == [1, cap, 1]
+    assert np.allclose(tt_full(xr), best, rtol=0, atol=1e-13 * np.linalg.norm(X))
+
+
 def _rand_sum(seed, ns, comp_rank, ncomp, decay=0.3):
     terms = []
     d = len(ns)
