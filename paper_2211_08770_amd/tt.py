@@ -594,7 +594,8 @@ def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: b
     """Q, R (and the LOO curve) of the TT vectors / lazy sums A (Algorithms 1-8).
 
     With partial_on_guard, a stop at the rank guard returns the completed
-    prefix (Q[:m_reached], R, None, stats with "guard": True) instead of raising.
+    prefix (Q[:m_reached], R with its columns from m_reached on set to zero, None,
+    stats with "guard": True) instead of raising.
     """
     m = len(A)
     hs = [_SumHolder(a) for a in A]
@@ -640,6 +641,7 @@ def orthogonalize(scheme: str, A, delta: float, rank_guard: int = 0, with_loo: b
             k = stats.m_reached
             Qp = [_finish_out(Q[i], vq[i]) for i in range(k)]
             Rm = np.array(R[:], dtype=np.float64).reshape(m, m).T.copy()
+            Rm[:, k:] = 0.0   # only the columns of the completed vectors are defined
             return Qp, Rm, None, {"rounds": stats.rounds, "m_reached": k, "max_pre_rank": stats.max_pre_rank,
                                   "max_post_rank": stats.max_post_rank, "guard": True}
     else:
