@@ -1,7 +1,11 @@
 // Small kernels of the TT hot path: TT inner products (batched over
-// component pairs), norms and scaling, block copies of TT sums, the FP64
-// Cholesky + triangular inverse of the Gram scheme, and the matrices whose
-// 2-norms give the loss of orthogonality.
+// component pairs; the contraction itself is in dotk.h), norms and scaling,
+// copies of TT-sum blocks (segments, row blocks with dtype conversion) and the
+// materialised axpy, the in-place compaction of bound-planned result cores,
+// the FP64 Cholesky + triangular inverse of the Gram scheme, the MGS and
+// serving projection coefficients, the matrices whose 2-norms give the loss of
+// orthogonality, the TT-Householder helpers (canonical basis, R column,
+// reflection and q coefficients) and the Laplacian TT-matrix core product.
 #include <algorithm>
 
 #include "common.h"
