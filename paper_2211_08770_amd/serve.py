@@ -65,7 +65,9 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
     """Replay nreq Poisson arrivals at `qps` (requests/s) over the solvers.
 
     Returns a dict with p50/p99 latency (ms) and throughput (requests/s) of
-    the requests served, the counts of requests rejected at admission and of
+    the requests served, the counts of requests rejected at admission (a
+    footprint above the budget, or, once every request has arrived and none is
+    in flight, above the room the bases leave) and of
     requests whose step failed (breakdown, capacity: reported by the engine,
     neither served nor timed), the high-water mark of the device memory the
     loop holds (bases plus in-flight requests) and the engine steps taken.
@@ -105,11 +107,6 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
                 rejected += 1
                 continue
             if held + fp > budget_bytes:
-                # memory is freed only by requests that finish: with none in flight this one can
-                # never be admitted, so it is rejected rather than waited for
-                if not inflight:
-                    s.queue.popleft()
-                    rejected += 1
                 continue
             s.queue.popleft()
             rid = eng.submit(scheme, s.basis, w, delta, basis_gram=s.gram)
@@ -138,6 +135,14 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
                 held += s.nbytes() - before
         elif nxt < nreq:
             time.sleep(max(0.0, min(reqs[nxt][0] - (time.perf_counter() - t0), 0.01)))
+        else:
+            # every request has arrived and none is in flight, so no finishing request will free
+            # memory: the head of each queue did not fit beside the bases and never will.  Those
+            # are rejected (the requests behind them are tried in the next pass).
+            for s in solvers:
+                if s.queue:
+                    s.queue.popleft()
+                    rejected += 1
     wall = time.perf_counter() - t0
     lat_ms = np.array(lat) * 1e3
     host = lambda t: [c.astype(np.float64) for c in t.numpy_cores()]

@@ -6,8 +6,9 @@ the loop's own logic is checked without a GPU: every request is served, rejected
 or reported failed, and counted once; a solver never has two requests in flight; the memory
 the loop holds never exceeds its budget and returns to the bases alone at the end; failed
 steps are neither timed nor appended to a basis; requests whose footprint exceeds the whole
-budget, or the room the bases leave while nothing is in flight (memory that no finishing
-request will free), are rejected, so the loop always ends.
+budget are rejected, and so are those that do not fit beside the bases once every request has
+arrived and none is in flight (no finishing request will free memory then), so the loop always
+ends.
 """
 import numpy as np
 import pytest
@@ -93,8 +94,8 @@ def test_budget_bounds_the_memory_held_and_rejects_what_never_fits():
     rep = serve.run_trace(sv, g, qps=4000.0, nreq=60, engine=eng, budget_bytes=budget)
     assert rep["completed"] + rep["failed"] + rep["rejected"] == 60
     assert rep["hbm_high_water_bytes"] <= budget
-    # the first requests fit; once the grown bases leave too little room even with nothing in
-    # flight, the rest are rejected instead of waited for (the loop ends)
+    # the first requests fit; once the grown bases leave too little room, the rest wait until
+    # every request has arrived and none is in flight, and are then rejected (the loop ends)
     assert rep["completed"] > 0 and rep["rejected"] > 0
     sv2, g2 = solvers()
     huge = StandInEngine(stages=2, fp_extra=16 << 30)   # no request fits the 8 GiB budget at all
