@@ -96,6 +96,7 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
             solvers[reqs[nxt][1]].queue.append(nxt)
             nxt += 1
         # admission: idle solvers with a queued request, while slots and memory allow
+        blocked = []                                   # solvers whose queue head did not fit
         for s in solvers:
             if s.busy or not s.queue or len(inflight) >= max_inflight:
                 continue
@@ -107,6 +108,7 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
                 rejected += 1
                 continue
             if held + fp > budget_bytes:
+                blocked.append(s)
                 continue
             s.queue.popleft()
             rid = eng.submit(scheme, s.basis, w, delta, basis_gram=s.gram)
@@ -137,12 +139,11 @@ def run_trace(solvers, g, qps=200.0, nreq=200, delta=1e-6, scheme="mgs2", budget
             time.sleep(max(0.0, min(reqs[nxt][0] - (time.perf_counter() - t0), 0.01)))
         else:
             # every request has arrived and none is in flight, so no finishing request will free
-            # memory: the head of each queue did not fit beside the bases and never will.  Those
-            # are rejected (the requests behind them are tried in the next pass).
-            for s in solvers:
-                if s.queue:
-                    s.queue.popleft()
-                    rejected += 1
+            # memory: a queue head that did not fit beside the bases in this pass never will.
+            # Those are rejected (the requests behind them are tried in the next pass).
+            for s in blocked:
+                s.queue.popleft()
+                rejected += 1
     wall = time.perf_counter() - t0
     lat_ms = np.array(lat) * 1e3
     host = lambda t: [c.astype(np.float64) for c in t.numpy_cores()]

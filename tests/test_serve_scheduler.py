@@ -111,3 +111,31 @@ def test_kept_samples_are_served_requests():
     for basis, w, q, r in rep["sample"]:
         assert abs(np.sqrt(sum(float(np.sum(c * c)) for c in q)) - 1.0) < 1e-12 or len(q) > 1
         assert r.shape == (len(basis) + 1,)
+
+
+
+class SomeTooBigEngine(StandInEngine):
+    """A request whose new vector starts with a positive entry has a footprint above any budget;
+    the others are small.  The decision depends on the request only, however often it is asked."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.too_big = set()
+
+    def footprint(self, scheme, basis, w):
+        first = float(w.data[0])
+        if first > 0:
+            self.too_big.add(first)
+            return 16 << 30
+        return super().footprint(scheme, basis, w)
+
+
+def test_a_request_behind_a_rejected_one_is_checked_before_it_is_rejected():
+    # all requests arrive at once; the too-big ones are rejected outright, and each request queued
+    # behind one is checked in a later pass and served (the budget is roomy), never rejected unchecked
+    sv, g = solvers(2)
+    eng = SomeTooBigEngine(stages=1)
+    rep = serve.run_trace(sv, g, qps=1e6, nreq=40, engine=eng)
+    assert 0 < len(eng.too_big) < 40
+    assert rep["rejected"] == len(eng.too_big)
+    assert rep["completed"] == 40 - len(eng.too_big) and rep["failed"] == 0
